@@ -1,0 +1,291 @@
+"""FFT-route estimators for the MABS and the 3D bispectrum, in float64.
+
+Oracle (test infrastructure only; see the package docstring).
+
+MABS (Gill & Bharadwaj 2025, Sec. 3.2):
+  * D(l_m, nu, theta): inverse FT of W_g V_g restricted to ring a_m (Eq. iFT);
+  * I(l_m, nu, theta): inverse FT of W_g N_g restricted to ring a_m (Eq. iFT_I),
+    where W_g N_g is the unit-weight sampling indicator [N_g > 0];
+  * B_A = (1/A) sum_theta D1 D2 D3 / sum_theta I1 I2 I3 (Eq. estimator_t).
+  The grid-unit normalisation used here: with NumPy's ifft (1/N_pix),
+  sum_theta D1 D2 D3 = N_pix^-2 sum over closed triangles of X1 X2 X3 and
+  sum_theta I1 I2 I3 = N_pix^-2 * (number of closed triangles), so
+  N_tri = N_pix^2 S_I and B = norm * N_pix * S_D / N_tri is the average of
+  X1 X2 X3 / N_pix over closed grid triangles (Sec. 3.2, the paragraph after
+  Eq. estimator_t).  `norm` stands for 1/A.
+  Ergodic collapse to (dnu1, dnu2) = (nu1 - nu3, nu2 - nu3) averages the
+  per-triplet estimates (Sec. 3.2, the paragraph before Eq. dft).
+
+3D bispectrum: the delay transform along frequency is applied to the weighted
+cube, the 3D grid is split into |k| shells, each shell is inverse-FFT'd to a
+real field and the same triple-product estimator is formed over voxels.  This
+regroups the paper's MABS -> Eq. (dft) route by 3D |k| shells (the identity is
+checked in tests/test_oracle_pins.py).  Flagged channels enter through
+rho3 = mean_nu w(nu)^3: N_eff = T3D * rho3 and B = norm * N_vox * S_D / N_eff.
+
+Weights (Sec. 3.2, Eq. vg): W_g = 1/N_g on filled cells, 0 on empty ones.
+Separable form: uv occupancy m(U) times channel weight w(nu) in {0, 1}.
+Non-Hermitian v = 0 (and Nyquist) columns are symmetrised as
+(X(u) + conj X(-u)) / 2 before the inverse transform.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, Iterable, Optional, Tuple
+
+import numpy as np
+
+from .bins import Bins, RING_U, SHELL_K
+
+COUNT_TOL = 1e-3   # largest |x - round(x)| accepted before rounding a count
+
+
+@dataclass
+class Weights:
+    """Exactly one of (ng) or (uv_mask, chan_w) is used; all None means unit weights."""
+    ng: Optional[np.ndarray] = None        # [nc][n][nh] cell counts N_g
+    uv_mask: Optional[np.ndarray] = None   # [n][nh] occupancy 0/1
+    chan_w: Optional[np.ndarray] = None    # [nc] channel weight 0/1
+
+    def separable(self) -> bool:
+        return self.ng is None
+
+    def data_weight(self, nc: int, n: int) -> np.ndarray:
+        """W_g[nu][u][v]."""
+        nh = n // 2 + 1
+        if self.ng is not None:
+            ng = np.asarray(self.ng, dtype=np.float64)
+            with np.errstate(divide="ignore"):
+                return np.where(ng > 0, 1.0 / ng, 0.0)
+        m = np.ones((n, nh)) if self.uv_mask is None else np.asarray(self.uv_mask, dtype=np.float64)
+        w = np.ones(nc) if self.chan_w is None else np.asarray(self.chan_w, dtype=np.float64)
+        return w[:, None, None] * m[None, :, :]
+
+    def unit_weight(self, nc: int, n: int) -> np.ndarray:
+        """W_g N_g = [N_g > 0] on [nu][u][v]."""
+        if self.ng is not None:
+            return (np.asarray(self.ng) > 0).astype(np.float64)
+        return (self.data_weight(nc, n) > 0).astype(np.float64)
+
+    def uv_unit(self, n: int) -> np.ndarray:
+        nh = n // 2 + 1
+        return np.ones((n, nh)) if self.uv_mask is None else (np.asarray(self.uv_mask) > 0).astype(np.float64)
+
+    def chan(self, nc: int) -> np.ndarray:
+        return np.ones(nc) if self.chan_w is None else np.asarray(self.chan_w, dtype=np.float64)
+
+
+def symmetrize_columns(x: np.ndarray, n: int) -> np.ndarray:
+    """Replace the self-conjugate half-plane columns (v = 0, and v = n/2 for even n)
+    by (X(u) + conj X(-u)) / 2 along the u axis (second-to-last)."""
+    x = np.array(x, dtype=np.complex128, copy=True)
+    neg = (-np.arange(n)) % n
+    cols = [0] + ([n // 2] if n % 2 == 0 else [])
+    for c in cols:
+        col = x[..., :, c]
+        x[..., :, c] = 0.5 * (col + np.conj(col[..., neg]))
+    return x
+
+
+def round_counts(x: np.ndarray) -> Tuple[np.ndarray, float]:
+    """Round float triangle counts to int64; returns (counts, max |x - round(x)|)."""
+    r = np.rint(x)
+    dev = float(np.max(np.abs(x - r))) if x.size else 0.0
+    return r.astype(np.int64), dev
+
+
+# ---------------------------------------------------------------------------
+# MABS
+# ---------------------------------------------------------------------------
+class MabsFields:
+    """Lazily computed ring-filtered fields D_b(nu) and I_b(nu) (Eqs. iFT, iFT_I)."""
+
+    def __init__(self, bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None):
+        assert bins.kind == RING_U
+        self.bins = bins
+        self.n, self.nc = bins.n, bins.nc
+        self.vis = np.asarray(vis)
+        self.w = weights or Weights()
+        self.W = self.w.data_weight(self.nc, self.n)
+        self.Y = self.w.unit_weight(self.nc, self.n)
+        self._d: Dict[int, np.ndarray] = {}
+        self._i: Dict[int, np.ndarray] = {}
+
+    def data(self, b: int) -> np.ndarray:
+        """D_b[nu][x][y], real, for all channels."""
+        if b not in self._d:
+            ring = (self.bins.lut == b).astype(np.float64)
+            x = ring[None] * self.W * self.vis
+            x = symmetrize_columns(x, self.n)
+            self._d[b] = np.fft.irfft2(x, s=(self.n, self.n), axes=(1, 2))
+        return self._d[b]
+
+    def count(self, b: int) -> np.ndarray:
+        """I_b[nu][x][y]: inverse FT of the unit-weight indicator on ring b."""
+        if b not in self._i:
+            ring = (self.bins.lut == b).astype(np.float64)
+            y = symmetrize_columns(ring[None] * self.Y, self.n)
+            self._i[b] = np.fft.irfft2(y, s=(self.n, self.n), axes=(1, 2))
+        return self._i[b]
+
+
+def triple_sum(a: np.ndarray, b: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """S[i][j][k] = sum_p a[i,p] b[j,p] c[k,p] for a [n1][P], b [n2][P], c [n3][P]."""
+    out = np.empty((a.shape[0], b.shape[0], c.shape[0]))
+    for i in range(a.shape[0]):
+        out[i] = (a[i][None, :] * b) @ c.T
+    return out
+
+
+def estimate_mabs(bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None,
+                  tri: Optional[np.ndarray] = None, nu1: Optional[Iterable[int]] = None,
+                  norm: float = 1.0, fields: Optional[MabsFields] = None):
+    """Full MABS over all (nu2, nu3) for each triangle and each nu1 in `nu1`.
+
+    Returns (B [nt][n1][nc][nc], N_tri [nt][n1][nc][nc], S_D, max count deviation).
+    B is NaN where N_tri = 0.
+    """
+    f = fields or MabsFields(bins, vis, weights)
+    tri = bins.triangles if tri is None else np.asarray(tri).reshape(-1, 3)
+    nu1 = np.arange(bins.nc) if nu1 is None else np.asarray(list(nu1), dtype=np.int64)
+    npix = bins.n * bins.n
+    nt = len(tri)
+    S = np.empty((nt, len(nu1), bins.nc, bins.nc))
+    N = np.empty((nt, len(nu1), bins.nc, bins.nc), dtype=np.int64)
+    dev = 0.0
+    for t, (b1, b2, b3) in enumerate(tri):
+        d1 = f.data(b1).reshape(bins.nc, -1)[nu1]
+        d2 = f.data(b2).reshape(bins.nc, -1)
+        d3 = f.data(b3).reshape(bins.nc, -1)
+        S[t] = triple_sum(d1, d2, d3)
+        i1 = f.count(b1).reshape(bins.nc, -1)[nu1]
+        i2 = f.count(b2).reshape(bins.nc, -1)
+        i3 = f.count(b3).reshape(bins.nc, -1)
+        cnt, dv = round_counts(float(npix) * float(npix) * triple_sum(i1, i2, i3))
+        N[t] = cnt
+        dev = max(dev, dv)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        B = np.where(N > 0, norm * npix * S / np.where(N > 0, N, 1), np.nan)
+    return B, N, S, dev
+
+
+def mabs_entry(fields: MabsFields, tri3, nu) -> Tuple[float, int, float]:
+    """One MABS entry (b1,b2,b3; nu1,nu2,nu3): (S_D, N_tri, S_I) computed directly."""
+    b1, b2, b3 = (int(x) for x in tri3)
+    n1, n2, n3 = (int(x) for x in nu)
+    sd = float(np.sum(fields.data(b1)[n1] * fields.data(b2)[n2] * fields.data(b3)[n3]))
+    si = float(np.sum(fields.count(b1)[n1] * fields.count(b2)[n2] * fields.count(b3)[n3]))
+    npix = fields.n * fields.n
+    return sd, int(np.rint(npix * npix * si)), si
+
+
+def collapse_mabs(B: np.ndarray, N: np.ndarray, circular: bool = False):
+    """Ergodic collapse of a full MABS [nt][nc][nc][nc] to (dnu1, dnu2).
+
+    Non-circular: Bbar[t][d1 + nc - 1][d2 + nc - 1] is the mean of B(nu3 + d1, nu3 + d2, nu3)
+    over nu3 with all three channels inside [0, nc) and N_tri > 0; N_nu counts those
+    nu3 and Ntot sums their N_tri.  Circular: channel indices are taken mod nc and the
+    output is [nt][nc][nc] indexed by (d1 mod nc, d2 mod nc).
+    """
+    nt, nc = B.shape[0], B.shape[1]
+    size = nc if circular else 2 * nc - 1
+    Bbar = np.full((nt, size, size), np.nan)
+    Nnu = np.zeros((nt, size, size), dtype=np.int64)
+    Ntot = np.zeros((nt, size, size), dtype=np.int64)
+    drange = range(0, nc) if circular else range(-(nc - 1), nc)
+    for t in range(nt):
+        for d1 in drange:
+            for d2 in drange:
+                acc, cnt, tot = 0.0, 0, 0
+                for n3 in range(nc):
+                    a, b = n3 + d1, n3 + d2
+                    if circular:
+                        a, b = a % nc, b % nc
+                    elif not (0 <= a < nc and 0 <= b < nc):
+                        continue
+                    if N[t, a, b, n3] > 0:
+                        acc += B[t, a, b, n3]
+                        cnt += 1
+                        tot += int(N[t, a, b, n3])
+                i1 = d1 if circular else d1 + nc - 1
+                i2 = d2 if circular else d2 + nc - 1
+                Nnu[t, i1, i2] = cnt
+                Ntot[t, i1, i2] = tot
+                if cnt:
+                    Bbar[t, i1, i2] = acc / cnt
+    return Bbar, Nnu, Ntot
+
+
+# ---------------------------------------------------------------------------
+# 3D bispectrum
+# ---------------------------------------------------------------------------
+def delay_transform(vis: np.ndarray, weights: Optional[Weights] = None) -> np.ndarray:
+    """Vt[eta][u][v] = sum_nu w(nu) m(U) V(U, nu) exp(-2 pi i eta nu / nc) (forward DFT over nu)."""
+    w = weights or Weights()
+    if not w.separable():
+        raise NotImplementedError("3D estimator needs separable weights")
+    nc, n = vis.shape[0], vis.shape[1]
+    x = symmetrize_columns(np.asarray(vis) * w.data_weight(nc, n), n)
+    return np.fft.fft(x, axis=0)
+
+
+class ShellFields:
+    """Lazily computed shell-filtered real fields F_j and count fields I_j over (eta, u, v)."""
+
+    def __init__(self, bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None):
+        assert bins.kind == SHELL_K
+        self.bins = bins
+        self.w = weights or Weights()
+        self.vt = delay_transform(vis, self.w)
+        self.m = self.w.uv_unit(bins.n)
+        self.shape = (bins.nc, bins.n, bins.n)
+        self._f: Dict[int, np.ndarray] = {}
+        self._i: Dict[int, np.ndarray] = {}
+
+    def data(self, j: int) -> np.ndarray:
+        if j not in self._f:
+            x = (self.bins.lut == j) * self.vt
+            self._f[j] = np.fft.irfftn(x, s=self.shape, axes=(0, 1, 2))
+        return self._f[j]
+
+    def count(self, j: int) -> np.ndarray:
+        if j not in self._i:
+            y = ((self.bins.lut == j) * self.m[None]).astype(np.float64)
+            self._i[j] = np.fft.irfftn(y, s=self.shape, axes=(0, 1, 2))
+        return self._i[j]
+
+    def drop(self, keep: Iterable[int] = ()):
+        keep = set(keep)
+        for d in (self._f, self._i):
+            for k in list(d):
+                if k not in keep:
+                    del d[k]
+
+
+def rho3(weights: Optional[Weights], nc: int) -> float:
+    """rho3 = (1/nc) sum_nu w(nu)^3 (flag correction of the 3D normaliser)."""
+    w = (weights or Weights()).chan(nc)
+    return float(np.mean(w ** 3))
+
+
+def estimate_3d(bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None,
+                tri: Optional[np.ndarray] = None, norm: float = 1.0,
+                fields: Optional[ShellFields] = None):
+    """3D bispectrum per candidate triangle.
+
+    Returns (B [nt], T3D [nt] int64, N_eff [nt], S_D [nt], max count deviation).
+    """
+    f = fields or ShellFields(bins, vis, weights)
+    tri = bins.triangles if tri is None else np.asarray(tri).reshape(-1, 3)
+    nvox = bins.nc * bins.n * bins.n
+    nt = len(tri)
+    S = np.empty(nt)
+    SI = np.empty(nt)
+    for t, (a, b, c) in enumerate(tri):
+        S[t] = np.sum(f.data(a) * f.data(b) * f.data(c))
+        SI[t] = np.sum(f.count(a) * f.count(b) * f.count(c))
+    T, dev = round_counts(float(nvox) * float(nvox) * SI)
+    neff = T.astype(np.float64) * rho3(weights, bins.nc)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        B = np.where(T > 0, norm * nvox * S / np.where(neff > 0, neff, 1.0), np.nan)
+    return B, T, neff, S, dev
