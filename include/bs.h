@@ -1,0 +1,179 @@
+/*
+ * bs.h -- C ABI of libbs, a gfx950 (MI355X) implementation of the FFT-accelerated
+ * binned bispectrum estimator on gridded radio-interferometric visibilities of
+ * Gill & Bharadwaj 2025 (arXiv:2506.10526), "A Visibility-based 21 cm Bispectrum
+ * Estimator for Radio-interferometric Data".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns an int status, BS_OK (0) on success or a
+ *   negative BS_E* code.  No C++ exception crosses this boundary.  The message
+ *   of the last failure on a context is returned by bs_last_error().
+ * Memory: array arguments are DEVICE pointers (hipMalloc'd, or a PyTorch tensor's
+ *   data_ptr()) unless the parameter name ends in _host.  They are borrowed for
+ *   the duration of the call only.  Outputs go to caller-allocated buffers.  All
+ *   device work is enqueued on the context's HIP stream; a call returns after the
+ *   work is enqueued and the small host-visible results (if any) are ready, so the
+ *   caller must synchronise the stream before reading device outputs.
+ *   The library owns its scratch memory (workspace, plans, count caches) until
+ *   bs_destroy(); it grows on demand with hipMalloc and is never shrunk.
+ * Layout of the visibility cube (Sec. 3.2, Eq. vg): V[nc][n][n/2+1], channel-major,
+ *   the Hermitian half plane v >= 0 of an n x n uv grid with signed FFT indices
+ *   (q = i for i < n/2, i - n otherwise).  complex64 (interleaved float re,im) for
+ *   BS_FP32 and BS_SPLIT_BF16, complex128 for BS_FP64.  Self-conjugate columns
+ *   (v = 0, v = n/2) are symmetrised as (X(u) + conj X(-u)) / 2 after weighting.
+ * Discrete conventions: unnormalised forward DFTs, inverse transforms carry 1/N
+ *   (N = pixels for the MABS, voxels for the 3D estimator).  B is in grid units
+ *   times `norm` (pass 1/A with A = pi theta_0^2 Q^3 / 3 for the physical units of
+ *   Eq. estimator_t).
+ * Threads: a context must not be used by two host threads at the same time.
+ */
+#ifndef BS_H
+#define BS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define BS_OK 0
+#define BS_EINVAL (-1)        /* bad argument: shapes, edges, pointers, unsupported combination of inputs */
+#define BS_ENOMEM (-2)        /* device allocation failed */
+#define BS_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
+#define BS_ECOUNT (-4)        /* an FP64 triangle count was not within 1e-3 of an integer */
+#define BS_EUNSUPPORTED (-5)  /* valid request this build does not implement (e.g. 3D with per-cell N_g) */
+
+typedef struct bs_ctx bs_ctx;
+typedef struct bs_bins bs_bins;
+
+/* ---- context ----
+ * bs_create: bind a context to HIP device `device` and stream `hip_stream`
+ *   (a hipStream_t; NULL = the device's null stream).  *out receives the context.
+ * bs_destroy: frees all library-owned device memory of the context.  NULL is a no-op.
+ * bs_last_error: message of the last failing call on `ctx` ("" if none). */
+int bs_create(int device, void* hip_stream, bs_ctx** out);
+void bs_destroy(bs_ctx* ctx);
+const char* bs_last_error(const bs_ctx* ctx);
+/* Rebind the stream work is enqueued on (same device). */
+int bs_set_stream(bs_ctx* ctx, void* hip_stream);
+
+/* ---- binning (Sec. 3.2 and Fig. 1: annular rings of the uv plane; 3D |k| shells) ----
+ * BS_RING_U: rings in |U| = sqrt(q_u^2 + q_v^2), in grid cells, for the MABS.
+ * BS_SHELL_K: shells in |k| = sqrt(k_perp^2 + k_par^2) in Mpc^-1 for the 3D estimator, with
+ *   k_perp = 2 pi du_lambda |U| / r_mpc (Sec. 2.1: l = 2 pi U = r k_perp) and
+ *   k_par = 2 pi q_eta / (rprime_mpc_per_mhz * nc * dnu_mhz) (Eq. dft: k_par,a = 2 pi a / (r' B_bw)),
+ *   evaluated in float64 as sqrt(cperp*cperp*(qu*qu+qv*qv) + cpar*cpar*qeta*qeta) with
+ *   cperp = 2 pi du / r and cpar = 2 pi / (r' nc dnu).
+ * Bins are half open, e_j <= x < e_{j+1}.  The uv support is 1 <= |U| <= umax cells
+ * (umax <= 0 selects floor((n-1)/3), which makes closure mod n true closure) and never
+ * contains Nyquist rows/columns; the Nyquist delay plane is excluded as well.
+ * Candidate triangles are the sorted bin triples b1 >= b2 >= b3 over non-empty bins
+ * (ordering k1 >= k2 >= k3 of Sec. 2.2, Eq. shape); when closure is true closure, triples
+ * with e_{b1} >= e_{b2+1} + e_{b3+1} cannot close and are dropped.  A candidate is valid
+ * when its triangle count is non-zero. */
+typedef enum { BS_RING_U = 0, BS_SHELL_K = 1 } bs_bin_kind;
+
+typedef struct {
+  int32_t kind;             /* bs_bin_kind */
+  int32_t n;                /* uv grid is n x n (n even, 8 <= n <= 1024) */
+  int32_t nc;               /* channels (2^a 3^b, 2 <= nc <= 1536) */
+  int32_t nbins;            /* number of bins, 1 <= nbins <= 120 */
+  const double* edges_host; /* nbins+1 strictly increasing finite edges: cells (RING_U) or Mpc^-1 (SHELL_K) */
+  double umax;              /* uv support radius in cells; <= 0 for the default floor((n-1)/3) */
+  double du_lambda;         /* SHELL_K only: uv cell size in wavelengths (dU_g of Sec. 3.2) */
+  double r_mpc;             /* SHELL_K only: comoving distance r */
+  double rprime_mpc_per_mhz;/* SHELL_K only: r' = dr/dnu */
+  double dnu_mhz;           /* SHELL_K only: channel width */
+} bs_bins_desc;
+
+/* Build the bin plan.  *out receives a plan owned by the caller (free with bs_free_bins);
+ * *n_candidates receives the number of candidate triangles.  Device LUTs live on the
+ * context's device.  ctx == NULL gives a host-only plan (triangles, modes, info; no
+ * estimates).  Errors: BS_EINVAL for bad descriptors. */
+int bs_make_bins(bs_ctx* ctx, const bs_bins_desc* desc, bs_bins** out, int32_t* n_candidates);
+/* Copy the candidate list (int32 [n_candidates][3], b1 >= b2 >= b3) and the per-bin mode
+ * counts over the full Fourier grid (int64 [nbins]) to host buffers; either may be NULL. */
+int bs_bins_triangles(const bs_bins* bins, int32_t* tri3_host, int64_t* modes_per_bin_host);
+/* Largest |q_eta| inside any shell (SHELL_K) and whether closure mod the grid is true closure. */
+int bs_bins_info(const bs_bins* bins, int32_t* eta_max, int32_t* true_closure);
+void bs_free_bins(bs_bins* bins);
+
+/* ---- weights (Sec. 3.2, Eq. vg and the weights below Eq. iFT) ----
+ * Exactly one form:
+ *  - per-cell counts: ng != NULL, uint16 [nc][n][n/2+1]; data weight W_g = 1/N_g on filled
+ *    cells and 0 on empty ones, unit weight [N_g > 0] (Eq. iFT_I).  The v = 0 column must be
+ *    Hermitian-consistent (N_g(-u,0) == N_g(u,0)).
+ *  - separable: ng == NULL; uv_mask uint8 [n][n/2+1] occupancy (NULL = all ones) times
+ *    chan_w float [nc] with values in {0,1} (flagged channels, NULL = all ones).  The library
+ *    multiplies V by W_g itself; the uv_mask v = 0 column must be Hermitian-consistent. */
+typedef struct {
+  const uint16_t* ng;
+  const uint8_t* uv_mask;
+  const float* chan_w;
+} bs_weights;
+
+typedef enum { BS_FP64 = 0, BS_FP32 = 1, BS_SPLIT_BF16 = 2 } bs_precision;
+
+/* ---- filtered fields (Eqs. iFT and iFT_I) ----
+ * three_d == 0 (RING_U bins): fields[nbins][nc][n][n] real, D(l_m, nu, theta) = inverse 2D FT
+ *   of W_g V_g restricted to ring m, per channel (NumPy normalisation, 1/n^2).
+ * three_d == 1 (SHELL_K bins): fields[nbins][nc][n][n] real, the inverse 3D FT over
+ *   (delay, u, v) of the delay-transformed weighted cube restricted to shell m (1/(nc n^2)).
+ * count_fields (nullable): same shape, float64, from the unit-weight indicator (Eq. iFT_I).
+ * `fields` is float32 for BS_FP32 / BS_SPLIT_BF16 and float64 for BS_FP64 (precision argument).
+ * Empty bins give all-zero fields. */
+int bs_filter_fields(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_weights* w,
+                     int32_t three_d, int32_t precision, void* fields, double* count_fields);
+
+/* ---- MABS estimator (Sec. 3.2, Eq. estimator_t; ergodic collapse described before Eq. dft) ----
+ * For each selected triangle t = (b1,b2,b3) and channels (nu1,nu2,nu3):
+ *   S_D = sum_theta D_b1(nu1) D_b2(nu2) D_b3(nu3),  N_tri = n^4 sum_theta I_b1 I_b2 I_b3 (exact int),
+ *   B = norm * n^2 * S_D / N_tri, and NaN where N_tri == 0.
+ * Selection: tri3_host (int32 [n_tri][3], any order of the three bins; NULL = all candidates)
+ *   and nu1_host (int32 [n_nu1]; NULL = all channels).
+ * collapse == 0: B, N_tri are [n_tri][n_nu1][nc][nc] indexed [t][i][nu2][nu3] with nu1 = nu1_host[i];
+ *   N_nu unused (may be NULL).
+ * collapse == 1 (non-circular) / 2 (circular channels): requires all channels as nu1 (nu1_host NULL);
+ *   B[t][d1'][d2'] is the mean over valid nu3 of B(nu3+d1, nu3+d2, nu3) with d' = d + nc - 1 and
+ *   size 2nc-1 (non-circular) or d' = d mod nc and size nc (circular); N_tri sums the counts of the
+ *   averaged triplets; N_nu (int32, same shape) counts them (Sec. 5, Fig. 2).
+ * The contraction runs in `precision`: BS_FP64 (vis complex128), BS_FP32 (FP32 MFMA) or
+ * BS_SPLIT_BF16 (three-product hi/lo bfloat16 MFMA with FP32 accumulation); partial sums across
+ * pixel chunks and the final division are float64 in every mode.  Counts always use float64 fields.
+ * Errors: BS_EINVAL (shapes, selection), BS_ECOUNT, BS_ENOMEM, BS_EHIP. */
+typedef struct {
+  int32_t n_tri;
+  const int32_t* tri3_host;
+  int32_t n_nu1;
+  const int32_t* nu1_host;
+  int32_t collapse;
+} bs_mabs_sel;
+
+int bs_estimate_mabs(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_weights* w,
+                     const bs_mabs_sel* sel, int32_t precision, double norm,
+                     double* B, int64_t* N_tri, int32_t* N_nu);
+
+/* ---- 3D bispectrum (delay transform along frequency, |k| shells; Sec. 2.2, Eq. dft) ----
+ * Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) exp(-2 pi i eta nu / nc); F_j = inverse 3D FT of Vt on shell j;
+ * for each candidate triangle (a,b,c): S_D = sum_x F_a F_b F_c over the nc*n*n voxels,
+ * T3D = (nc n^2)^2 sum_x I_a I_b I_c (exact integer, I_j from the unit indicator of shell j),
+ * rho3 = (1/nc) sum_nu w(nu)^3, N_eff = T3D rho3 and B = norm * nc * n^2 * S_D / N_eff (NaN if T3D == 0).
+ * Outputs (device): B float64 [n_cand], N_tri int64 [n_cand] (= T3D), N_eff float64 [n_cand] (nullable).
+ * Requires separable weights (BS_EUNSUPPORTED for per-cell N_g).  Counts depend only on the geometry and
+ * are cached per (bins, uv_mask) in the context. */
+int bs_estimate_3d(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_weights* w,
+                   int32_t precision, double norm, double* B, int64_t* N_tri, double* N_eff);
+
+/* ---- diagnostics ----
+ * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP
+ * events on the context's stream: out_ms_host[0] = whole call, [1] = the dominant contraction kernel,
+ * [2] = fields/FFT kernels.  Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
+int bs_set_timing(bs_ctx* ctx, int32_t enable);
+int bs_last_timing(const bs_ctx* ctx, double* out_ms_host, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BS_H */

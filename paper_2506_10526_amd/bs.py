@@ -1,0 +1,198 @@
+"""ctypes binding of libbs (include/bs.h): argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and passes device
+pointers (PyTorch tensors' data_ptr()) straight through; all computation happens in
+the HIP library.  If libbs.so is missing the import of this module still succeeds, but
+every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbs.so")
+
+BS_OK, BS_EINVAL, BS_ENOMEM, BS_EHIP, BS_ECOUNT, BS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BS_RING_U, BS_SHELL_K = 0, 1
+BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
+
+EXPORTED = [
+    "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_estimate_3d",
+    "bs_set_timing", "bs_last_timing",
+]
+
+
+class BsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libbs error {code}: {msg}")
+        self.code = code
+
+
+class bs_bins_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("nbins", ctypes.c_int32), ("edges_host", ctypes.POINTER(ctypes.c_double)),
+                ("umax", ctypes.c_double), ("du_lambda", ctypes.c_double), ("r_mpc", ctypes.c_double),
+                ("rprime_mpc_per_mhz", ctypes.c_double), ("dnu_mhz", ctypes.c_double)]
+
+
+class bs_weights(ctypes.Structure):
+    _fields_ = [("ng", ctypes.c_void_p), ("uv_mask", ctypes.c_void_p), ("chan_w", ctypes.c_void_p)]
+
+
+class bs_mabs_sel(ctypes.Structure):
+    _fields_ = [("n_tri", ctypes.c_int32), ("tri3_host", ctypes.POINTER(ctypes.c_int32)),
+                ("n_nu1", ctypes.c_int32), ("nu1_host", ctypes.POINTER(ctypes.c_int32)),
+                ("collapse", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIBPATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.bs_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.bs_destroy.argtypes = [vp]
+    L.bs_destroy.restype = None
+    L.bs_last_error.argtypes = [vp]
+    L.bs_last_error.restype = ctypes.c_char_p
+    L.bs_set_stream.argtypes = [vp, vp]
+    L.bs_make_bins.argtypes = [vp, ctypes.POINTER(bs_bins_desc), ctypes.POINTER(vp), ctypes.POINTER(i32)]
+    L.bs_bins_triangles.argtypes = [vp, vp, vp]
+    L.bs_bins_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.bs_free_bins.argtypes = [vp]
+    L.bs_free_bins.restype = None
+    L.bs_filter_fields.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, i32, vp, vp]
+    L.bs_estimate_mabs.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), ctypes.POINTER(bs_mabs_sel), i32, dbl,
+                                   vp, vp, vp]
+    L.bs_estimate_3d.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, dbl, vp, vp, vp]
+    L.bs_set_timing.argtypes = [vp, i32]
+    L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
+    for name in EXPORTED:
+        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _check(ctx, rc: int):
+    if rc != BS_OK:
+        msg = lib().bs_last_error(ctx).decode() if ctx else ""
+        raise BsError(rc, msg)
+
+
+# ---------------------------------------------------------------- entry points
+def bs_create(device: int = 0, stream: Optional[int] = None) -> int:
+    h = ctypes.c_void_p()
+    rc = lib().bs_create(device, stream, ctypes.byref(h))
+    if rc != BS_OK:
+        raise BsError(rc, "bs_create failed")
+    return h.value
+
+
+def bs_destroy(ctx: int) -> None:
+    lib().bs_destroy(ctx)
+
+
+def bs_last_error(ctx: int) -> str:
+    return lib().bs_last_error(ctx).decode()
+
+
+def bs_set_stream(ctx: int, stream: Optional[int]) -> None:
+    _check(ctx, lib().bs_set_stream(ctx, stream))
+
+
+def bs_make_bins(ctx: Optional[int], kind: int, n: int, nc: int, edges: Sequence[float], umax: float = 0.0,
+                 du_lambda: float = 0.0, r_mpc: float = 0.0, rprime_mpc_per_mhz: float = 0.0,
+                 dnu_mhz: float = 0.0):
+    """Returns (bins handle, n_candidates)."""
+    e = (ctypes.c_double * len(edges))(*[float(x) for x in edges])
+    d = bs_bins_desc(kind, n, nc, len(edges) - 1, e, umax, du_lambda, r_mpc, rprime_mpc_per_mhz, dnu_mhz)
+    h = ctypes.c_void_p()
+    nc_ = ctypes.c_int32()
+    _check(ctx, lib().bs_make_bins(ctx, ctypes.byref(d), ctypes.byref(h), ctypes.byref(nc_)))
+    return h.value, nc_.value
+
+
+def bs_bins_triangles(bins: int, n_candidates: int, nbins: int):
+    """Host copies: (triangles int32 [n][3], modes int64 [nbins]) as nested lists via numpy."""
+    import numpy as np
+    tri = np.zeros((max(n_candidates, 1), 3), dtype=np.int32)
+    modes = np.zeros(max(nbins, 1), dtype=np.int64)
+    rc = lib().bs_bins_triangles(bins, tri.ctypes.data, modes.ctypes.data)
+    if rc != BS_OK:
+        raise BsError(rc, "bs_bins_triangles failed")
+    return tri[:n_candidates], modes[:nbins]
+
+
+def bs_bins_info(bins: int):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().bs_bins_info(bins, ctypes.byref(a), ctypes.byref(b))
+    if rc != BS_OK:
+        raise BsError(rc, "bs_bins_info failed")
+    return a.value, bool(b.value)
+
+
+def bs_free_bins(bins: int) -> None:
+    lib().bs_free_bins(bins)
+
+
+def _weights(ng=None, uv_mask=None, chan_w=None) -> bs_weights:
+    return bs_weights(_ptr(ng), _ptr(uv_mask), _ptr(chan_w))
+
+
+def bs_filter_fields(ctx: int, bins: int, vis, three_d: int, precision: int, fields, count_fields=None,
+                     ng=None, uv_mask=None, chan_w=None) -> None:
+    w = _weights(ng, uv_mask, chan_w)
+    _check(ctx, lib().bs_filter_fields(ctx, bins, _ptr(vis), ctypes.byref(w), three_d, precision,
+                                       _ptr(fields), _ptr(count_fields)))
+
+
+def bs_estimate_mabs(ctx: int, bins: int, vis, precision: int, B, N_tri, N_nu=None, norm: float = 1.0,
+                     tri3=None, nu1=None, collapse: int = 0, ng=None, uv_mask=None, chan_w=None) -> None:
+    w = _weights(ng, uv_mask, chan_w)
+    tri_arr = nu_arr = None
+    ntri = nnu = 0
+    if tri3 is not None:
+        flat = [int(x) for row in tri3 for x in row]
+        ntri = len(flat) // 3
+        tri_arr = (ctypes.c_int32 * max(len(flat), 1))(*flat)
+    if nu1 is not None:
+        nu = [int(x) for x in nu1]
+        nnu = len(nu)
+        nu_arr = (ctypes.c_int32 * max(nnu, 1))(*nu)
+    sel = bs_mabs_sel(ntri, tri_arr, nnu, nu_arr, collapse)
+    _check(ctx, lib().bs_estimate_mabs(ctx, bins, _ptr(vis), ctypes.byref(w), ctypes.byref(sel), precision,
+                                       float(norm), _ptr(B), _ptr(N_tri), _ptr(N_nu)))
+
+
+def bs_estimate_3d(ctx: int, bins: int, vis, precision: int, B, N_tri, N_eff=None, norm: float = 1.0,
+                   uv_mask=None, chan_w=None, ng=None) -> None:
+    w = _weights(ng, uv_mask, chan_w)
+    _check(ctx, lib().bs_estimate_3d(ctx, bins, _ptr(vis), ctypes.byref(w), precision, float(norm),
+                                     _ptr(B), _ptr(N_tri), _ptr(N_eff)))
+
+
+def bs_set_timing(ctx: int, enable: bool) -> None:
+    _check(ctx, lib().bs_set_timing(ctx, 1 if enable else 0))
+
+
+def bs_last_timing(ctx: int):
+    out = (ctypes.c_double * 3)()
+    _check(ctx, lib().bs_last_timing(ctx, out, 3))
+    return list(out)

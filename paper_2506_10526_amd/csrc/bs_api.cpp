@@ -1,0 +1,523 @@
+// C ABI of libbs: context, workspace, bin plans, and the MABS estimator pipeline.
+// The 3D estimator lives in bs_api3d.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "bs_ctx.h"
+#include "bs_kernels.h"
+
+// ------------------------------------------------------------------ helpers
+int ctx_fail(bs_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                         \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return ctx_fail(ctx, BS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define LAUNCHCHK(ctx, what)                                                                      \
+  do {                                                                                            \
+    hipError_t e_ = hipGetLastError();                                                            \
+    if (e_ != hipSuccess) return ctx_fail(ctx, BS_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void* ctx_ws(bs_ctx* c, const char* name, size_t bytes) {
+  DevBuf& b = c->ws[name];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  if (getenv("BS_FORCE_ENOMEM")) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  b.p = p;
+  b.bytes = bytes;
+  return p;
+}
+
+bool fft_len_ok(int L) {
+  if (L < 2) return false;
+  while (L % 2 == 0) L /= 2;
+  while (L % 3 == 0) L /= 3;
+  return L == 1;
+}
+
+FftPlan make_fft_plan(int L) {
+  FftPlan p{};
+  p.L = L;
+  int m = L, nr = 0;
+  while (m % 8 == 0 && nr < 13) { p.rad[nr++] = 8; m /= 8; }
+  if (m % 4 == 0) { p.rad[nr++] = 4; m /= 4; }
+  if (m % 2 == 0) { p.rad[nr++] = 2; m /= 2; }
+  while (m % 3 == 0 && nr < 14) { p.rad[nr++] = 3; m /= 3; }
+  p.nr = nr;
+  return p;
+}
+
+const void* ctx_twiddle(bs_ctx* c, int L, bool fp64) {
+  auto& mp = fp64 ? c->tw64 : c->tw32;
+  auto it = mp.find(L);
+  if (it != mp.end()) return it->second;
+  std::vector<double> w(2 * (size_t)L);
+  for (int m = 0; m < L; ++m) {
+    // exp(-2 pi i m / L), reduced to the first octant-free form via exact symmetric angles
+    long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+    w[2 * m] = (double)cosl(ang);
+    w[2 * m + 1] = (double)sinl(ang);
+  }
+  void* d = nullptr;
+  size_t bytes = fp64 ? 16 * (size_t)L : 8 * (size_t)L;
+  if (hipMalloc(&d, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  if (fp64) {
+    if (hipMemcpy(d, w.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  } else {
+    std::vector<float> f(2 * (size_t)L);
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)w[i];
+    if (hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  }
+  mp[L] = d;
+  return d;
+}
+
+// ------------------------------------------------------------------ context
+extern "C" int bs_create(int device, void* hip_stream, bs_ctx** out) {
+  if (!out) return BS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { (void)hipGetLastError(); return BS_EHIP; }
+  if (device < 0 || device >= ndev) return BS_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return BS_EHIP;
+  bs_ctx* c = new bs_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) { delete c; return BS_EHIP; }
+  }
+  *out = c;
+  return BS_OK;
+}
+
+extern "C" void bs_destroy(bs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->ws) if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : c->tw32) (void)hipFree(kv.second);
+  for (auto& kv : c->tw64) (void)hipFree(kv.second);
+  for (auto& kv : c->counts) if (kv.second.d_counts) (void)hipFree(kv.second.d_counts);
+  for (auto& e : c->ev) if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+extern "C" const char* bs_last_error(const bs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int bs_set_stream(bs_ctx* c, void* s) {
+  if (!c) return BS_EINVAL;
+  c->stream = (hipStream_t)s;
+  return BS_OK;
+}
+
+extern "C" int bs_set_timing(bs_ctx* c, int32_t enable) {
+  if (!c) return BS_EINVAL;
+  c->timing = enable != 0;
+  c->have_timing = false;
+  return BS_OK;
+}
+
+extern "C" int bs_last_timing(const bs_ctx* cc, double* out, int32_t n) {
+  bs_ctx* c = const_cast<bs_ctx*>(cc);
+  if (!c || !out || !c->timing || !c->have_timing) return BS_EINVAL;
+  // events: 0 start, 1 end, 2/3 contraction, 4/5 fields
+  float ms = 0.f;
+  if (hipEventSynchronize(c->ev[1]) != hipSuccess) return BS_EHIP;
+  double v[3] = {0, 0, 0};
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) v[0] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) v[1] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) v[2] = ms;
+  (void)hipGetLastError();
+  for (int i = 0; i < n && i < 3; ++i) out[i] = v[i];
+  return BS_OK;
+}
+
+// ------------------------------------------------------------------ bins
+extern "C" int bs_make_bins(bs_ctx* c, const bs_bins_desc* d, bs_bins** out, int32_t* ncand) {
+  if (!d || !out) return ctx_fail(c, BS_EINVAL, "bs_make_bins: NULL argument");
+  *out = nullptr;
+  if (d->kind == BS_SHELL_K && !fft_len_ok(d->nc)) return ctx_fail(c, BS_EINVAL, "nc must be 2^a 3^b");
+  if (d->kind == BS_RING_U && !fft_len_ok(d->n)) return ctx_fail(c, BS_EINVAL, "n must be 2^a 3^b");
+  bs_bins* b = new bs_bins();
+  std::string e = bsplan::build_plan(d->kind, d->n, d->nc, d->nbins, d->edges_host, d->umax, d->du_lambda,
+                                     d->r_mpc, d->rprime_mpc_per_mhz, d->dnu_mhz, b->P);
+  if (!e.empty()) { delete b; return ctx_fail(c, BS_EINVAL, "bs_make_bins: " + e); }
+  if (!fft_len_ok(d->n)) { delete b; return ctx_fail(c, BS_EINVAL, "n must be 2^a 3^b"); }
+  b->ctx = c;
+  if (!c) {  // host-only plan: triangle lists and mode counts, no device LUT
+    *out = b;
+    if (ncand) *ncand = (int32_t)(b->P.tri.size() / 3);
+    return BS_OK;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) { delete b; return ctx_fail(c, BS_EHIP, "hipSetDevice"); }
+  size_t bytes = b->P.lut.size();
+  if (hipMalloc(&b->d_lut, bytes) != hipSuccess) { (void)hipGetLastError(); delete b; return ctx_fail(c, BS_ENOMEM, "lut"); }
+  if (hipMemcpy(b->d_lut, b->P.lut.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(b->d_lut); delete b; return ctx_fail(c, BS_EHIP, "lut copy");
+  }
+  *out = b;
+  if (ncand) *ncand = (int32_t)(b->P.tri.size() / 3);
+  return BS_OK;
+}
+
+extern "C" int bs_bins_triangles(const bs_bins* b, int32_t* tri, int64_t* modes) {
+  if (!b) return BS_EINVAL;
+  if (tri) std::memcpy(tri, b->P.tri.data(), b->P.tri.size() * sizeof(int32_t));
+  if (modes) std::memcpy(modes, b->P.modes.data(), b->P.modes.size() * sizeof(int64_t));
+  return BS_OK;
+}
+
+extern "C" int bs_bins_info(const bs_bins* b, int32_t* eta_max, int32_t* true_closure) {
+  if (!b) return BS_EINVAL;
+  if (eta_max) *eta_max = b->P.eta_max;
+  if (true_closure) *true_closure = b->P.true_closure ? 1 : 0;
+  return BS_OK;
+}
+
+extern "C" void bs_free_bins(bs_bins* b) {
+  if (!b) return;
+  if (b->d_lut) (void)hipFree(b->d_lut);
+  delete b;
+}
+
+// ------------------------------------------------------------------ ring fields
+namespace {
+
+struct RingFieldLaunch {
+  int G, CB, RB;
+  size_t lds;
+};
+
+RingFieldLaunch ring_field_geometry(int n, int vmax, size_t esz) {
+  const int ncols = vmax + 1, M = n / 2;
+  RingFieldLaunch r{};
+  for (int G = 1; G <= n / 4; G *= 2) {
+    if (n % G) break;
+    int Lc = n / G;
+    int CB = std::max(1, std::min(ncols, 2048 / Lc));
+    int RB = std::max(1, std::min(Lc, 2048 / M));
+    size_t work = std::max((size_t)CB * Lc, (size_t)RB * M);
+    size_t lds = esz * ((size_t)ncols * Lc + 2 * work);
+    r = {G, CB, RB, lds};
+    if (lds <= 128 * 1024) return r;
+  }
+  return r;
+}
+
+// Launch ring-filtered fields for `blocks` (ring ids) over channels [0, nch) of `vis`.
+int run_ring_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64,
+                    bool count_mode, bool ignore_chan, int nch, const std::vector<int>& blocks,
+                    void* out, long long bin_stride) {
+  const auto& P = b->P;
+  const int n = P.n;
+  if (blocks.empty()) return BS_OK;
+  int* d_bins = (int*)ctx_ws(c, count_mode ? "ring_bins_c" : "ring_bins_d", blocks.size() * sizeof(int));
+  if (!d_bins) return ctx_fail(c, BS_ENOMEM, "workspace (ring ids)");
+  HIPCHK(c, hipMemcpyAsync(d_bins, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  const void* tw = ctx_twiddle(c, n, fp64);
+  if (!tw) return ctx_fail(c, BS_ENOMEM, "twiddle table");
+  RingFieldLaunch g = ring_field_geometry(n, P.vmax, fp64 ? 16 : 8);
+  if (g.lds > 160 * 1024) return ctx_fail(c, BS_EUNSUPPORTED, "ring field transform does not fit in LDS");
+  MabsFieldArgs a{};
+  a.vis = vis;
+  a.ng = w ? w->ng : nullptr;
+  a.uvm = w ? w->uv_mask : nullptr;
+  a.chw = w ? w->chan_w : nullptr;
+  a.lut = b->d_lut;
+  a.smax = P.smax;
+  a.bins = d_bins;
+  a.n = n; a.nh = P.nh; a.nc = P.nc; a.vmax = P.vmax;
+  a.G = g.G; a.CB = g.CB; a.RB = g.RB;
+  a.count_mode = count_mode ? 1 : 0;
+  a.ignore_chan = ignore_chan ? 1 : 0;
+  a.out = out;
+  a.plane_stride = (long long)n * n;
+  a.bin_stride = bin_stride;
+  a.tw_n = tw;
+  a.pcol = make_fft_plan(n / g.G);
+  a.prow = make_fft_plan(n / 2);
+  a.scale = 1.0 / ((double)n * (double)n);
+  // grid.y is limited to 65535: split the channel range
+  for (int c0 = 0; c0 < nch; c0 += 65535) {
+    a.chan_offset = c0;
+    int cn = std::min(65535, nch - c0);
+    if (fp64) launch_mabs_fields_f64(a, (int)blocks.size(), cn, g.lds, c->stream);
+    else launch_mabs_fields_f32(a, (int)blocks.size(), cn, g.lds, c->stream);
+    LAUNCHCHK(c, "ring field kernel");
+  }
+  return BS_OK;
+}
+
+int check_weights(bs_ctx* c, const bs_weights* w) {
+  if (!w) return BS_OK;
+  if (w->ng && (w->uv_mask || w->chan_w)) return ctx_fail(c, BS_EINVAL, "weights: give either ng or (uv_mask, chan_w)");
+  return BS_OK;
+}
+
+uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
+  const unsigned char* q = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) { h ^= q[i]; h *= 1099511628211ULL; }
+  return h;
+}
+
+}  // namespace
+
+extern "C" int bs_filter_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
+                                int32_t three_d, int32_t precision, void* fields, double* count_fields);
+int filter_fields_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, int32_t precision,
+                     void* fields, double* count_fields);
+
+extern "C" int bs_filter_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
+                                int32_t three_d, int32_t precision, void* fields, double* count_fields) {
+  if (!c || !b || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_filter_fields: NULL context or host-only bins");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  int rc = check_weights(c, w);
+  if (rc) return rc;
+  if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
+  if (three_d) return filter_fields_3d(c, b, vis, w, precision, fields, count_fields);
+  if (b->P.kind != BS_RING_U) return ctx_fail(c, BS_EINVAL, "three_d == 0 needs BS_RING_U bins");
+  if (!vis && fields) return ctx_fail(c, BS_EINVAL, "vis is NULL");
+  const auto& P = b->P;
+  const long long plane = (long long)P.n * P.n;
+  std::vector<int> blocks(P.nbins);
+  for (int i = 0; i < P.nbins; ++i) blocks[i] = i;
+  if (fields) {
+    rc = run_ring_fields(c, b, vis, w, precision == BS_FP64, false, false, P.nc, blocks, fields, plane * P.nc);
+    if (rc) return rc;
+  }
+  if (count_fields) {
+    rc = run_ring_fields(c, b, vis, w, true, true, false, P.nc, blocks, count_fields, plane * P.nc);
+    if (rc) return rc;
+  }
+  return BS_OK;
+}
+
+// ------------------------------------------------------------------ MABS
+extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
+                                const bs_mabs_sel* sel, int32_t precision, double norm, double* B,
+                                int64_t* N_tri, int32_t* N_nu) {
+  if (!c || !b || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_estimate_mabs: NULL context or host-only bins");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  const auto& P = b->P;
+  if (P.kind != BS_RING_U) return ctx_fail(c, BS_EINVAL, "MABS needs BS_RING_U bins");
+  if (!vis || !B || !N_tri) return ctx_fail(c, BS_EINVAL, "vis, B and N_tri must be non-NULL");
+  if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
+  int rc = check_weights(c, w);
+  if (rc) return rc;
+  const int nc = P.nc, n = P.n;
+  const int Ppix = n * n;
+  if (precision != BS_FP64 && n % 8)
+    return ctx_fail(c, BS_EUNSUPPORTED, "MFMA contraction needs n % 8 == 0 (pixel rows in 64-element blocks)");
+  // ---- selection ----
+  std::vector<int> tri;
+  if (sel && sel->tri3_host) {
+    if (sel->n_tri < 0) return ctx_fail(c, BS_EINVAL, "n_tri < 0");
+    tri.assign(sel->tri3_host, sel->tri3_host + 3 * (size_t)sel->n_tri);
+    for (int x : tri) if (x < 0 || x >= P.nbins) return ctx_fail(c, BS_EINVAL, "triangle bin out of range");
+  } else {
+    tri.assign(P.tri.begin(), P.tri.end());
+  }
+  const int ntri = (int)(tri.size() / 3);
+  const int collapse = sel ? sel->collapse : 0;
+  if (collapse < 0 || collapse > 2) return ctx_fail(c, BS_EINVAL, "collapse must be 0, 1 or 2");
+  std::vector<int> nu1;
+  if (sel && sel->nu1_host) {
+    if (collapse) return ctx_fail(c, BS_EINVAL, "collapse needs all channels as nu1");
+    if (sel->n_nu1 <= 0) return ctx_fail(c, BS_EINVAL, "n_nu1 must be positive");
+    nu1.assign(sel->nu1_host, sel->nu1_host + sel->n_nu1);
+    for (int x : nu1) if (x < 0 || x >= nc) return ctx_fail(c, BS_EINVAL, "nu1 out of range");
+  } else {
+    nu1.resize(nc);
+    for (int i = 0; i < nc; ++i) nu1[i] = i;
+  }
+  if (collapse && !N_nu) return ctx_fail(c, BS_EINVAL, "collapse needs N_nu");
+  if (ntri == 0) return BS_OK;
+  const int n_nu1 = (int)nu1.size();
+  const bool separable = !(w && w->ng);
+  const bool fp64 = precision == BS_FP64;
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+
+  // ---- ring blocks used by the selection ----
+  std::map<int, int> blk;
+  for (int x : tri) blk.emplace(x, 0);
+  std::vector<int> blocks;
+  for (auto& kv : blk) { kv.second = (int)blocks.size(); blocks.push_back(kv.first); }
+  std::vector<int> tri_blk(tri.size());
+  for (size_t i = 0; i < tri.size(); ++i) tri_blk[i] = blk[tri[i]];
+  const int nbu = (int)blocks.size();
+  const long long bstride = (long long)nc * Ppix;
+
+  // ---- data fields ----
+  size_t esz = fp64 ? 8 : 4;
+  void* F = ctx_ws(c, "mabs_F", (size_t)nbu * bstride * esz);
+  if (!F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
+  rc = run_ring_fields(c, b, vis, w, fp64, false, false, nc, blocks, F, bstride);
+  if (rc) return rc;
+  uint16_t *Fh = nullptr, *Fl = nullptr;
+  if (precision == BS_SPLIT_BF16) {
+    Fh = (uint16_t*)ctx_ws(c, "mabs_Fh", (size_t)nbu * bstride * 2);
+    Fl = (uint16_t*)ctx_ws(c, "mabs_Fl", (size_t)nbu * bstride * 2);
+    if (!Fh || !Fl) return ctx_fail(c, BS_ENOMEM, "workspace (split fields)");
+    launch_split_bf16((const float*)F, Fh, Fl, (long long)nbu * bstride, c->stream);
+    LAUNCHCHK(c, "split kernel");
+  }
+  if (c->timing) (void)hipEventRecord(c->ev[5], c->stream);
+
+  unsigned int* bad = (unsigned int*)ctx_ws(c, "bad_flag", 256);
+  if (!bad) return ctx_fail(c, BS_ENOMEM, "workspace (flag)");
+  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned int), c->stream));
+
+  // ---- counts ----
+  int* d_tri = (int*)ctx_ws(c, "mabs_tri", tri_blk.size() * sizeof(int) + 16);
+  if (!d_tri) return ctx_fail(c, BS_ENOMEM, "workspace (triangles)");
+  HIPCHK(c, hipMemcpyAsync(d_tri, tri_blk.data(), tri_blk.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  int64_t* d_tperp = nullptr;
+  double* I64 = nullptr;
+  if (separable) {
+    // channel-independent count fields and n^4 sum_p I1 I2 I3 per triangle (cached per geometry)
+    uint64_t key = P.hash ^ 0x9e3779b97f4a7c15ULL;
+    std::vector<uint8_t> hm;
+    if (w && w->uv_mask) {
+      hm.resize((size_t)n * P.nh);
+      HIPCHK(c, hipMemcpyAsync(hm.data(), w->uv_mask, hm.size(), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      key = hash_bytes(key, hm.data(), hm.size());
+    }
+    key = hash_bytes(key, tri.data(), tri.size() * sizeof(int));
+    auto it = c->counts.find(key);
+    if (it == c->counts.end()) {
+      double* Ic = (double*)ctx_ws(c, "mabs_Iperp", (size_t)nbu * Ppix * 8);
+      double* Ts = (double*)ctx_ws(c, "mabs_Tsum", (size_t)ntri * 8 + 16);
+      if (!Ic || !Ts) return ctx_fail(c, BS_ENOMEM, "workspace (counts)");
+      bs_weights wu{nullptr, w ? w->uv_mask : nullptr, nullptr};
+      rc = run_ring_fields(c, b, nullptr, &wu, true, true, true, 1, blocks, Ic, Ppix);
+      if (rc) return rc;
+      launch_tperp(Ic, d_tri, ntri, Ppix, (double)Ppix * (double)Ppix, Ts, c->stream);
+      LAUNCHCHK(c, "count contraction");
+      CountCache cc;
+      cc.tri.assign(tri.begin(), tri.end());
+      if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
+      launch_round_counts(Ts, ntri, cc.d_counts, bad, c->stream);
+      LAUNCHCHK(c, "count rounding");
+      unsigned int hbad = 0;
+      HIPCHK(c, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (hbad) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "triangle count not an integer"); }
+      it = c->counts.emplace(key, std::move(cc)).first;
+    }
+    d_tperp = it->second.d_counts;
+  } else {
+    I64 = (double*)ctx_ws(c, "mabs_I64", (size_t)nbu * bstride * 8);
+    if (!I64) return ctx_fail(c, BS_ENOMEM, "workspace (count fields)");
+    rc = run_ring_fields(c, b, nullptr, w, true, true, false, nc, blocks, I64, bstride);
+    if (rc) return rc;
+  }
+
+  // ---- contraction + finalisation, batched over triangles to bound the workspace ----
+  int* d_nu1 = (int*)ctx_ws(c, "mabs_nu1", nu1.size() * sizeof(int) + 16);
+  if (!d_nu1) return ctx_fail(c, BS_ENOMEM, "workspace (nu1)");
+  HIPCHK(c, hipMemcpyAsync(d_nu1, nu1.data(), nu1.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  const long long nrows = (long long)n_nu1 * nc;
+  const size_t per_tri = (size_t)nrows * nc * 8;
+  // number of pixel chunks: enough blocks to fill the chip, chunks of >= 1024 pixels
+  const int tm = fp64 ? 64 : 128, tn = fp64 ? 64 : 128;
+  long long tiles_per_tri = ((nrows + tm - 1) / tm) * ((nc + tn - 1) / tn);
+  const size_t budget = (size_t)8 << 30;
+  int tb = (int)std::max<size_t>(1, std::min<size_t>(ntri, budget / std::max<size_t>(per_tri, 1)));
+  long long blocks_batch = tiles_per_tri * tb;
+  int kchunks = 1;
+  while (blocks_batch * kchunks < 2048 && Ppix / (kchunks * 2) >= 1024 && (Ppix / (kchunks * 2)) % 32 == 0) kchunks *= 2;
+  int kchunk = Ppix / kchunks;
+  // the batch must hold kchunks partial copies
+  tb = (int)std::max<size_t>(1, std::min<size_t>(ntri, budget / std::max<size_t>(per_tri * kchunks, 1)));
+  double* S = (double*)ctx_ws(c, "mabs_S", per_tri * kchunks * tb);
+  double* Sc = nullptr;
+  if (!separable) Sc = (double*)ctx_ws(c, "mabs_Sc", per_tri * kchunks * tb);
+  if (!S || (!separable && !Sc)) return ctx_fail(c, BS_ENOMEM, "workspace (partial sums)");
+  const int D = collapse == 1 ? 2 * nc - 1 : nc;
+  const size_t out_per_tri = collapse ? (size_t)D * D : (size_t)nrows * nc;
+  bool first_gemm = true;
+  for (int t0 = 0; t0 < ntri; t0 += tb) {
+    const int nt = std::min(tb, ntri - t0);
+    MabsGemmArgs g{};
+    g.F = fp64 ? nullptr : (const float*)F;
+    g.Fh = Fh; g.Fl = Fl;
+    g.F64 = fp64 ? (const double*)F : nullptr;
+    g.tri = d_tri + 3 * t0;
+    g.nu1 = d_nu1;
+    g.nc = nc; g.n_nu1 = n_nu1; g.P = Ppix; g.ntri = nt;
+    g.kchunk = kchunk; g.kchunks = kchunks;
+    g.bin_stride = bstride;
+    g.S = S;
+    if (c->timing && first_gemm) (void)hipEventRecord(c->ev[2], c->stream);
+    if (precision == BS_SPLIT_BF16) launch_mabs_gemm_split(g, c->stream);
+    else if (precision == BS_FP32) launch_mabs_gemm_f32(g, c->stream);
+    else launch_mabs_gemm_f64(g, c->stream);
+    LAUNCHCHK(c, "contraction kernel");
+    if (c->timing && t0 + nt >= ntri) (void)hipEventRecord(c->ev[3], c->stream);
+    first_gemm = false;
+    if (!separable) {
+      MabsGemmArgs gc = g;
+      gc.F = nullptr; gc.Fh = gc.Fl = nullptr;
+      gc.F64 = I64;
+      gc.S = Sc;
+      launch_mabs_gemm_f64(gc, c->stream);
+      LAUNCHCHK(c, "count contraction kernel");
+    }
+    if (!collapse) {
+      MabsFinalArgs f{};
+      f.S = S; f.kchunks = kchunks;
+      f.Sc = Sc; f.kchunks_c = kchunks;
+      f.Tperp = d_tperp ? d_tperp + t0 : nullptr;
+      f.chw = separable && w ? w->chan_w : nullptr;
+      f.nu1 = d_nu1;
+      f.nc = nc; f.n_nu1 = n_nu1; f.ntri = nt;
+      f.npix = (double)Ppix; f.norm = norm;
+      f.B = B + (size_t)t0 * out_per_tri;
+      f.N = N_tri + (size_t)t0 * out_per_tri;
+      f.bad = bad;
+      launch_mabs_finalize(f, c->stream);
+      LAUNCHCHK(c, "finalize kernel");
+    } else {
+      MabsCollapseArgs f{};
+      f.S = S; f.kchunks = kchunks;
+      f.Sc = Sc; f.kchunks_c = kchunks;
+      f.Tperp = d_tperp ? d_tperp + t0 : nullptr;
+      f.chw = separable && w ? w->chan_w : nullptr;
+      f.nc = nc; f.ntri = nt; f.circular = collapse == 2;
+      f.npix = (double)Ppix; f.norm = norm;
+      f.B = B + (size_t)t0 * out_per_tri;
+      f.N = N_tri + (size_t)t0 * out_per_tri;
+      f.Nnu = N_nu + (size_t)t0 * out_per_tri;
+      f.bad = bad;
+      launch_mabs_collapse(f, c->stream);
+      LAUNCHCHK(c, "collapse kernel");
+    }
+  }
+  if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
+  if (!separable) {
+    unsigned int hbad = 0;
+    HIPCHK(c, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (hbad) return ctx_fail(c, BS_ECOUNT, "triangle count not an integer");
+  }
+  return BS_OK;
+}

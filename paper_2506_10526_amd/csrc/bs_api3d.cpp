@@ -1,0 +1,300 @@
+// C ABI: 3D bispectrum (delay transform along frequency, |k| shells) and its fields.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bs_ctx.h"
+#include "bs_kernels.h"
+
+#define HIPCHK(ctx, call)                                                                         \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return ctx_fail(ctx, BS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define LAUNCHCHK(ctx, what)                                                                      \
+  do {                                                                                            \
+    hipError_t e_ = hipGetLastError();                                                            \
+    if (e_ != hipSuccess) return ctx_fail(ctx, BS_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+// Host-side description of the shell blocks a 3D call works on.
+struct Plan3 {
+  std::vector<int> blocks;        // shell id per block
+  std::vector<int> hj;            // largest |eta| per block
+  std::vector<long long> offT, offG;
+  long long totT = 0, totG = 0;
+  int H = 0;
+  std::vector<Work3> wv, wu, we;
+  int NLv = 16, NLu = 16, NLe = 16, NLd = 8;
+};
+
+const int kMaxFields = 32, kMaxPairs = 112;
+
+void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp64, Plan3& p) {
+  const int n = P.n, nub = 2 * P.vmax + 1;
+  const long long n2 = (long long)n * n;
+  p.blocks = blocks;
+  p.hj.clear(); p.offT.clear(); p.offG.clear();
+  p.wv.clear(); p.wu.clear(); p.we.clear();
+  p.totT = p.totG = 0;
+  p.H = 0;
+  p.NLe = fp64 ? 8 : 16;
+  if (P.nc >= 1024) p.NLe = fp64 ? 4 : 8;
+  p.NLd = (P.nc > 512) ? (fp64 ? 4 : 8) : (fp64 ? 8 : 16);
+  for (size_t j = 0; j < blocks.size(); ++j) {
+    int h = std::max(0, P.eta_hi[blocks[j]]);
+    p.hj.push_back(h);
+    p.H = std::max(p.H, h);
+    p.offT.push_back(p.totT);
+    p.offG.push_back(p.totG);
+    p.totT += (long long)(h + 1) * nub * n;
+    p.totG += (long long)(h + 1) * n2;
+    for (int e = 0; e <= h; ++e) {
+      for (int q0 = 0; q0 < nub; q0 += p.NLv) p.wv.push_back({(int)j, e, q0, 0});
+      for (int x0 = 0; x0 < n; x0 += p.NLu) p.wu.push_back({(int)j, e, x0, 0});
+    }
+    for (long long l0 = 0; l0 < n2; l0 += p.NLe) p.we.push_back({(int)j, 0, (int)l0, 0});
+  }
+}
+
+template <typename X>
+X* upload(bs_ctx* c, const char* name, const std::vector<X>& v, int& rc) {
+  X* d = (X*)ctx_ws(c, name, std::max<size_t>(v.size() * sizeof(X), 16));
+  if (!d) { rc = ctx_fail(c, BS_ENOMEM, std::string("workspace ") + name); return nullptr; }
+  if (!v.empty() && hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    rc = ctx_fail(c, BS_EHIP, std::string("upload ") + name);
+    return nullptr;
+  }
+  rc = BS_OK;
+  return d;
+}
+
+// Runs the field pipeline for `blocks`; fields land in `F` ([block][M n^2], type by fp64).
+// indicator: unit indicator of shell and support instead of data (no delay transform).
+int run_fields3(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64, bool indicator,
+                Plan3& p, void* F, const char* tag) {
+  const auto& P = b->P;
+  const int n = P.n, nc = P.nc, nh = P.nh, nub = 2 * P.vmax + 1, nvb = P.vmax + 1;
+  const size_t cz = fp64 ? 16 : 8;
+  int rc = BS_OK;
+  std::string t(tag);
+  Shell3Geom g{};
+  g.n = n; g.nh = nh; g.nc = nc; g.vmax = P.vmax; g.nub = nub; g.nvb = nvb;
+  g.H = p.H; g.smax = P.smax; g.S1 = P.smax + 1;
+  g.lut = b->d_lut;
+  g.uvm = w ? w->uv_mask : nullptr;
+  const void* tw_nc = ctx_twiddle(c, nc, fp64);
+  const void* tw_n = ctx_twiddle(c, n, fp64);
+  if (!tw_nc || !tw_n) return ctx_fail(c, BS_ENOMEM, "twiddle tables");
+  void* D = nullptr;
+  if (!indicator) {
+    D = ctx_ws(c, (t + "_D").c_str(), (size_t)(2 * p.H + 1) * nub * nvb * cz);
+    if (!D) return ctx_fail(c, BS_ENOMEM, "workspace (delay)");
+    Delay3Args d{};
+    d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = D; d.tw = tw_nc;
+    d.plan = make_fft_plan(nc); d.NL = p.NLd;
+    size_t lds = 2 * (size_t)p.NLd * (nc + 1) * cz;
+    if (fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
+    LAUNCHCHK(c, "delay transform");
+  }
+  void* Tm = ctx_ws(c, (t + "_T").c_str(), (size_t)p.totT * cz);
+  void* Gm = ctx_ws(c, (t + "_G").c_str(), (size_t)p.totG * cz);
+  if (!Tm || !Gm) return ctx_fail(c, BS_ENOMEM, "workspace (3D passes)");
+  int* d_shell = upload(c, (t + "_shell").c_str(), p.blocks, rc); if (rc) return rc;
+  int* d_hj = upload(c, (t + "_hj").c_str(), p.hj, rc); if (rc) return rc;
+  long long* d_offT = upload(c, (t + "_offT").c_str(), p.offT, rc); if (rc) return rc;
+  long long* d_offG = upload(c, (t + "_offG").c_str(), p.offG, rc); if (rc) return rc;
+  Work3* d_wv = upload(c, (t + "_wv").c_str(), p.wv, rc); if (rc) return rc;
+  Work3* d_wu = upload(c, (t + "_wu").c_str(), p.wu, rc); if (rc) return rc;
+  Work3* d_we = upload(c, (t + "_we").c_str(), p.we, rc); if (rc) return rc;
+  Pass3Args a{};
+  a.g = g; a.shell_of_block = d_shell; a.hj = d_hj;
+  // v pass
+  a.work = d_wv; a.off_in = nullptr; a.off_out = d_offT; a.in = D; a.out = Tm; a.tw = tw_n;
+  a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = indicator ? 1 : 0;
+  launch_vpass3(a, (int)p.wv.size(), fp64, c->stream, 2 * (size_t)p.NLv * n * cz);
+  LAUNCHCHK(c, "v pass");
+  // u pass
+  a.work = d_wu; a.off_in = d_offT; a.off_out = d_offG; a.in = Tm; a.out = Gm; a.NL = p.NLu;
+  launch_upass3(a, (int)p.wu.size(), fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
+  LAUNCHCHK(c, "u pass");
+  // eta pass (C2R), output length nc
+  const int M = nc;
+  if (M % 2) return ctx_fail(c, BS_EUNSUPPORTED, "3D fields need an even number of channels");
+  a.work = d_we; a.off_in = d_offG; a.off_out = nullptr; a.in = Gm; a.out = F;
+  a.tw = tw_nc; a.plan = make_fft_plan(M / 2); a.NL = p.NLe; a.M = M;
+  a.scale = 1.0 / ((double)M * (double)n * (double)n);
+  a.fstride = (long long)M * n * n;
+  launch_etapass3(a, (int)p.we.size(), fp64, c->stream, 2 * (size_t)p.NLe * (M / 2 + 1) * cz);
+  LAUNCHCHK(c, "eta pass");
+  return BS_OK;
+}
+
+int check_3d_inputs(bs_ctx* c, const bs_bins* b, const bs_weights* w) {
+  if (b->P.kind != BS_SHELL_K) return ctx_fail(c, BS_EINVAL, "3D estimator needs BS_SHELL_K bins");
+  if (w && w->ng) return ctx_fail(c, BS_EUNSUPPORTED, "3D estimator needs separable weights (uv_mask, chan_w)");
+  if (!fft_len_ok(b->P.nc) || (b->P.nc % 2)) return ctx_fail(c, BS_EUNSUPPORTED, "nc must be even and 2^a 3^b");
+  return BS_OK;
+}
+
+uint64_t hash_bytes3(uint64_t h, const void* p, size_t n) {
+  const unsigned char* q = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) { h ^= q[i]; h *= 1099511628211ULL; }
+  return h;
+}
+
+}  // namespace
+
+int filter_fields_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, int32_t precision,
+                     void* fields, double* count_fields) {
+  int rc = check_3d_inputs(c, b, w);
+  if (rc) return rc;
+  const auto& P = b->P;
+  const bool fp64 = precision == BS_FP64;
+  const long long fst = (long long)P.nc * P.n * P.n;
+  std::vector<int> blocks;
+  for (int j = 0; j < P.nbins; ++j) if (P.modes[j] > 0) blocks.push_back(j);
+  // fields of empty shells are zero; non-empty ones are written block by block
+  for (int pass = 0; pass < 2; ++pass) {
+    void* out = pass == 0 ? fields : (void*)count_fields;
+    if (!out) continue;
+    bool f64 = pass == 1 ? true : fp64;
+    size_t esz = f64 ? 8 : 4;
+    HIPCHK(c, hipMemsetAsync(out, 0, (size_t)P.nbins * fst * esz, c->stream));
+    if (pass == 0 && !vis) return ctx_fail(c, BS_EINVAL, "vis is NULL");
+    for (int j : blocks) {
+      Plan3 p;
+      build_plan3(P, std::vector<int>{j}, f64, p);
+      void* dst = (char*)out + (size_t)j * fst * esz;
+      rc = run_fields3(c, b, vis, w, f64, pass == 1, p, dst, pass == 0 ? "ff3" : "ff3c");
+      if (rc) return rc;
+    }
+  }
+  return BS_OK;
+}
+
+extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, int32_t precision,
+                              double norm, double* B, int64_t* N_tri, double* N_eff) {
+  if (!c || !b || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_estimate_3d: NULL context or host-only bins");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  int rc = check_3d_inputs(c, b, w);
+  if (rc) return rc;
+  if (!vis || !B || !N_tri) return ctx_fail(c, BS_EINVAL, "vis, B and N_tri must be non-NULL");
+  if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
+  const auto& P = b->P;
+  const int ntri = (int)(P.tri.size() / 3);
+  if (ntri == 0) return BS_OK;
+  const bool fp64 = precision == BS_FP64;
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  // ---- blocks, pairs, triangle -> (pair, column) ----
+  std::map<int, int> blk;
+  for (int x : P.tri) blk.emplace(x, 0);
+  std::vector<int> blocks;
+  for (auto& kv : blk) { kv.second = (int)blocks.size(); blocks.push_back(kv.first); }
+  if ((int)blocks.size() > kMaxFields) return ctx_fail(c, BS_EUNSUPPORTED, "more than 32 shells in use");
+  std::map<std::pair<int, int>, int> pr;
+  std::vector<int> pairs, tpair(ntri), tcol(ntri);
+  for (int t = 0; t < ntri; ++t) {
+    int a = blk[P.tri[3 * t]], bb = blk[P.tri[3 * t + 1]];
+    auto key = std::make_pair(a, bb);
+    auto it = pr.find(key);
+    if (it == pr.end()) {
+      it = pr.emplace(key, (int)(pairs.size() / 2)).first;
+      pairs.push_back(a); pairs.push_back(bb);
+    }
+    tpair[t] = it->second;
+    tcol[t] = blk[P.tri[3 * t + 2]];
+  }
+  const int npairs = (int)(pairs.size() / 2);
+  if (npairs > kMaxPairs) return ctx_fail(c, BS_EUNSUPPORTED, "more than 112 shell pairs in use");
+  const long long nvox = (long long)P.nc * P.n * P.n;
+  int* d_pairs = upload(c, "c3_pairs", pairs, rc); if (rc) return rc;
+  int* d_tp = upload(c, "c3_tpair", tpair, rc); if (rc) return rc;
+  int* d_tc = upload(c, "c3_tcol", tcol, rc); if (rc) return rc;
+  long long nblk = std::min<long long>(2048, (nvox + 127) / 128);
+  long long chunk = ((nvox + nblk - 1) / nblk + 127) / 128 * 128;
+  nblk = (nvox + chunk - 1) / chunk;
+  double* partial = (double*)ctx_ws(c, "c3_partial", (size_t)nblk * 112 * 32 * 8);
+  if (!partial) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
+  double rho3 = 1.0;
+  if (w && w->chan_w) {
+    std::vector<float> hw(P.nc);
+    HIPCHK(c, hipMemcpyAsync(hw.data(), w->chan_w, P.nc * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0;
+    for (float x : hw) s += (double)x * x * x;
+    rho3 = s / P.nc;
+  }
+  // ---- counts (FP64, cached per geometry and uv support) ----
+  uint64_t key = P.hash ^ 0x3d3d3d3d3d3d3d3dULL;
+  if (w && w->uv_mask) {
+    std::vector<uint8_t> hm((size_t)P.n * P.nh);
+    HIPCHK(c, hipMemcpyAsync(hm.data(), w->uv_mask, hm.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    key = hash_bytes3(key, hm.data(), hm.size());
+  }
+  auto it = c->counts.find(key);
+  if (it == c->counts.end()) {
+    Plan3 pc;
+    build_plan3(P, blocks, true, pc);
+    void* F64 = ctx_ws(c, "c3_F64", (size_t)blocks.size() * nvox * 8);
+    if (!F64) return ctx_fail(c, BS_ENOMEM, "workspace (count fields)");
+    rc = run_fields3(c, b, nullptr, w, true, true, pc, F64, "c3c");
+    if (rc) return rc;
+    Con3Args ca{};
+    ca.F = F64; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
+    ca.chunk = chunk; ca.partial = partial;
+    launch_contract3(ca, 0, (int)nblk, c->stream);
+    LAUNCHCHK(c, "count contraction");
+    double* Ssum = (double*)ctx_ws(c, "c3_Ssum", (size_t)ntri * 8 + 16);
+    unsigned int* bad = (unsigned int*)ctx_ws(c, "bad_flag", 256);
+    if (!Ssum || !bad) return ctx_fail(c, BS_ENOMEM, "workspace (count sums)");
+    Fin3Args f{};
+    f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
+    f.T3D = nullptr; f.Ssum = Ssum; f.sfac = (double)nvox * (double)nvox;
+    launch_fin3(f, c->stream);
+    LAUNCHCHK(c, "count finalize");
+    CountCache cc;
+    if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
+    HIPCHK(c, hipMemsetAsync(bad, 0, 4, c->stream));
+    launch_round_counts(Ssum, ntri, cc.d_counts, bad, c->stream);
+    LAUNCHCHK(c, "count rounding");
+    unsigned int hbad = 0;
+    HIPCHK(c, hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (hbad) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "3D triangle count not an integer"); }
+    cc.tri.assign(P.tri.begin(), P.tri.end());
+    it = c->counts.emplace(key, std::move(cc)).first;
+    if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  }
+  // ---- data fields ----
+  Plan3 pd;
+  build_plan3(P, blocks, fp64, pd);
+  void* F = ctx_ws(c, "c3_F", (size_t)blocks.size() * nvox * (fp64 ? 8 : 4));
+  if (!F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
+  rc = run_fields3(c, b, vis, w, fp64, false, pd, F, "c3d");
+  if (rc) return rc;
+  if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  Con3Args ca{};
+  ca.F = F; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
+  ca.chunk = chunk; ca.partial = partial;
+  launch_contract3(ca, fp64 ? 0 : (precision == BS_FP32 ? 1 : 2), (int)nblk, c->stream);
+  LAUNCHCHK(c, "contraction");
+  if (c->timing) (void)hipEventRecord(c->ev[3], c->stream);
+  Fin3Args f{};
+  f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
+  f.T3D = it->second.d_counts; f.rho3 = rho3; f.nvox = (double)nvox; f.norm = norm; f.sfac = 1.0;
+  f.B = B; f.N = N_tri; f.Neff = N_eff;
+  launch_fin3(f, c->stream);
+  LAUNCHCHK(c, "finalize");
+  if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
+  return BS_OK;
+}

@@ -1,0 +1,49 @@
+// Internal context and plan objects behind the opaque handles of bs.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bs.h"
+#include "bs_plan.h"
+#include "fft_lds.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct CountCache {
+  std::vector<int32_t> tri;       // triangle list the counts were made for
+  int64_t* d_counts = nullptr;    // device int64 per triangle
+  std::vector<int64_t> h_counts;  // host copy
+};
+
+struct bs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, DevBuf> ws;      // grow-only workspace slots
+  std::map<int, void*> tw32, tw64;        // twiddle tables exp(-2 pi i m / L), by L
+  std::map<uint64_t, CountCache> counts;  // geometry-keyed count caches
+  bool timing = false;
+  hipEvent_t ev[8] = {};
+  double last_ms[4] = {0, 0, 0, 0};
+  bool have_timing = false;
+};
+
+struct bs_bins {
+  bs_ctx* ctx = nullptr;
+  bsplan::Plan P;
+  int8_t* d_lut = nullptr;
+};
+
+// ---- helpers implemented in bs_api.cpp ----
+int ctx_fail(bs_ctx* c, int code, const std::string& msg);
+void* ctx_ws(bs_ctx* c, const char* name, size_t bytes);       // grow-only; NULL on failure
+const void* ctx_twiddle(bs_ctx* c, int L, bool fp64);          // NULL on failure
+FftPlan make_fft_plan(int L);
+bool fft_len_ok(int L);

@@ -1,0 +1,153 @@
+// Kernel argument blocks and launch wrappers shared between the C ABI layer and the
+// HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fft_lds.h"
+
+// ---------------------------------------------------------------- ring fields
+struct MabsFieldArgs {
+  const void* vis;          // complex64 (T=float) or complex128 (T=double), [nc][n][nh]
+  const uint16_t* ng;       // per-cell counts or NULL
+  const uint8_t* uvm;       // separable occupancy or NULL
+  const float* chw;         // separable channel weights or NULL
+  const int8_t* lut;        // ring of s = qu^2 + qv^2, s <= smax
+  int smax;
+  const int* bins;          // ring id per z block
+  int n, nh, nc, vmax, G, CB, RB;
+  int count_mode;           // 0: W V, 1: unit indicator [N_g > 0]
+  int chan_offset;          // first channel of this launch (grid.y indexes channels from here)
+  int ignore_chan;          // count mode, separable: channel-independent indicator
+  void* out;                // T fields
+  long long plane_stride;   // n*n
+  long long bin_stride;     // between ring blocks
+  const void* tw_n;         // Cx<T> exp(-2 pi i m / n), m < n
+  FftPlan pcol;             // length n / G
+  FftPlan prow;             // length n / 2
+  double scale;             // 1 / n^2
+};
+
+// ------------------------------------------------------------- contractions
+struct MabsGemmArgs {
+  const float* F;           // FP32 fields [nb][nc][P]
+  const uint16_t* Fh;       // bf16 hi parts (bit patterns), same layout
+  const uint16_t* Fl;       // bf16 lo parts
+  const double* F64;        // FP64 fields
+  const int* tri;           // [ntri][3] ring-block indices (b1, b2, b3)
+  const int* nu1;           // selected nu1 channels [n_nu1]
+  int nc, n_nu1, P, ntri;
+  int kchunk, kchunks;      // pixels per chunk, number of chunks
+  long long bin_stride;     // nc * P
+  double* S;                // [kchunks][ntri][n_nu1*nc][nc]
+};
+
+struct MabsFinalArgs {
+  const double* S;          // data sums [kchunks][ntri][rows][nc]
+  int kchunks;
+  const double* Sc;         // count sums (general N_g), same layout, or NULL
+  int kchunks_c;
+  const int64_t* Tperp;     // separable: n^4-scaled count per triangle [ntri]
+  const float* chw;         // separable channel weights (NULL = all ones)
+  const int* nu1;           // [n_nu1]
+  int nc, n_nu1, ntri;
+  double npix, norm;
+  double* B;                // [ntri][n_nu1][nc][nc]
+  int64_t* N;
+  unsigned int* bad;        // set to 1 when a count is not within 1e-3 of an integer
+};
+
+struct MabsCollapseArgs {
+  const double* S; int kchunks;
+  const double* Sc; int kchunks_c;
+  const int64_t* Tperp; const float* chw;
+  int nc, ntri, circular;
+  double npix, norm;
+  double* B;  int64_t* N;  int32_t* Nnu;   // [ntri][D][D]
+  unsigned int* bad;
+};
+
+void launch_mabs_fields_f32(const MabsFieldArgs& a, int nbins, int nchan, size_t lds, hipStream_t s);
+void launch_mabs_fields_f64(const MabsFieldArgs& a, int nbins, int nchan, size_t lds, hipStream_t s);
+void launch_split_bf16(const float* F, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s);
+void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s);
+void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s);
+void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s);
+// Tsum[t] = npix^2 * sum_p I_b1 I_b2 I_b3 over channel-independent FP64 count fields [nb][P].
+void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s);
+void launch_round_counts(const double* x, int n, int64_t* out, unsigned int* bad, hipStream_t s);
+void launch_mabs_finalize(const MabsFinalArgs& a, hipStream_t s);
+void launch_mabs_collapse(const MabsCollapseArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------ 3D path
+// Shell geometry shared by the 3D kernels.  The uv support box is qu in [-vmax, vmax],
+// qv in [0, vmax] (stored half plane) -> nub = 2 vmax + 1, nvb = vmax + 1.
+struct Shell3Geom {
+  int n, nh, nc, vmax, nub, nvb;
+  int H;                    // delay planes stored: eta in [-H, H]
+  int smax, S1;             // LUT row length S1 = smax + 1
+  const int8_t* lut;        // shell of (|eta|, s)
+  const uint8_t* uvm;       // uv occupancy [n][nh] or NULL
+};
+
+struct Delay3Args {
+  Shell3Geom g;
+  const void* vis;          // [nc][n][nh] complex (T)
+  const float* chw;         // [nc] or NULL
+  void* out;                // [2H+1][nub][nvb] complex (T)
+  const void* tw;           // exp(-2 pi i m / nc)
+  FftPlan plan;             // length nc
+  int NL;                   // lines (consecutive qv) per block
+};
+
+// One work item = (shell block j, eta, start index) for the v and u passes, and
+// (shell block j, start line) for the eta pass.
+struct Work3 {
+  int j, eta, start, pad;
+};
+
+struct Pass3Args {
+  Shell3Geom g;
+  const int* shell_of_block;   // shell id per block
+  const Work3* work;
+  const long long* off_in;     // per block element offset of the pass input
+  const long long* off_out;    // per block element offset of the pass output
+  const int* hj;               // per block: largest |eta| stored (H_j)
+  const void* in;              // complex (T)
+  void* out;                   // complex (T) or real (T) for the eta pass
+  const void* tw;              // exp(-2 pi i m / L) for the pass length L
+  FftPlan plan;
+  int NL;
+  int indicator;               // v pass: 1 = unit indicator of shell and support, 0 = data
+  int M;                       // eta pass: output length along eta
+  double scale;                // eta pass: overall 1 / (M n^2)
+  long long fstride;           // eta pass: elements per output field (M n^2)
+};
+
+struct Con3Args {
+  const void* F;               // fields [nbu][vox] (T)
+  long long vox;               // voxels per field
+  int nbu;                     // fields (<= 32)
+  const int* pairs;            // [npairs][2] field blocks (a, b)
+  int npairs;                  // <= 112
+  long long chunk;             // voxels per block (multiple of 128)
+  double* partial;             // [gridDim.x][112][32]
+};
+
+struct Fin3Args {
+  const double* partial; int nparts;  // reduce over parts
+  const int* tri_pair; const int* tri_col;  // per triangle
+  int ntri;
+  const int64_t* T3D;          // counts (NULL when computing counts)
+  double* Ssum;                // [ntri] output sums (count pass) or NULL
+  double rho3, nvox, norm, sfac;
+  double* B; int64_t* N; double* Neff;
+};
+
+void launch_delay3_f32(const Delay3Args& a, hipStream_t s, size_t lds);
+void launch_delay3_f64(const Delay3Args& a, hipStream_t s, size_t lds);
+void launch_vpass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds);
+void launch_upass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds);
+void launch_etapass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds);
+void launch_contract3(const Con3Args& a, int mode, int nblocks, hipStream_t s);  // mode: 0 FP64, 1 FP32, 2 split
+void launch_fin3(const Fin3Args& a, hipStream_t s);

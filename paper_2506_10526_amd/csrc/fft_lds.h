@@ -1,0 +1,167 @@
+// LDS-staged mixed-radix Stockham FFT for gfx950 work-groups.
+//
+// A work-group transforms `nl` lines of length L that sit contiguously in LDS
+// (line i at a + i*L).  Each radix-R pass reads from one LDS buffer and writes
+// the self-sorting (Stockham) permutation into the other, so no bit reversal
+// is needed.  Twiddles come from a float64-accurate table exp(-2 pi i m / Lt)
+// held in global memory (L2-resident); the L-point transform reads entry
+// m * (Lt / L).  Radices 2, 3, 4 and 8 cover every length 2^a 3^b used by the
+// estimator (uv grids 64..1024, channel axes up to 1536).
+//
+// Conventions: SIGN = -1 computes X[q] = sum_r x[r] exp(-2 pi i r q / L)
+// (forward), SIGN = +1 the unnormalised inverse.
+#pragma once
+#include <hip/hip_runtime.h>
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmk(T x, T y) { Cx<T> r; r.x = x; r.y = y; return r; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) { return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename T>
+__device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return cmk(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return cmk(a.x * s, a.y * s); }
+// multiply by SIGN * i
+template <int SIGN, typename T>
+__device__ __forceinline__ Cx<T> cmul_si(Cx<T> a) { return SIGN > 0 ? cmk(-a.y, a.x) : cmk(a.y, -a.x); }
+
+struct FftPlan {
+  int L;        // transform length
+  int nr;       // number of radix passes
+  int rad[14];  // radices, product == L
+};
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft2(Cx<T>* v) {
+  Cx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft3(Cx<T>* v) {
+  const T c = T(-0.5);
+  const T s = T(SIGN) * T(0.86602540378443864676);  // sin(2 pi / 3)
+  Cx<T> t1 = cadd(v[1], v[2]);
+  Cx<T> t2 = csub(v[1], v[2]);
+  Cx<T> m = cadd(v[0], cscale(t1, c));
+  Cx<T> is = cmk(-s * t2.y, s * t2.x);  // i * s * t2
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(m, is);
+  v[2] = csub(m, is);
+}
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft4(Cx<T>* v) {
+  Cx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  Cx<T> c = cadd(v[1], v[3]), d = cmul_si<SIGN>(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft8(Cx<T>* v) {
+  const T h = T(0.70710678118654752440);
+  Cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  Cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<SIGN>(e);
+  dft4<SIGN>(o);
+  // w^q = exp(SIGN 2 pi i q / 8), q = 0..3
+  Cx<T> w1 = cmk(h, T(SIGN) * h);
+  Cx<T> w3 = cmk(-h, T(SIGN) * h);
+  Cx<T> t0 = o[0];
+  Cx<T> t1 = cmul(o[1], w1);
+  Cx<T> t2 = cmul_si<SIGN>(o[2]);
+  Cx<T> t3 = cmul(o[3], w3);
+  v[0] = cadd(e[0], t0); v[4] = csub(e[0], t0);
+  v[1] = cadd(e[1], t1); v[5] = csub(e[1], t1);
+  v[2] = cadd(e[2], t2); v[6] = csub(e[2], t2);
+  v[3] = cadd(e[3], t3); v[7] = csub(e[3], t3);
+}
+
+// One Stockham pass of radix R over nl lines, butterflies spread over the work-group.
+template <int SIGN, int R, typename T>
+__device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<T>* __restrict__ dst, int L,
+                                              int Ns, int nl, int ld, const Cx<T>* __restrict__ tw, int tws) {
+  const int nbf = L / R;
+  const int total = nl * nbf;
+  const int tstep = (L / (Ns * R)) * tws;  // table stride of the unit angle 2 pi / (Ns R)
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int line = t / nbf;
+    int j = t - line * nbf;
+    const Cx<T>* in = src + (size_t)line * ld;
+    Cx<T>* out = dst + (size_t)line * ld;
+    int k = j % Ns;
+    Cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[j + r * nbf];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        Cx<T> w = tw[k * r * tstep];
+        if (SIGN > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    if (R == 2) dft2<SIGN>(v);
+    else if (R == 3) dft3<SIGN>(v);
+    else if (R == 4) dft4<SIGN>(v);
+    else dft8<SIGN>(v);
+    int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+  }
+}
+
+// Transform nl lines held in `a` (line i at a + i*ld, ld >= L; ld = L when omitted).
+// `b` is scratch of the same size.  Returns the buffer holding the result (a or b).
+// Ends with a barrier.
+template <int SIGN, typename T>
+__device__ Cx<T>* lds_fft(Cx<T>* a, Cx<T>* b, const FftPlan& p, int nl, const Cx<T>* __restrict__ tw, int tws,
+                          int ld = 0) {
+  if (ld <= 0) ld = p.L;
+  int Ns = 1;
+  Cx<T>* src = a;
+  Cx<T>* dst = b;
+  for (int s = 0; s < p.nr; ++s) {
+    int R = p.rad[s];
+    if (R == 8) stockham_pass<SIGN, 8>(src, dst, p.L, Ns, nl, ld, tw, tws);
+    else if (R == 4) stockham_pass<SIGN, 4>(src, dst, p.L, Ns, nl, ld, tw, tws);
+    else if (R == 3) stockham_pass<SIGN, 3>(src, dst, p.L, Ns, nl, ld, tw, tws);
+    else stockham_pass<SIGN, 2>(src, dst, p.L, Ns, nl, ld, tw, tws);
+    __syncthreads();
+    Cx<T>* t = src; src = dst; dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// Pack a Hermitian half spectrum H[0..M] (M = L/2, values read through `get`) into the
+// M-point complex sequence Z whose inverse DFT z gives the real inverse transform
+// x[2m] = Re z[m], x[2m+1] = Im z[m] of length L:
+//   Z[k] = (H[k] + conj H[M-k]) + i e^{+2 pi i k / L} (H[k] - conj H[M-k]),
+// with the imaginary parts of H[0] and H[M] dropped (the self-conjugate terms).
+// twL is the table exp(-2 pi i m / (L * twsL)).
+template <typename T, typename Get>
+__device__ __forceinline__ Cx<T> c2r_pack(int k, int M, Get get, const Cx<T>* __restrict__ twL, int twsL) {
+  Cx<T> hk = get(k);
+  Cx<T> hm = get(M - k);
+  if (k == 0) { hk.y = T(0); hm.y = T(0); }
+  Cx<T> e = cadd(hk, cconj(hm));
+  Cx<T> d = csub(hk, cconj(hm));
+  Cx<T> w = twL[k * twsL];
+  w.y = -w.y;  // e^{+2 pi i k / L}
+  Cx<T> o = cmul(d, w);
+  return cmk(e.x - o.y, e.y + o.x);  // e + i o
+}
