@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark: 3D bispectrum of an MWA-shaped cube on one MI355X.
+
+Workload (the metric's configuration): 256 x 256 uv x 768 channels of 40 kHz (30.72 MHz
+band), quadratic non-Gaussian field delta = g + 0.5 (g^2 - <g^2>) with P(k) ~ k^-2,
+20 log |k| shells over 0.003 - 1.258 Mpc^-1 and every candidate triangle k1 >= k2 >= k3
+(483).  One step = one bs_estimate_3d call on a cube already resident in HBM: delay
+transform, shell-filtered 3D inverse transforms, the triple-product contraction and the
+normalisation (triangle counts depend only on the geometry and are cached after the
+first call).  The metric counts one product per valid triangle per voxel.
+
+Also reported on the same cube: the plain FP32 path of the same step, and the MABS
+contraction on MFMA for 133 ring triples x 8 nu1 rows (768 x 768 x 65536 GEMMs).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mabs]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--seed", type=int, default=1)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-mabs", action="store_true")
+    p.add_argument("--no-fp32", action="store_true")
+    return p.parse_args()
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, V, edges, gpu_B, tri_all):
+    """The FP64 oracle on a bounded sample of the same workload: the delay transform, the
+    fields of the three largest shells and every candidate triangle among them.  The full-
+    workload time is extrapolated from the per-field and per-triangle times."""
+    import threading
+    from oracle import bins as ob
+    from oracle import estimator as oe
+    b = ob.make_bins(ob.SHELL_K, w.n, w.nc, edges, du=w.du, r_mpc=w.r_mpc, rprime=w.rprime, dnu=w.dnu)
+    t0 = time.perf_counter()
+    sf = oe.ShellFields(b, V.astype(np.complex128))
+    t_delay = time.perf_counter() - t0
+    shells = [17, 18, 19]
+    t0 = time.perf_counter()
+    for j in shells:
+        sf.data(j)
+    t_field = (time.perf_counter() - t0) / len(shells)
+    sel = [i for i, t in enumerate(b.triangles) if all(x in shells for x in t)]
+    t0 = time.perf_counter()
+    S = np.array([np.sum(sf.data(b.triangles[i][0]) * sf.data(b.triangles[i][1]) * sf.data(b.triangles[i][2]))
+                  for i in sel])
+    t_tri = (time.perf_counter() - t0) / max(len(sel), 1)
+    for j in shells:
+        sf.count(j)
+    SI = np.array([np.sum(sf.count(b.triangles[i][0]) * sf.count(b.triangles[i][1]) * sf.count(b.triangles[i][2]))
+                   for i in sel])
+    nvox = w.nc * w.n * w.n
+    T = np.rint(float(nvox) ** 2 * SI)
+    Bref = np.where(T > 0, nvox * S / np.maximum(T, 1), np.nan)
+    err = np.abs(gpu_B[sel] - Bref) / np.abs(Bref)
+    n_valid = int(np.count_nonzero(T)) if len(sel) else 0
+    t_full = t_delay + 20 * t_field + len(tri_all) * t_tri
+    products_full = len(tri_all) * nvox
+    return {
+        "value": products_full / t_full,
+        "unit": "products/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"float64 NumPy oracle (single thread) on the same cube: delay transform ({t_delay:.1f} s), "
+                   f"3 of 20 shell fields ({t_field:.1f} s each), {len(sel)} of {len(tri_all)} triangles "
+                   f"({t_tri:.2f} s each); full step extrapolated as delay + 20 fields + all triangles "
+                   f"= {t_full:.0f} s, counts excluded as on the GPU"),
+        "max_rel_err_vs_gpu_on_sample": float(np.nanmax(err)) if len(sel) else None,
+        "sample_valid_triangles": n_valid,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2506_10526_amd import bs, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = synth.config2()
+    edges = w.shell_edges(20)
+    log(f"[bench] generating {w.n}x{w.n}x{w.nc} cube (seed {args.seed})")
+    V = synth.make_cube(w, seed=args.seed, dtype=np.complex64)
+    Vd = torch.from_numpy(V).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = bs.bs_create(0, stream.cuda_stream)
+    bins, ncand = bs.bs_make_bins(ctx, bs.BS_SHELL_K, w.n, w.nc, edges, du_lambda=w.du, r_mpc=w.r_mpc,
+                                  rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    tri, modes = bs.bs_bins_triangles(bins, ncand, 20)
+    B = torch.empty(ncand, dtype=torch.float64, device=dev)
+    N = torch.empty(ncand, dtype=torch.int64, device=dev)
+    nvox = w.nc * w.n * w.n
+    bs.bs_set_timing(ctx, True)
+
+    def step(prec):
+        return lambda: bs.bs_estimate_3d(ctx, bins, Vd, prec, B, N)
+
+    log("[bench] 3D split-BF16: warmup + timed steps")
+    t_split = time_steps(step(bs.BS_SPLIT_BF16), args.steps, args.warmup, torch)
+    tim_split = bs.bs_last_timing(ctx)
+    Bs = B.cpu().numpy().copy()
+    Nt = N.cpu().numpy().copy()
+    count_dev = bs.bs_last_count_dev(ctx)
+    log(f"[bench] triangle counts: max |x - rint(x)| = {count_dev:.3e}, max count {Nt.max():.3e}")
+    n_valid = int(np.count_nonzero(Nt))
+    products = n_valid * nvox
+    log(f"[bench] split: {t_split * 1e3:.3f} ms/step, kernels total {tim_split[0]:.3f} contraction {tim_split[1]:.3f} "
+        f"fields {tim_split[2]:.3f} ms")
+    fp32 = None
+    if not args.no_fp32:
+        log("[bench] 3D FP32: timed steps")
+        t32 = time_steps(step(bs.BS_FP32), max(3, args.steps // 2), 1, torch)
+        tim32 = bs.bs_last_timing(ctx)
+        B32 = B.cpu().numpy()
+        ok = Nt > 0
+        fp32 = {"value": products / t32, "ms_per_step": t32 * 1e3, "contraction_ms": tim32[1],
+                "split_over_fp32": t32 / t_split,
+                "max_abs_diff_split_vs_fp32_over_max_B": float(np.max(np.abs(Bs[ok] - B32[ok])) / np.max(np.abs(B32[ok])))}
+        log(f"[bench] fp32: {t32 * 1e3:.3f} ms/step, contraction {tim32[1]:.3f} ms")
+    # dominant kernel of the split step: the contraction (reads every shell field once)
+    nbu = len(np.unique(tri))
+    con_bytes = nbu * nvox * 4.0
+    con_ms = tim_split[1]
+    fld_ms = tim_split[2]
+    if con_ms >= fld_ms:
+        roof = {"bound": "hbm", "kernel": "k3_contract<split-bf16>", "achieved": con_bytes / (con_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                "algorithmic_bytes": con_bytes, "avg_ms": con_ms}
+    else:
+        roof = {"bound": "hbm", "kernel": "3D field transforms", "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "traffic": None, "avg_ms": fld_ms}
+    if roof.get("achieved") is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    mabs = None
+    if not args.no_mabs:
+        log("[bench] MABS contraction: 133 ring triples x 8 nu1 rows")
+        redges = w.shell_edges(20) / (2 * np.pi * w.du / w.r_mpc)
+        rb, rcand = bs.bs_make_bins(ctx, bs.BS_RING_U, w.n, w.nc, redges)
+        nu1 = list(range(0, w.nc, 96))
+        Bm = torch.empty((rcand, len(nu1), w.nc, w.nc), dtype=torch.float64, device=dev)
+        Nm = torch.empty((rcand, len(nu1), w.nc, w.nc), dtype=torch.int64, device=dev)
+        res = {}
+        for name, prec in (("split_bf16", bs.BS_SPLIT_BF16), ("fp32", bs.BS_FP32)):
+            f = lambda: bs.bs_estimate_mabs(ctx, rb, Vd, prec, Bm, Nm, nu1=nu1)
+            tt = time_steps(f, 2, 1, torch)
+            tm = bs.bs_last_timing(ctx)
+            nval = int(torch.count_nonzero(Nm).item())
+            prods = nval * w.n * w.n
+            macs = 3 if prec == bs.BS_SPLIT_BF16 else 1
+            flops = 2.0 * macs * rcand * len(nu1) * w.nc * w.nc * w.n * w.n
+            peak = BF16_PEAK_TFLOPS if prec == bs.BS_SPLIT_BF16 else FP32_MFMA_PEAK_TFLOPS
+            ach = flops / (tm[1] * 1e-3) / 1e12
+            res[name] = {"value": prods / tt, "unit": "products/s", "ms_per_call": tt * 1e3,
+                         "contraction_ms": tm[1], "products": prods,
+                         "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                                      "frac": ach / peak, "mfma_flops_per_launch": flops}}
+            log(f"[bench] mabs {name}: {tt * 1e3:.1f} ms/call, contraction {tm[1]:.1f} ms, {ach:.0f} TFLOP/s")
+        res["split_over_fp32"] = res["fp32"]["contraction_ms"] / res["split_bf16"]["contraction_ms"]
+        res["workload"] = "133 ring triples (10 rings, k_perp of the 20 shells) x nu1 in {0,96,...,672} x all (nu2, nu3)"
+        mabs = res
+        bs.bs_free_bins(rb)
+        del Bm, Nm
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline(w, V, edges, Bs, tri)
+    out = {
+        "metric": "bin-triangle·voxel products/s, split-BF16 MFMA vs FP32 at ≤1e-4 rel err",
+        "value": products / t_split,
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_split * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, split-bf16 MFMA contraction, f64 sums",
+        "data": "synthetic",
+        "config": {"workload": "3D BS, 256x256 uv x 768 ch (40 kHz), quadratic field f=0.5, 20 log k-shells "
+                               "0.003-1.258 Mpc^-1, all k1>=k2>=k3 candidates",
+                   "triangles_candidate": int(ncand), "triangles_valid": n_valid, "voxels": nvox,
+                   "products_per_step": products, "parallelism": "single GPU",
+                   "count_max_dev_from_integer": count_dev},
+        "roofline": roof,
+        "kernel_ms": {"step_events": tim_split[0], "contraction": tim_split[1], "fields": tim_split[2]},
+        "fp32": fp32,
+        "mabs": mabs,
+        "cpu_baseline": cpu,
+    }
+    bs.bs_free_bins(bins)
+    bs.bs_destroy(ctx)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

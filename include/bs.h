@@ -42,7 +42,7 @@ extern "C" {
 #define BS_EINVAL (-1)        /* bad argument: shapes, edges, pointers, unsupported combination of inputs */
 #define BS_ENOMEM (-2)        /* device allocation failed */
 #define BS_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
-#define BS_ECOUNT (-4)        /* an FP64 triangle count was not within 1e-3 of an integer */
+#define BS_ECOUNT (-4)        /* an FP64 triangle count was farther than 0.25 from an integer */
 #define BS_EUNSUPPORTED (-5)  /* valid request this build does not implement (e.g. 3D with per-cell N_g) */
 
 typedef struct bs_ctx bs_ctx;
@@ -172,6 +172,10 @@ int bs_estimate_3d(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_w
  * [2] = fields/FFT kernels.  Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
 int bs_set_timing(bs_ctx* ctx, int32_t enable);
 int bs_last_timing(const bs_ctx* ctx, double* out_ms_host, int32_t n);
+/* Largest |x - rint(x)| over the FP64 triangle counts x of the last estimate (or of the cached
+ * counts it used).  Counts are rounded only when this is <= 0.25, else the call fails with
+ * BS_ECOUNT. */
+int bs_last_count_dev(const bs_ctx* ctx, double* dev_host);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
     "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_estimate_3d",
-    "bs_set_timing", "bs_last_timing",
+    "bs_set_timing", "bs_last_timing", "bs_last_count_dev",
 ]
 
 
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
     L.bs_estimate_3d.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, dbl, vp, vp, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
+    L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
     for name in EXPORTED:
         if name not in ("bs_destroy", "bs_last_error", "bs_free_bins"):
             getattr(L, name).restype = ctypes.c_int
@@ -196,3 +197,9 @@ def bs_last_timing(ctx: int):
     out = (ctypes.c_double * 3)()
     _check(ctx, lib().bs_last_timing(ctx, out, 3))
     return list(out)
+
+
+def bs_last_count_dev(ctx: int) -> float:
+    d = ctypes.c_double()
+    _check(ctx, lib().bs_last_count_dev(ctx, ctypes.byref(d)))
+    return d.value

@@ -122,6 +122,12 @@ extern "C" void bs_destroy(bs_ctx* c) {
 
 extern "C" const char* bs_last_error(const bs_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+extern "C" int bs_last_count_dev(const bs_ctx* c, double* dev) {
+  if (!c || !dev) return BS_EINVAL;
+  *dev = c->last_count_dev;
+  return BS_OK;
+}
+
 extern "C" int bs_set_stream(bs_ctx* c, void* s) {
   if (!c) return BS_EINVAL;
   c->stream = (hipStream_t)s;
@@ -381,9 +387,9 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
   }
   if (c->timing) (void)hipEventRecord(c->ev[5], c->stream);
 
-  unsigned int* bad = (unsigned int*)ctx_ws(c, "bad_flag", 256);
+  unsigned long long* bad = (unsigned long long*)ctx_ws(c, "count_dev", 256);
   if (!bad) return ctx_fail(c, BS_ENOMEM, "workspace (flag)");
-  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned int), c->stream));
+  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned long long), c->stream));
 
   // ---- counts ----
   int* d_tri = (int*)ctx_ws(c, "mabs_tri", tri_blk.size() * sizeof(int) + 16);
@@ -417,13 +423,16 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
       if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
       launch_round_counts(Ts, ntri, cc.d_counts, bad, c->stream);
       LAUNCHCHK(c, "count rounding");
-      unsigned int hbad = 0;
-      HIPCHK(c, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, c->stream));
+      double dev = 0.0;
+      HIPCHK(c, hipMemcpyAsync(&dev, bad, sizeof(dev), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
-      if (hbad) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "triangle count not an integer"); }
+      c->last_count_dev = dev;
+      if (!(dev <= kCountTol)) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev)); }
+      cc.dev = dev;
       it = c->counts.emplace(key, std::move(cc)).first;
     }
     d_tperp = it->second.d_counts;
+    c->last_count_dev = it->second.dev;
   } else {
     I64 = (double*)ctx_ws(c, "mabs_I64", (size_t)nbu * bstride * 8);
     if (!I64) return ctx_fail(c, BS_ENOMEM, "workspace (count fields)");
@@ -514,10 +523,11 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
   }
   if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
   if (!separable) {
-    unsigned int hbad = 0;
-    HIPCHK(c, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, c->stream));
+    double dev = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&dev, bad, sizeof(dev), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (hbad) return ctx_fail(c, BS_ECOUNT, "triangle count not an integer");
+    c->last_count_dev = dev;
+    if (!(dev <= kCountTol)) return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev));
   }
   return BS_OK;
 }

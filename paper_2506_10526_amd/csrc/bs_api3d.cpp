@@ -255,7 +255,7 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     launch_contract3(ca, 0, (int)nblk, c->stream);
     LAUNCHCHK(c, "count contraction");
     double* Ssum = (double*)ctx_ws(c, "c3_Ssum", (size_t)ntri * 8 + 16);
-    unsigned int* bad = (unsigned int*)ctx_ws(c, "bad_flag", 256);
+    unsigned long long* bad = (unsigned long long*)ctx_ws(c, "count_dev", 256);
     if (!Ssum || !bad) return ctx_fail(c, BS_ENOMEM, "workspace (count sums)");
     Fin3Args f{};
     f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
@@ -264,17 +264,20 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     LAUNCHCHK(c, "count finalize");
     CountCache cc;
     if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
-    HIPCHK(c, hipMemsetAsync(bad, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(bad, 0, 8, c->stream));
     launch_round_counts(Ssum, ntri, cc.d_counts, bad, c->stream);
     LAUNCHCHK(c, "count rounding");
-    unsigned int hbad = 0;
-    HIPCHK(c, hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    double dev = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&dev, bad, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (hbad) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "3D triangle count not an integer"); }
+    c->last_count_dev = dev;
+    if (!(dev <= kCountTol)) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "3D triangle count off an integer by " + std::to_string(dev)); }
+    cc.dev = dev;
     cc.tri.assign(P.tri.begin(), P.tri.end());
     it = c->counts.emplace(key, std::move(cc)).first;
     if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
   }
+  c->last_count_dev = it->second.dev;
   // ---- data fields ----
   Plan3 pd;
   build_plan3(P, blocks, fp64, pd);

@@ -20,7 +20,11 @@ struct CountCache {
   std::vector<int32_t> tri;       // triangle list the counts were made for
   int64_t* d_counts = nullptr;    // device int64 per triangle
   std::vector<int64_t> h_counts;  // host copy
+  double dev = 0.0;               // max |count - rint(count)| when the counts were made
 };
+
+// Largest distance of an FP64 triangle count from an integer that is accepted before rounding.
+constexpr double kCountTol = 0.25;
 
 struct bs_ctx {
   int device = 0;
@@ -33,6 +37,7 @@ struct bs_ctx {
   hipEvent_t ev[8] = {};
   double last_ms[4] = {0, 0, 0, 0};
   bool have_timing = false;
+  double last_count_dev = 0.0;
 };
 
 struct bs_bins {

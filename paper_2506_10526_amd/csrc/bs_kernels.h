@@ -54,7 +54,7 @@ struct MabsFinalArgs {
   double npix, norm;
   double* B;                // [ntri][n_nu1][nc][nc]
   int64_t* N;
-  unsigned int* bad;        // set to 1 when a count is not within 1e-3 of an integer
+  unsigned long long* bad;  // max |count - rint(count)| (double bits)
 };
 
 struct MabsCollapseArgs {
@@ -64,7 +64,7 @@ struct MabsCollapseArgs {
   int nc, ntri, circular;
   double npix, norm;
   double* B;  int64_t* N;  int32_t* Nnu;   // [ntri][D][D]
-  unsigned int* bad;
+  unsigned long long* bad;
 };
 
 void launch_mabs_fields_f32(const MabsFieldArgs& a, int nbins, int nchan, size_t lds, hipStream_t s);
@@ -75,7 +75,7 @@ void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s);
 void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s);
 // Tsum[t] = npix^2 * sum_p I_b1 I_b2 I_b3 over channel-independent FP64 count fields [nb][P].
 void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s);
-void launch_round_counts(const double* x, int n, int64_t* out, unsigned int* bad, hipStream_t s);
+void launch_round_counts(const double* x, int n, int64_t* out, unsigned long long* maxdev, hipStream_t s);
 void launch_mabs_finalize(const MabsFinalArgs& a, hipStream_t s);
 void launch_mabs_collapse(const MabsCollapseArgs& a, hipStream_t s);
 

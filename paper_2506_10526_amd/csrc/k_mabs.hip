@@ -421,13 +421,18 @@ __global__ __launch_bounds__(256) void k_tperp(const double* __restrict__ I, con
   if (threadIdx.x == 0) Tsum[t] = npix2 * red[0];
 }
 
-__device__ __forceinline__ int64_t round_count(double x, unsigned int* bad) {
+// Rounds an FP64 triangle count and records |x - rint(x)| in *maxdev (bit pattern of a
+// non-negative double, so integer max == floating max; NaN maps above every finite value).
+__device__ __forceinline__ int64_t round_count(double x, unsigned long long* maxdev) {
   double r = rint(x);
-  if (!(fabs(x - r) <= 1e-3)) atomicOr(bad, 1u);
+  double d = fabs(x - r);
+  if (d != d) d = __builtin_inf();
+  atomicMax(maxdev, (unsigned long long)__double_as_longlong(d));
   return (int64_t)r;
 }
 
-__global__ void k_round_counts(const double* __restrict__ x, int n, int64_t* __restrict__ out, unsigned int* bad) {
+__global__ void k_round_counts(const double* __restrict__ x, int n, int64_t* __restrict__ out,
+                               unsigned long long* bad) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = round_count(x[i], bad);
 }
@@ -441,7 +446,7 @@ __device__ __forceinline__ double sum_chunks(const double* S, int kchunks, size_
 __device__ __forceinline__ void mabs_entry(const double* S, int kchunks, const double* Sc, int kchunks_c,
                                            const int64_t* Tperp, const float* chw, int ntri, int nrows, int nc,
                                            int t, int R, int n1, int n2, int n3, double npix, double norm,
-                                           unsigned int* bad, double& Bo, int64_t& No) {
+                                           unsigned long long* bad, double& Bo, int64_t& No) {
   size_t chunk_stride = (size_t)ntri * nrows * nc;
   size_t idx = ((size_t)t * nrows + R) * nc + n3;
   double s = sum_chunks(S, kchunks, chunk_stride, idx);
@@ -539,7 +544,7 @@ void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s) {
 void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s) {
   if (ntri > 0) hipLaunchKernelGGL(k_tperp, dim3(ntri), dim3(256), 0, s, I, tri, P, npix2, Tsum);
 }
-void launch_round_counts(const double* x, int n, int64_t* out, unsigned int* bad, hipStream_t s) {
+void launch_round_counts(const double* x, int n, int64_t* out, unsigned long long* bad, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_round_counts, dim3((n + 255) / 256), dim3(256), 0, s, x, n, out, bad);
 }
 void launch_mabs_finalize(const MabsFinalArgs& a, hipStream_t s) {
