@@ -57,10 +57,10 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
     p.offG.push_back(p.totG);
     p.totT += (long long)(h + 1) * nub * n;
     p.totG += (long long)(h + 1) * n2;
-    for (int e = 0; e <= h; ++e) {
+    for (int e = 0; e <= h; ++e)
       for (int q0 = 0; q0 < nub; q0 += p.NLv) p.wv.push_back({(int)j, e, q0, 0});
-      for (int x0 = 0; x0 < n; x0 += p.NLu) p.wu.push_back({(int)j, e, x0, 0});
-    }
+    for (int xv = 0; xv < n; ++xv)
+      for (int e0 = 0; e0 <= h; e0 += p.NLu) p.wu.push_back({(int)j, e0, xv, 0});
     for (long long l0 = 0; l0 < n2; l0 += p.NLe) p.we.push_back({(int)j, 0, (int)l0, 0});
   }
 }
@@ -80,7 +80,8 @@ X* upload(bs_ctx* c, const char* name, const std::vector<X>& v, int& rc) {
 // Runs the field pipeline for `blocks`; fields land in `F` ([block][M n^2], type by fp64).
 // indicator: unit indicator of shell and support instead of data (no delay transform).
 int run_fields3(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64, bool indicator,
-                Plan3& p, void* F, const char* tag) {
+                Plan3& p, void* F, const char* tag, void** G_out = nullptr, long long** offG_out = nullptr,
+                int** hj_out = nullptr) {
   const auto& P = b->P;
   const int n = P.n, nc = P.nc, nh = P.nh, nub = 2 * P.vmax + 1, nvb = P.vmax + 1;
   const size_t cz = fp64 ? 16 : 8;
@@ -120,12 +121,16 @@ int run_fields3(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* 
   // v pass
   a.work = d_wv; a.off_in = nullptr; a.off_out = d_offT; a.in = D; a.out = Tm; a.tw = tw_n;
   a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = indicator ? 1 : 0;
-  launch_vpass3(a, (int)p.wv.size(), fp64, c->stream, 2 * (size_t)p.NLv * n * cz);
+  launch_vpass3(a, (int)p.wv.size(), fp64, c->stream, 2 * (size_t)p.NLv * (n + 1) * cz);
   LAUNCHCHK(c, "v pass");
   // u pass
   a.work = d_wu; a.off_in = d_offT; a.off_out = d_offG; a.in = Tm; a.out = Gm; a.NL = p.NLu;
   launch_upass3(a, (int)p.wu.size(), fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
   LAUNCHCHK(c, "u pass");
+  if (G_out) {  // the caller fuses the eta pass with the contraction
+    *G_out = Gm; *offG_out = d_offG; *hj_out = d_hj;
+    return BS_OK;
+  }
   // eta pass (C2R), output length nc
   const int M = nc;
   if (M % 2) return ctx_fail(c, BS_EUNSUPPORTED, "3D fields need an even number of channels");
@@ -222,8 +227,9 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   long long nblk = std::min<long long>(2048, (nvox + 127) / 128);
   long long chunk = ((nvox + nblk - 1) / nblk + 127) / 128 * 128;
   nblk = (nvox + chunk - 1) / chunk;
-  double* partial = (double*)ctx_ws(c, "c3_partial", (size_t)nblk * 112 * 32 * 8);
-  if (!partial) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
+  double* partial = (double*)ctx_ws(c, "c3_partial", (size_t)std::max<long long>(nblk, 1024) * 112 * 32 * 8);
+  double* reduced = (double*)ctx_ws(c, "c3_reduced", (size_t)112 * 32 * 8);
+  if (!partial || !reduced) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
   double rho3 = 1.0;
   if (w && w->chan_w) {
     std::vector<float> hw(P.nc);
@@ -260,7 +266,7 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     Fin3Args f{};
     f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
     f.T3D = nullptr; f.Ssum = Ssum; f.sfac = (double)nvox * (double)nvox;
-    launch_fin3(f, c->stream);
+    launch_fin3(f, reduced, c->stream);
     LAUNCHCHK(c, "count finalize");
     CountCache cc;
     if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
@@ -278,25 +284,70 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
   }
   c->last_count_dev = it->second.dev;
-  // ---- data fields ----
+  // ---- data fields and contraction ----
   Plan3 pd;
   build_plan3(P, blocks, fp64, pd);
-  void* F = ctx_ws(c, "c3_F", (size_t)blocks.size() * nvox * (fp64 ? 8 : 4));
-  if (!F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
-  rc = run_fields3(c, b, vis, w, fp64, false, pd, F, "c3d");
-  if (rc) return rc;
-  if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
-  Con3Args ca{};
-  ca.F = F; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
-  ca.chunk = chunk; ca.partial = partial;
-  launch_contract3(ca, fp64 ? 0 : (precision == BS_FP32 ? 1 : 2), (int)nblk, c->stream);
-  LAUNCHCHK(c, "contraction");
+  // Delay-axis grid of the fused path.  With true closure (3 H < nc) any grid M > 3 H closes the
+  // same triangles as the nc grid, so the smallest FFT-friendly multiple of 128 above 3 H is used
+  // and the sums are rescaled by (M / nc)^2 (sum over M n^2 voxels of fields normalised by
+  // 1 / (M n^2) versus nc n^2).
+  int M = P.nc;
+  if (P.true_closure && !getenv("BS_3D_FULLGRID")) {
+    for (int m = 128; m < P.nc; m += 128)
+      if (m > 3 * P.eta_max && fft_len_ok(m) && P.nc % 2 == 0) { M = m; break; }
+  }
+  const bool fused = !fp64 && (M % 128 == 0) && !getenv("BS_3D_UNFUSED");
+  if (!fused) M = P.nc;
+  const double sfac = ((double)M / P.nc) * ((double)M / P.nc);
+  int nparts = (int)nblk;
+  if (fused) {
+    void* G = nullptr;
+    long long* d_offG = nullptr;
+    int* d_hj = nullptr;
+    rc = run_fields3(c, b, vis, w, false, false, pd, nullptr, "c3d", &G, &d_offG, &d_hj);
+    if (rc) return rc;
+    if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+    const long long nlines = (long long)P.n * P.n;
+    const int fblocks = (int)std::min<long long>(nlines, 512);
+    Fused3Args fa{};
+    fa.G = G; fa.offG = d_offG; fa.hj = d_hj; fa.nbu = (int)blocks.size(); fa.nlines = nlines; fa.M = M;
+    fa.plan = make_fft_plan(M / 2);
+    fa.tw = ctx_twiddle(c, M, false);
+    if (!fa.tw) return ctx_fail(c, BS_ENOMEM, "twiddle table");
+    fa.scale = 1.0 / ((double)M * (double)P.n * (double)P.n);
+    fa.pairs = d_pairs; fa.npairs = npairs;
+    fa.lines_per_block = (nlines + fblocks - 1) / fblocks;
+    fa.partial = partial;
+    const size_t ld = (size_t)M / 2 + 2;
+    int stage_len = 0;
+    for (int h : pd.hj) stage_len += h + 1;
+    if (stage_len > 512) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction: more than 512 delay modes per line");
+    // FFT buffers, twiddles, two spectrum stages, pair table, prefix and slot tables
+    size_t lds = 2 * fa.nbu * ld * 8 + (size_t)M * 8 + 2 * 512 * 8 + (224 + 33 + 512) * 4;
+    lds = std::max<size_t>(lds, 112 * 32 * 8);
+    if (lds > 160 * 1024) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction does not fit in LDS");
+    launch_fused3(fa, precision == BS_FP32 ? 1 : 2, fblocks, lds, c->stream);
+    LAUNCHCHK(c, "fused contraction");
+    nparts = fblocks;
+  } else {
+    void* F = ctx_ws(c, "c3_F", (size_t)blocks.size() * nvox * (fp64 ? 8 : 4));
+    if (!F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
+    rc = run_fields3(c, b, vis, w, fp64, false, pd, F, "c3d");
+    if (rc) return rc;
+    if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+    Con3Args ca{};
+    ca.F = F; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
+    ca.chunk = chunk; ca.partial = partial;
+    launch_contract3(ca, fp64 ? 0 : (precision == BS_FP32 ? 1 : 2), (int)nblk, c->stream);
+    LAUNCHCHK(c, "contraction");
+  }
   if (c->timing) (void)hipEventRecord(c->ev[3], c->stream);
   Fin3Args f{};
-  f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
-  f.T3D = it->second.d_counts; f.rho3 = rho3; f.nvox = (double)nvox; f.norm = norm; f.sfac = 1.0;
+  f.partial = partial; f.nparts = nparts; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
+  f.T3D = it->second.d_counts; f.rho3 = rho3; f.nvox = (double)nvox; f.norm = norm; f.sfac = sfac;
   f.B = B; f.N = N_tri; f.Neff = N_eff;
-  launch_fin3(f, c->stream);
+  c->last_grid_M = M;
+  launch_fin3(f, reduced, c->stream);
   LAUNCHCHK(c, "finalize");
   if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
   return BS_OK;

@@ -38,6 +38,7 @@ struct bs_ctx {
   double last_ms[4] = {0, 0, 0, 0};
   bool have_timing = false;
   double last_count_dev = 0.0;
+  int last_grid_M = 0;   // delay-axis grid of the last 3D contraction
 };
 
 struct bs_bins {

@@ -150,4 +150,21 @@ void launch_vpass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size
 void launch_upass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds);
 void launch_etapass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds);
 void launch_contract3(const Con3Args& a, int mode, int nblocks, hipStream_t s);  // mode: 0 FP64, 1 FP32, 2 split
-void launch_fin3(const Fin3Args& a, hipStream_t s);
+struct Fused3Args {
+  const void* G;               // line-major delay spectra G_j[line][eta] (complex float)
+  const long long* offG;       // per block
+  const int* hj;               // per block
+  int nbu;                     // fields (<= 32)
+  long long nlines;            // n * n
+  int M;                       // eta output length (even)
+  FftPlan plan;                // length M / 2
+  const void* tw;              // exp(-2 pi i m / M)
+  double scale;                // 1 / (M n^2)
+  const int* pairs; int npairs;
+  long long lines_per_block;
+  double* partial;             // [gridDim.x][112][32]
+};
+
+// Reduces the per-block partials into `reduced` ([112][32]) and finalises every triangle.
+void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s);
+void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s);

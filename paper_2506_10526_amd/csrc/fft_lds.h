@@ -34,6 +34,15 @@ __device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return cmk(a.x * s, a.y 
 template <int SIGN, typename T>
 __device__ __forceinline__ Cx<T> cmul_si(Cx<T> a) { return SIGN > 0 ? cmk(-a.y, a.x) : cmk(a.y, -a.x); }
 
+// Exact q = t / d, r = t % d for 0 <= t < 2^18 and 1 <= d <= 4096 from a float reciprocal
+// rd = 1/d (one correction step; checked exhaustively over that range).
+__device__ __forceinline__ void fdivmod(int t, int d, float rd, int& q, int& r) {
+  q = (int)((float)t * rd);
+  r = t - q * d;
+  if (r < 0) { --q; r += d; }
+  if (r >= d) { ++q; r -= d; }
+}
+
 struct FftPlan {
   int L;        // transform length
   int nr;       // number of radix passes
@@ -97,12 +106,13 @@ __device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<
   const int nbf = L / R;
   const int total = nl * nbf;
   const int tstep = (L / (Ns * R)) * tws;  // table stride of the unit angle 2 pi / (Ns R)
+  const float rnbf = 1.0f / (float)nbf, rns = 1.0f / (float)Ns;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    int line = t / nbf;
-    int j = t - line * nbf;
+    int line, j, jq, k;
+    fdivmod(t, nbf, rnbf, line, j);
+    fdivmod(j, Ns, rns, jq, k);
     const Cx<T>* in = src + (size_t)line * ld;
     Cx<T>* out = dst + (size_t)line * ld;
-    int k = j % Ns;
     Cx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[j + r * nbf];
@@ -118,7 +128,7 @@ __device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<
     else if (R == 3) dft3<SIGN>(v);
     else if (R == 4) dft4<SIGN>(v);
     else dft8<SIGN>(v);
-    int o = (j / Ns) * Ns * R + k;
+    int o = jq * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
   }

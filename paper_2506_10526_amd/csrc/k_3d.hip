@@ -82,50 +82,59 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   const Shell3Geom& g = a.g;
   const Work3 w = a.work[blockIdx.x];
   const int shell = a.shell_of_block[w.j];
-  const int n = g.n;
+  const int n = g.n, ld = n + 1;
   const int nl = min(a.NL, g.nub - w.start);
   Cx<T>* A = (Cx<T>*)smem_raw;
-  Cx<T>* Bf = A + (size_t)a.NL * n;
+  Cx<T>* Bf = A + (size_t)a.NL * ld;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     int l = e / n, i = e - l * n;
     int qu = w.start + l - g.vmax;
-    A[e] = shell_value<T>(a, shell, w.eta, qu, sidx(i, n));
+    A[(size_t)l * ld + i] = shell_value<T>(a, shell, w.eta, qu, sidx(i, n));
   }
   __syncthreads();
-  Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1);
-  Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j] + ((size_t)w.eta * g.nub + w.start) * n;
-  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) out[e] = r[e];
+  Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  // T_j[x_v][eta][qu]: consecutive threads write consecutive qu rows of one x_v
+  const int hp1 = a.hj[w.j] + 1;
+  Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    int i = e / nl, l = e - i * nl;
+    out[((size_t)i * hp1 + w.eta) * g.nub + w.start + l] = r[(size_t)l * ld + i];
+  }
 }
 
 // --------------------------------------------------------------- u pass
+// Work item (j, x_v = w.start, eta0 = w.eta): the delay planes eta0.. of one x_v column.
+// Output G_j[line = x_u n + x_v][eta] keeps each line's delay spectrum contiguous.
 template <typename T>
 __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Shell3Geom& g = a.g;
   const Work3 w = a.work[blockIdx.x];
-  const int n = g.n;
-  const int nl = min(a.NL, n - w.start);
-  const int ld = n + 1;
+  const int n = g.n, ld = n + 1;
+  const int hp1 = a.hj[w.j] + 1;
+  const int xv = w.start, e0 = w.eta;
+  const int nl = min(a.NL, hp1 - e0);
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
-  const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + (size_t)w.eta * g.nub * n + w.start;
+  const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + ((size_t)xv * hp1 + e0) * g.nub;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int i = e / nl, l = e - i * nl;
+    int l = e / n, i = e - l * n;
     int qu = sidx(i, n);
     Cx<T> x = cmk(T(0), T(0));
-    if (qu >= -g.vmax && qu <= g.vmax) x = in[(size_t)(qu + g.vmax) * n + l];
+    if (qu >= -g.vmax && qu <= g.vmax) x = in[(size_t)l * g.nub + qu + g.vmax];
     A[(size_t)l * ld + i] = x;
   }
   __syncthreads();
   Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
-  Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j] + (size_t)w.eta * n * n + w.start;
+  Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     int i = e / nl, l = e - i * nl;
-    out[(size_t)i * n + l] = r[(size_t)l * ld + i];
+    out[((size_t)i * n + xv) * hp1 + e0 + l] = r[(size_t)l * ld + i];
   }
 }
 
 // --------------------------------------------------------------- eta pass (C2R)
+// Writes the real fields F_j[x_eta][line] (used for the field output and the FP64 counts).
 template <typename T>
 __global__ __launch_bounds__(256) void k3_etapass(Pass3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -139,11 +148,12 @@ __global__ __launch_bounds__(256) void k3_etapass(Pass3Args a) {
   const int Hj = a.hj[w.j];
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
-  const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + w.start;
+  const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + (size_t)w.start * (Hj + 1);
   const Cx<T>* tw = (const Cx<T>*)a.tw;  // table of length M
   for (int e = threadIdx.x; e < nl * Mh; e += blockDim.x) {
-    int k = e / nl, l = e - k * nl;
-    auto get = [&](int eta) -> Cx<T> { return eta <= Hj ? in[(size_t)eta * n2 + l] : cmk(T(0), T(0)); };
+    int l = e / Mh, k = e - l * Mh;
+    const Cx<T>* gl = in + (size_t)l * (Hj + 1);
+    auto get = [&](int eta) -> Cx<T> { return eta <= Hj ? gl[eta] : cmk(T(0), T(0)); };
     A[(size_t)l * ld + k] = c2r_pack<T>(k, Mh, get, tw, 1);
   }
   __syncthreads();
@@ -181,18 +191,136 @@ __device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
   }
 }
 
+template <int MODE>
+using acc_t = typename std::conditional<MODE == 0, f64x4, f32x4>::type;
+
+// One 32-voxel step of one wave: voxels v0 .. v0+31 of the LDS field rows sF + j*ld
+// (j < nbu; rows beyond nbu read as zero).  A rows are the pair products F_a F_b, B columns
+// the fields F_c; sp holds the pair table (-1 = padding row).
+template <int MODE, typename T>
+__device__ __forceinline__ void con3_step(const T* __restrict__ sF, int ld, int nbu, int v0, const int* sp, int RT,
+                                          int CT, acc_t<MODE> (&acc)[C3_RT][C3_CT]) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  if constexpr (MODE == 2) {
+    const int vb = v0 + kq * 8;
+    bf16x8 bh[C3_CT], bl[C3_CT];
+#pragma unroll
+    for (int ct = 0; ct < C3_CT; ++ct) {
+      float v[8];
+      const int c = ct * 16 + r16;
+      if (c < nbu) {
+        const T* src = &sF[(size_t)c * ld + vb];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (float)src[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = 0.f;
+      }
+      split8(v, bh[ct], bl[ct]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < C3_RT; ++rt) {
+      if (rt < RT) {
+        int p = rt * 16 + r16;
+        int pa = sp[2 * p], pb = sp[2 * p + 1];
+        float v[8];
+        if (pa >= 0) {
+          const T* sa = &sF[(size_t)pa * ld + vb];
+          const T* sb = &sF[(size_t)pb * ld + vb];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = (float)sa[q] * (float)sb[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = 0.f;
+        }
+        bf16x8 ah, al;
+        split8(v, ah, al);
+#pragma unroll
+        for (int ct = 0; ct < C3_CT; ++ct) {
+          if (ct < CT) {
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll 2
+    for (int ks = 0; ks < 8; ++ks) {
+      const int vx = v0 + ks * 4 + kq;
+      T bv[C3_CT];
+#pragma unroll
+      for (int ct = 0; ct < C3_CT; ++ct) {
+        const int c = ct * 16 + r16;
+        bv[ct] = c < nbu ? sF[(size_t)c * ld + vx] : T(0);
+      }
+#pragma unroll
+      for (int rt = 0; rt < C3_RT; ++rt) {
+        if (rt < RT) {
+          int p = rt * 16 + r16;
+          int pa = sp[2 * p], pb = sp[2 * p + 1];
+          T av = pa >= 0 ? sF[(size_t)pa * ld + vx] * sF[(size_t)pb * ld + vx] : T(0);
+#pragma unroll
+          for (int ct = 0; ct < C3_CT; ++ct) {
+            if (ct < CT) {
+              if constexpr (MODE == 0)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[rt][ct], 0, 0, 0);
+              else
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ct], acc[rt][ct], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void con3_flush(acc_t<MODE> (&acc)[C3_RT][C3_CT], double (&acc64)[C3_RT][C3_CT][4]) {
+#pragma unroll
+  for (int i = 0; i < C3_RT; ++i)
+#pragma unroll
+    for (int j = 0; j < C3_CT; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { acc64[i][j][q] += (double)acc[i][j][q]; acc[i][j][q] = 0; }
+}
+
+// Reduce the four waves' sums in a fixed order into red[112][32] and store them as this
+// block's partial sums.  red must be zeroed and visible to all threads before the call.
+template <int MODE>
+__device__ __forceinline__ void con3_store(acc_t<MODE> (&acc)[C3_RT][C3_CT], double (&acc64)[C3_RT][C3_CT][4],
+                                           double* red, double* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < C3_RT; ++i)
+#pragma unroll
+        for (int j = 0; j < C3_CT; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // 16x16 MFMA output rows: 4*(lane/16)+q for the f32/bf16 forms, lane/16+4*q for f64
+            int p = i * 16 + (MODE == 0 ? kq + 4 * q : kq * 4 + q), c = j * 16 + r16;
+            red[p * 32 + c] += acc64[i][j][q] + (double)acc[i][j][q];
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 112 * 32; e += 256) out[e] = red[e];
+}
+
+// Contraction over precomputed fields F[j][vox] streamed through LDS in 128-voxel slabs.
 template <int MODE, typename T>  // MODE 0: FP64 MFMA, 1: FP32 MFMA, 2: split-BF16 MFMA
 __global__ __launch_bounds__(256) void k3_contract(Con3Args a) {
   __shared__ T sF[32 * C3_LDS];
   __shared__ int sp[2 * 112];
   __shared__ double red[112 * 32];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r16 = lane & 15, kq = lane >> 4;
+  const int tid = threadIdx.x, wave = tid >> 6;
   for (int e = tid; e < 2 * 112; e += 256) sp[e] = e < 2 * a.npairs ? a.pairs[e] : -1;
   for (int e = tid; e < 112 * 32; e += 256) red[e] = 0.0;
   const int RT = (a.npairs + 15) / 16, CT = (a.nbu + 15) / 16;
-  typedef typename std::conditional<MODE == 0, f64x4, f32x4>::type accv;
-  accv acc[C3_RT][C3_CT];
+  acc_t<MODE> acc[C3_RT][C3_CT];
   double acc64[C3_RT][C3_CT][4];
 #pragma unroll
   for (int i = 0; i < C3_RT; ++i)
@@ -211,106 +339,119 @@ __global__ __launch_bounds__(256) void k3_contract(Con3Args a) {
       long long x = x0 + v;
       sF[j * C3_LDS + v] = x < x_end ? F[(size_t)j * a.vox + x] : T(0);
     }
-    for (int e = a.nbu * C3_SLAB + tid; e < 32 * C3_SLAB; e += 256) {
-      int j = e / C3_SLAB, v = e - j * C3_SLAB;
-      sF[j * C3_LDS + v] = T(0);
-    }
     __syncthreads();
-    const int vw = wave * 32;
-    if constexpr (MODE == 2) {
-      const int vb = vw + kq * 8;
-      bf16x8 bh[C3_CT], bl[C3_CT];
-#pragma unroll
-      for (int ct = 0; ct < C3_CT; ++ct) {
-        float v[8];
-        const T* src = &sF[(ct * 16 + r16) * C3_LDS + vb];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (float)src[q];
-        split8(v, bh[ct], bl[ct]);
-      }
-#pragma unroll
-      for (int rt = 0; rt < C3_RT; ++rt) {
-        if (rt < RT) {
-          int p = rt * 16 + r16;
-          int pa = sp[2 * p], pb = sp[2 * p + 1];
-          float v[8];
-          if (pa >= 0) {
-            const T* sa = &sF[pa * C3_LDS + vb];
-            const T* sb = &sF[pb * C3_LDS + vb];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = (float)sa[q] * (float)sb[q];
-          } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = 0.f;
-          }
-          bf16x8 ah, al;
-          split8(v, ah, al);
-#pragma unroll
-          for (int ct = 0; ct < C3_CT; ++ct) {
-            if (ct < CT) {
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
-            }
-          }
-        }
-      }
-    } else {
-#pragma unroll 2
-      for (int ks = 0; ks < 8; ++ks) {
-        const int vx = vw + ks * 4 + kq;
-        T bv[C3_CT];
-#pragma unroll
-        for (int ct = 0; ct < C3_CT; ++ct) bv[ct] = sF[(ct * 16 + r16) * C3_LDS + vx];
-#pragma unroll
-        for (int rt = 0; rt < C3_RT; ++rt) {
-          if (rt < RT) {
-            int p = rt * 16 + r16;
-            int pa = sp[2 * p], pb = sp[2 * p + 1];
-            T av = pa >= 0 ? sF[pa * C3_LDS + vx] * sF[pb * C3_LDS + vx] : T(0);
-#pragma unroll
-            for (int ct = 0; ct < C3_CT; ++ct) {
-              if (ct < CT) {
-                if constexpr (MODE == 0)
-                  acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[rt][ct], 0, 0, 0);
-                else
-                  acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ct], acc[rt][ct], 0, 0, 0);
-              }
-            }
-          }
-        }
-      }
-    }
+    con3_step<MODE, T>(sF, C3_LDS, a.nbu, wave * 32, sp, RT, CT, acc);
     __syncthreads();
     since += C3_SLAB;
-    if (MODE != 0 && since >= 512) {
-      since = 0;
-#pragma unroll
-      for (int i = 0; i < C3_RT; ++i)
-#pragma unroll
-        for (int j = 0; j < C3_CT; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) { acc64[i][j][q] += (double)acc[i][j][q]; acc[i][j][q] = 0; }
-    }
+    if (MODE != 0 && since >= 512) { since = 0; con3_flush<MODE>(acc, acc64); }
   }
-  // reduce the four waves in a fixed order, then store this block's partial sums
-  for (int wv = 0; wv < 4; ++wv) {
-    if (wave == wv) {
+  con3_store<MODE>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
+}
+
+// Fused C2R along eta + contraction.  A block owns a range of (x_u, x_v) lines; for each line
+// it unpacks every shell's delay spectrum G_j[line][0..H_j] (Hermitian half eta >= 0), runs the
+// M/2-point inverse FFT of the C2R packing for all shells at once in LDS (the complex result
+// read as floats is the real field x_eta = 0..M-1), and contracts the M voxels of the line.
+// The next line's spectra are fetched into registers while the current line is processed, and
+// twiddles and per-shell metadata live in LDS, so no dependent global load sits in the loop.
+constexpr int FUSED_STAGE = 512;   // max sum_j (H_j + 1) held per line
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nbu = a.nbu, M = a.M, Mh = M / 2, ld = Mh + 2;   // padded rows stagger LDS banks
+  Cx<float>* A = (Cx<float>*)smem_raw;
+  Cx<float>* Bf = A + (size_t)nbu * ld;
+  Cx<float>* tw = Bf + (size_t)nbu * ld;                    // [M]
+  Cx<float>* stage = tw + M;                                  // [2][FUSED_STAGE]
+  int* sp = (int*)(stage + 2 * FUSED_STAGE);                  // [224]
+  int* pre = sp + 224;                                        // [33] prefix of H_j + 1
+  int* sj = pre + 33;                                         // [FUSED_STAGE] shell of a stage slot
+  for (int e = tid; e < 2 * 112; e += 256) sp[e] = e < 2 * a.npairs ? a.pairs[e] : -1;
+  for (int e = tid; e < M; e += 256) tw[e] = ((const Cx<float>*)a.tw)[e];
+  if (tid == 0) {
+    int acc = 0;
+    for (int j = 0; j < nbu; ++j) { pre[j] = acc; acc += a.hj[j] + 1; }
+    pre[nbu] = acc;
+  }
+  __syncthreads();
+  const int L = pre[nbu];
+  for (int e = tid; e < L; e += 256) {
+    int j = 0;
+    while (pre[j + 1] <= e) ++j;
+    sj[e] = j;
+  }
+  const int RT = (a.npairs + 15) / 16, CT = (nbu + 15) / 16;
+  acc_t<MODE> acc[C3_RT][C3_CT];
+  double acc64[C3_RT][C3_CT][4];
 #pragma unroll
-      for (int i = 0; i < C3_RT; ++i)
+  for (int i = 0; i < C3_RT; ++i)
 #pragma unroll
-        for (int j = 0; j < C3_CT; ++j)
+    for (int j = 0; j < C3_CT; ++j)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            // 16x16 MFMA output rows: 4*(lane/16)+q for the f32/bf16 forms, lane/16+4*q for f64
-            int p = i * 16 + (MODE == 0 ? kq + 4 * q : kq * 4 + q), c = j * 16 + r16;
-            red[p * 32 + c] += acc64[i][j][q] + (double)acc[i][j][q];
-          }
+      for (int q = 0; q < 4; ++q) { acc[i][j][q] = 0; acc64[i][j][q] = 0.0; }
+  const Cx<float>* G = (const Cx<float>*)a.G;
+  const float sc = (float)a.scale;
+  const float rMh = 1.0f / (float)Mh;
+  const long long l_beg = (long long)blockIdx.x * a.lines_per_block;
+  const long long l_end = l_beg + a.lines_per_block < a.nlines ? l_beg + a.lines_per_block : a.nlines;
+  __syncthreads();
+  // global address of stage slot e for `line`
+  auto slot_src = [&](int e, long long line) -> const Cx<float>* {
+    int j = sj[e];
+    return G + a.offG[j] + (size_t)line * (pre[j + 1] - pre[j]) + (e - pre[j]);
+  };
+  // prime stage 0 with the first line
+  if (l_beg < l_end)
+    for (int e = tid; e < L; e += 256) stage[e] = *slot_src(e, l_beg);
+  int cur = 0;
+  int since = 0;
+  __syncthreads();
+  for (long long line = l_beg; line < l_end; ++line) {
+    // prefetch the next line (at most two slots per thread)
+    Cx<float> pf0 = cmk(0.f, 0.f), pf1 = cmk(0.f, 0.f);
+    const bool more = line + 1 < l_end;
+    if (more) {
+      if (tid < L) pf0 = *slot_src(tid, line + 1);
+      if (tid + 256 < L) pf1 = *slot_src(tid + 256, line + 1);
+    }
+    const Cx<float>* st = stage + cur * FUSED_STAGE;
+    for (int e = tid; e < nbu * Mh; e += 256) {
+      int j, k;
+      fdivmod(e, Mh, rMh, j, k);
+      const int p0 = pre[j], hp1 = pre[j + 1] - p0;
+      auto get = [&](int eta) -> Cx<float> { return eta < hp1 ? st[p0 + eta] : cmk(0.f, 0.f); };
+      Cx<float> z = c2r_pack<float>(k, Mh, get, tw, 1);
+      A[(size_t)j * ld + k] = cmk(z.x * sc, z.y * sc);
     }
     __syncthreads();
+    Cx<float>* r = lds_fft<+1, float>(A, Bf, a.plan, nbu, tw, 2, ld);
+    const float* Fl = (const float*)r;   // row j: floats [2 j ld, 2 j ld + M)
+    for (int v0 = wave * 32; v0 < M; v0 += 128) con3_step<MODE, float>(Fl, 2 * ld, nbu, v0, sp, RT, CT, acc);
+    if (more) {
+      Cx<float>* nx = stage + (cur ^ 1) * FUSED_STAGE;
+      if (tid < L) nx[tid] = pf0;
+      if (tid + 256 < L) nx[tid + 256] = pf1;
+    }
+    cur ^= 1;
+    __syncthreads();
+    since += M / 4;   // voxels per wave per line
+    if (since >= 512) { since = 0; con3_flush<MODE>(acc, acc64); }
   }
-  double* out = a.partial + (size_t)blockIdx.x * 112 * 32;
-  for (int e = tid; e < 112 * 32; e += 256) out[e] = red[e];
+  double* red = (double*)smem_raw;   // reuse the FFT buffers
+  for (int e = tid; e < 112 * 32; e += 256) red[e] = 0.0;
+  __syncthreads();
+  con3_store<MODE>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
+}
+
+// Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
+__global__ void k3_reduce_parts(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 112 * 32) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * 112 * 32 + e];
+  out[e] = s;
 }
 
 // --------------------------------------------------------------- finalisation
@@ -318,9 +459,7 @@ __global__ void k3_fin(Fin3Args a) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ntri) return;
   int idx = a.tri_pair[t] * 32 + a.tri_col[t];
-  double s = 0.0;
-  for (int p = 0; p < a.nparts; ++p) s += a.partial[(size_t)p * 112 * 32 + idx];
-  s *= a.sfac;
+  double s = a.partial[idx] * a.sfac;   // partial holds the reduced sums here
   if (!a.T3D) {
     a.Ssum[t] = s;
     return;
@@ -368,6 +507,18 @@ void launch_contract3(const Con3Args& a, int mode, int nblocks, hipStream_t s) {
   else if (mode == 1) hipLaunchKernelGGL((k3_contract<1, float>), dim3(nblocks), dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k3_contract<2, float>), dim3(nblocks), dim3(256), 0, s, a);
 }
-void launch_fin3(const Fin3Args& a, hipStream_t s) {
-  if (a.ntri > 0) hipLaunchKernelGGL(k3_fin, dim3((a.ntri + 127) / 128), dim3(128), 0, s, a);
+void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
+  hipLaunchKernelGGL(k3_reduce_parts, dim3((112 * 32 + 255) / 256), dim3(256), 0, s, a.partial, a.nparts, reduced);
+  Fin3Args b = a;
+  b.partial = reduced;
+  if (a.ntri > 0) hipLaunchKernelGGL(k3_fin, dim3((a.ntri + 127) / 128), dim3(128), 0, s, b);
+}
+void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s) {
+  if (mode == 1) {
+    (void)hipFuncSetAttribute((const void*)k3_fused<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k3_fused<1>, dim3(nblocks), dim3(256), lds, s, a);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k3_fused<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k3_fused<2>, dim3(nblocks), dim3(256), lds, s, a);
+  }
 }

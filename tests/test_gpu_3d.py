@@ -51,9 +51,25 @@ def run3(ctx, h, V, prec, ncand, **wk):
 
 
 @pytest.mark.parametrize("prec", PREC)
-@pytest.mark.parametrize("case", ["cubic16x8", "cubic32x24_flags"])
-def test_3d_matches_oracle(ctx, prec, case):
-    if case == "cubic16x8":
+@pytest.mark.parametrize("case", ["cubic16x8", "cubic32x24_flags", "cubic32x128_fused", "cubic32x128_unfused",
+                                  "cubic32x256_coarse", "cubic32x256_fullgrid"])
+def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
+    """Small cubes: radix-2/3 delay axes, flags, and (nc = 128) the fused eta-C2R + contraction
+    kernel next to the path that materialises the fields (BS_3D_UNFUSED=1)."""
+    if case.endswith("_unfused"):
+        monkeypatch.setenv("BS_3D_UNFUSED", "1")
+    if case.endswith("_fullgrid"):
+        monkeypatch.setenv("BS_3D_FULLGRID", "1")
+    if case.startswith("cubic32x256"):
+        # delay modes |eta| <= 9: the fused path contracts on a 128-point delay grid
+        n, nc, nb, kmax = 32, 256, 6, 10.0
+        wl = synth.small_workload(n, nc)
+        cw = None
+    elif case.startswith("cubic32x128"):
+        n, nc, nb, kmax = 32, 128, 6, 10.0
+        wl = synth.small_workload(n, nc, flags_mod32=(0, 16, 31))
+        cw = wl.chan_w()
+    elif case == "cubic16x8":
         n, nc, nb, kmax = 16, 8, 5, 5.5
         wl = synth.small_workload(n, nc)
         cw = None
