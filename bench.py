@@ -45,7 +45,19 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-mabs", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     return p.parse_args()
+
+
+def copy_calibration(torch):
+    """A copy kernel of known size: 1 GiB read + 1 GiB written per launch, three launches."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 2 * a.numel() * 4, "launches": 3}))
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -115,6 +127,9 @@ def main():
     from paper_2506_10526_amd import bs, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     dev = torch.device("cuda:0")
     w = synth.config2()
     edges = w.shell_edges(20)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "bs_kernels.h"
 
@@ -339,6 +340,211 @@ __global__ __launch_bounds__(256) void k_mabs_gemm(MabsGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Split-BF16 contraction, large tiles.  Block tile 128 x 256 (rows R = i*nc + nu2, columns nu3),
+// four waves of 64 x 128 (2 x 4 MFMA 32x32x16 tiles, 128 FP32 accumulators per lane), pixel
+// stages of 32, double-buffered LDS with one barrier per stage:
+//  * the pre-split B rows (bf16 hi/lo of F_b3) go from global memory straight into the next
+//    LDS buffer with 16-byte global_load_lds (lane l lands at byte 16 l of the wave's window);
+//  * A = F_b1(nu1) .* F_b2(nu2) is formed and split into bf16 hi/lo by the VALU from F2 values
+//    prefetched into registers and, when the whole tile shares one nu1 (UNI), an F1 chunk that
+//    each wave also loads straight into LDS;
+//  * the MFMAs of the current stage run while those loads are in flight.
+// LDS rows hold 32 bf16 as four 16-byte chunks XOR-swizzled by row.  The block's FP32 tile is
+// added into its FP64 output every SFLUSH pixels.  Blocks are mapped to tiles so that tiles
+// sharing a B column block and neighbouring A rows run on the same XCD (blocks are dealt to the
+// eight XCDs round-robin).
+// ---------------------------------------------------------------------------
+constexpr int S_TM = 128, S_TN = 256, S_TK = 32, SFLUSH = 4096;
+// uint16 offsets inside one stage buffer
+constexpr int S_AH = 0, S_AL = S_TM * S_TK, S_BH = 2 * S_TM * S_TK, S_BL = S_BH + S_TN * S_TK;
+constexpr int S_F1 = S_BL + S_TN * S_TK;           // 4 waves x 1 KB of F1 staging
+constexpr int S_BUF = S_F1 + 4 * 512;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int swz(int r, int chunk) { return (chunk ^ ((r >> 2) & 3)); }
+
+template <bool UNI>
+__global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  uint16_t* lds = (uint16_t*)smem_raw;   // [2][S_BUF]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int nrows = a.n_nu1 * a.nc;
+  const int rtiles = (nrows + S_TM - 1) / S_TM, ctiles = (a.nc + S_TN - 1) / S_TN;
+  const int nb = rtiles * ctiles * a.ntri * a.kchunks;
+  // XCD-aware remap of the linear block id
+  int b = blockIdx.x;
+  const int full = (nb / 8) * 8;
+  if (b < full) b = (b & 7) * (full / 8) + (b >> 3);
+  const int rt = b % rtiles;
+  int rest = b / rtiles;
+  const int ct = rest % ctiles;
+  rest /= ctiles;
+  const int kc = rest % a.kchunks;
+  const int t = rest / a.kchunks;
+  const int row0 = rt * S_TM, col0 = ct * S_TN;
+  const int b1 = a.tri[3 * t], b2 = a.tri[3 * t + 1], b3 = a.tri[3 * t + 2];
+  const int kbeg = kc * a.kchunk;
+  const int kend = min(a.P, kbeg + a.kchunk);
+
+  // A loader: row ar (16 pixels starting at ahalf)
+  const int ar = tid >> 1, ahalf = (tid & 1) * 16;
+  const int R = row0 + ar;
+  const bool rok = R < nrows;
+  const int Rc = rok ? R : nrows - 1;
+  const int ia = Rc / a.nc, nu2 = Rc - ia * a.nc;
+  const float* f1 = a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[ia] * a.P + ahalf;
+  const float* f2 = a.F + (size_t)b2 * a.bin_stride + (size_t)nu2 * a.P + ahalf;
+  // F1 chunk for the whole tile (UNI): lanes 0..7 cover 32 floats, the others repeat chunk 7
+  const float* f1u = a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[row0 / a.nc] * a.P + 4 * min(lane, 7);
+  // B DMA: this wave's rows w*64 .. w*64+63, 16 rows per instruction
+  const uint16_t* bsrc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int br = wave * 64 + q * 16 + (lane >> 2);
+    const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
+    bsrc[q] = (const uint16_t*)0 + ((size_t)b3 * a.bin_stride + (size_t)col * a.P) +
+              8 * swz(br, lane & 3);
+  }
+
+  float4 pa1[4], pa2[4];
+  auto issue = [&](int k0, uint16_t* buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __builtin_amdgcn_global_load_lds((const void*)(a.Fh + ((bsrc[q] - (const uint16_t*)0) + k0)),
+                                       (lds_void*)(buf + S_BH + (wave * 64 + q * 16) * S_TK), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(a.Fl + ((bsrc[q] - (const uint16_t*)0) + k0)),
+                                       (lds_void*)(buf + S_BL + (wave * 64 + q * 16) * S_TK), 16, 0, 0);
+    }
+    if (UNI) {
+      __builtin_amdgcn_global_load_lds((const void*)(f1u + k0), (lds_void*)(buf + S_F1 + wave * 512), 16, 0, 0);
+    } else {
+      const float4* p1 = (const float4*)(f1 + k0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pa1[q] = p1[q];
+    }
+    const float4* p2 = (const float4*)(f2 + k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pa2[q] = p2[q];
+  };
+  auto form = [&](uint16_t* buf) {
+    uint16_t* Ah = buf + S_AH;
+    uint16_t* Al = buf + S_AL;
+    if (UNI) {
+      const float4* fw = (const float4*)(buf + S_F1 + wave * 512) + (ahalf >> 2);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pa1[q] = fw[q];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint16_t h[8], l[8];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float4 x = pa1[2 * c + q], y = pa2[2 * c + q];
+        float v[4] = {x.x * y.x, x.y * y.y, x.z * y.z, x.w * y.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float vv = rok ? v[u] : 0.f;
+          h[4 * q + u] = bf16_bits(vv);
+          l[4 * q + u] = bf16_bits(vv - bf16_float(h[4 * q + u]));
+        }
+      }
+      const int pc = swz(ar, (ahalf >> 3) + c);
+      *(uint4*)&Ah[ar * S_TK + pc * 8] = *(uint4*)h;
+      *(uint4*)&Al[ar * S_TK + pc * 8] = *(uint4*)l;
+    }
+  };
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  double* S = a.S + ((size_t)kc * a.ntri + t) * (size_t)nrows * a.nc;
+  const bool interior = row0 + S_TM <= nrows && col0 + S_TN <= a.nc;
+  bool first_flush = true;
+
+  issue(kbeg, lds);
+  __builtin_amdgcn_s_waitcnt(0);
+  form(lds);
+  __syncthreads();
+  int cur = 0;
+  // outer loop: FP64 flush of the block's tile every SFLUSH pixels; inner loop: stages (MFMA only)
+  for (int kf = kbeg; kf < kend; kf += SFLUSH) {
+    const int kfe = min(kend, kf + SFLUSH);
+    for (int k0 = kf; k0 < kfe; k0 += S_TK) {
+      const bool more = k0 + S_TK < kend;
+      uint16_t* nxt = lds + (cur ^ 1) * S_BUF;
+      if (more) issue(k0 + S_TK, nxt);
+      const uint16_t* buf = lds + cur * S_BUF;
+      const uint16_t* Ah = buf + S_AH;
+      const uint16_t* Al = buf + S_AL;
+      const uint16_t* Bh = buf + S_BH;
+      const uint16_t* Bl = buf + S_BL;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const int chunk = kk * 2 + (lane >> 5);
+        bf16x8 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int r = wm * 64 + i * 32 + (lane & 31);
+          const int off = r * S_TK + swz(r, chunk) * 8;
+          ah[i] = *(const bf16x8*)&Ah[off];
+          al[i] = *(const bf16x8*)&Al[off];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 128 + j * 32 + (lane & 31);
+          const int off = c * S_TK + swz(c, chunk) * 8;
+          bh[j] = *(const bf16x8*)&Bh[off];
+          bl[j] = *(const bf16x8*)&Bl[off];
+        }
+        // the three products of a tile are issued eight MFMAs apart (no back-to-back dependence)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) {
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA and register loads of the next stage
+        form(nxt);
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = col0 + wn * 128 + j * 32 + (lane & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int row = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+          if (interior || (row < nrows && col < a.nc)) {
+            double* d = &S[(size_t)row * a.nc + col];
+            double v = (double)acc[i][j][e];
+            *d = first_flush ? v : *d + v;
+          }
+          acc[i][j][e] = 0.f;
+        }
+      }
+    first_flush = false;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 contraction on the vector ALUs (data in BS_FP64 mode, counts for per-cell N_g).
 // 64 x 64 tile, 256 threads, 4 x 4 outputs per thread (strided by 16), K staged by 16.
 // ---------------------------------------------------------------------------
@@ -533,7 +739,20 @@ static dim3 gemm_grid(const MabsGemmArgs& a, int tm, int tn) {
   return dim3((a.nc + tn - 1) / tn, (nrows + tm - 1) / tm, a.ntri * a.kchunks);
 }
 void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mabs_gemm<2>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
+  if (getenv("BS_MABS_SMALL_TILES")) {
+    hipLaunchKernelGGL(k_mabs_gemm<2>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
+    return;
+  }
+  const int nrows = a.n_nu1 * a.nc;
+  const long long nb = (long long)((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
+  const size_t lds = 2 * (size_t)S_BUF * 2;
+  if (a.nc % S_TM == 0) {
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_mabs_gemm_split2<true>, dim3((unsigned)nb), dim3(256), lds, s, a);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_mabs_gemm_split2<false>, dim3((unsigned)nb), dim3(256), lds, s, a);
+  }
 }
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
