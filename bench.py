@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
 
 
 def log(*a):
@@ -171,20 +172,24 @@ def main():
                 "split_over_fp32": t32 / t_split,
                 "max_abs_diff_split_vs_fp32_over_max_B": float(np.max(np.abs(Bs[ok] - B32[ok])) / np.max(np.abs(B32[ok])))}
         log(f"[bench] fp32: {t32 * 1e3:.3f} ms/step, contraction {tim32[1]:.3f} ms")
-    # dominant kernel of the split step: the contraction (reads every shell field once)
-    nbu = len(np.unique(tri))
-    con_bytes = nbu * nvox * 4.0
+    # Dominant kernel of the split step: the fused eta-C2R + contraction (k3_fused).  It is bound
+    # by vector ALU / LDS instruction issue, not by HBM, so it is priced in algorithmic FP32
+    # flops per contracted voxel (M n^2 voxels on the M-point delay grid):
+    #   20 shells x 2.5 log2(M) (real inverse FFT along eta)
+    #   + one multiply per (b1, b2) pair of a valid triangle + one multiply-add per valid triangle
+    M = int(tim_split[3]) or w.nc
+    valid = tri[Nt > 0]
+    n_pairs = len({(int(a), int(b)) for a, b, _ in valid})
+    flops_per_vox = 20 * 2.5 * np.log2(M) + n_pairs + 2.0 * n_valid
+    vox_c = M * w.n * w.n
     con_ms = tim_split[1]
     fld_ms = tim_split[2]
-    if con_ms >= fld_ms:
-        roof = {"bound": "hbm", "kernel": "k3_contract<split-bf16>", "achieved": con_bytes / (con_ms * 1e-3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
-                "algorithmic_bytes": con_bytes, "avg_ms": con_ms}
-    else:
-        roof = {"bound": "hbm", "kernel": "3D field transforms", "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None, "avg_ms": fld_ms}
-    if roof.get("achieved") is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
+    ach = flops_per_vox * vox_c / (con_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "k3_fused<split-bf16> (eta C2R + contraction)", "achieved": ach,
+            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
+            "traffic": None, "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
+            "delay_grid_M": M, "avg_ms": con_ms,
+            "fields_kernels_ms": fld_ms}
     mabs = None
     if not args.no_mabs:
         log("[bench] MABS contraction: 133 ring triples x 8 nu1 rows")

@@ -169,7 +169,8 @@ int bs_estimate_3d(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_w
 /* ---- diagnostics ----
  * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP
  * events on the context's stream: out_ms_host[0] = whole call, [1] = the dominant contraction kernel,
- * [2] = fields/FFT kernels.  Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
+ * [2] = fields/FFT kernels, [3] = the delay-axis grid length M the last 3D
+ * contraction ran on (0 before any 3D call).  Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
 int bs_set_timing(bs_ctx* ctx, int32_t enable);
 int bs_last_timing(const bs_ctx* ctx, double* out_ms_host, int32_t n);
 /* Largest |x - rint(x)| over the FP64 triangle counts x of the last estimate (or of the cached

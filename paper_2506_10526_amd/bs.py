@@ -194,8 +194,8 @@ def bs_set_timing(ctx: int, enable: bool) -> None:
 
 
 def bs_last_timing(ctx: int):
-    out = (ctypes.c_double * 3)()
-    _check(ctx, lib().bs_last_timing(ctx, out, 3))
+    out = (ctypes.c_double * 4)()
+    _check(ctx, lib().bs_last_timing(ctx, out, 4))
     return list(out)
 
 
