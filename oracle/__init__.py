@@ -21,5 +21,7 @@ estimator   filtered fields, MABS and 3D estimators (Eqs. iFT, iFT_I, estimator_
 brute       direct enumeration of closed grid triangles (Sec. 3.2)
 theory      closed-form bispectrum of the quadratic field (Eq. mb1, Eq. bsana),
             N_nu sampling (Sec. 5, Fig. 2), route equivalence (Eq. dft)
+generator   counter-based (Philox4x64-10) seeded cubes of the quadratic field (Sec. 4),
+            the definition the GPU Monte Carlo generator is checked against
 """
-from . import bins, estimator, brute, theory  # noqa: F401
+from . import bins, estimator, brute, theory, generator  # noqa: F401
