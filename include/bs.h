@@ -166,6 +166,50 @@ int bs_estimate_mabs(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs
 int bs_estimate_3d(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_weights* w,
                    int32_t precision, double norm, double* B, int64_t* N_tri, double* N_eff);
 
+/* ---- seeded synthetic cubes (Sec. 4, Eq. mb1) ----
+ * One realization of the validation field on the GPU: white noise from Philox4x64-10 (Salmon et al.
+ * 2011) with key (seed, realization) and counter (i/4, 0, 0, 0) for voxel i = (z n + x) n + y, the
+ * four outputs turned into 24-bit uniforms ((x >> 40) + 1/2) 2^-24 and two Box-Muller pairs;
+ * g = irfftn(rfftn(white) sqrt(A P)), P = |k|^pk_index (P(0) = 0), A = sigma^2 N_vox / sum_k P;
+ * delta = g + f_ng (g^2 - mean g^2); V[z] = rfft2(delta[z]) * chan_w[z] (chan_w NULL = ones).
+ * Wave vectors: BS_K_CUBIC k = 2 pi (q_z/nc, q_x/n, q_y/n); BS_K_PHYSICAL k_par = 2 pi q_z /
+ * (rprime nc dnu), k_perp = 2 pi du_lambda |q| / r_mpc (Mpc^-1).
+ * vis: device complex64 [nc][n][n/2+1] (written).  Requires n % 4 == 0, n and nc of the form
+ * 2^a 3^b, nc even, n <= 1024, nc <= 1536 (BS_EINVAL otherwise).  Work is FP32 with FP64 sums. */
+#define BS_K_CUBIC 0
+#define BS_K_PHYSICAL 1
+typedef struct {
+  int32_t n, nc, kind;
+  double sigma, f_ng, pk_index;
+  double du_lambda, r_mpc, rprime_mpc_per_mhz, dnu_mhz;
+} bs_field_desc;
+int bs_generate_cube(bs_ctx* ctx, const bs_field_desc* desc, uint64_t seed, uint64_t realization,
+                     const float* chan_w, void* vis);
+
+/* ---- Monte Carlo over seeded realizations of the 3D estimator (Sec. 4: ensemble means and
+ * errors from independent realizations) ----
+ * bs_mc_create: plan R realizations of desc's field through bs_estimate_3d with `bins` (BS_SHELL_K,
+ *   same n and nc), weights `w` (separable; chan_w also zeroes the generated channels), precision
+ *   BS_FP32 or BS_SPLIT_BF16 and `norm`.  The object owns its cube, field and accumulator buffers
+ *   and its own HIP stream; bins and the weight arrays are borrowed and must outlive it.
+ * bs_mc_run: realizations first .. first+count-1 of `seed`, each generated, estimated and added
+ *   to FP64 per-triangle accumulators (count, mean, M2; Welford) on the device.  use_graph != 0
+ *   captures one realization into a hipGraph on the first call and replays it (the realization
+ *   index advances on the device); 0 launches the kernels directly.  Ordered after earlier work on
+ *   the context's stream, and later work on that stream waits for it.
+ * bs_mc_stats: per candidate triangle (host arrays [n_cand], each nullable): realizations
+ *   accumulated (0 where N_tri = 0), mean B and unbiased variance (NaN with fewer than 2).
+ * bs_mc_last: B and N_tri of the last realization (host arrays [n_cand], nullable).
+ * bs_mc_reset: zero the accumulators.  bs_mc_destroy: free everything (NULL is a no-op). */
+typedef struct bs_mc bs_mc;
+int bs_mc_create(bs_ctx* ctx, const bs_bins* bins, const bs_field_desc* desc, const bs_weights* w,
+                 int32_t precision, double norm, bs_mc** out);
+int bs_mc_run(bs_mc* mc, uint64_t seed, uint64_t first_realization, int32_t count, int32_t use_graph);
+int bs_mc_stats(bs_mc* mc, int64_t* n_host, double* mean_host, double* var_host);
+int bs_mc_last(bs_mc* mc, double* B_host, int64_t* N_host);
+int bs_mc_reset(bs_mc* mc);
+void bs_mc_destroy(bs_mc* mc);
+
 /* ---- diagnostics ----
  * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP
  * events on the context's stream: out_ms_host[0] = whole call, [1] = the dominant contraction kernel,

@@ -21,8 +21,10 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
     "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_estimate_3d",
-    "bs_set_timing", "bs_last_timing", "bs_last_count_dev",
+    "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
+    "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy",
 ]
+BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
 
 
 class BsError(RuntimeError):
@@ -46,6 +48,13 @@ class bs_mabs_sel(ctypes.Structure):
     _fields_ = [("n_tri", ctypes.c_int32), ("tri3_host", ctypes.POINTER(ctypes.c_int32)),
                 ("n_nu1", ctypes.c_int32), ("nu1_host", ctypes.POINTER(ctypes.c_int32)),
                 ("collapse", ctypes.c_int32)]
+
+
+class bs_field_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nc", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("f_ng", ctypes.c_double), ("pk_index", ctypes.c_double),
+                ("du_lambda", ctypes.c_double), ("r_mpc", ctypes.c_double),
+                ("rprime_mpc_per_mhz", ctypes.c_double), ("dnu_mhz", ctypes.c_double)]
 
 
 _lib = None
@@ -78,8 +87,18 @@ def lib() -> ctypes.CDLL:
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
+    u64 = ctypes.c_uint64
+    L.bs_generate_cube.argtypes = [vp, ctypes.POINTER(bs_field_desc), u64, u64, vp, vp]
+    L.bs_mc_create.argtypes = [vp, vp, ctypes.POINTER(bs_field_desc), ctypes.POINTER(bs_weights), i32, dbl,
+                               ctypes.POINTER(vp)]
+    L.bs_mc_run.argtypes = [vp, u64, u64, i32, i32]
+    L.bs_mc_stats.argtypes = [vp, vp, vp, vp]
+    L.bs_mc_last.argtypes = [vp, vp, vp]
+    L.bs_mc_reset.argtypes = [vp]
+    L.bs_mc_destroy.argtypes = [vp]
+    L.bs_mc_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins"):
+        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -203,3 +222,57 @@ def bs_last_count_dev(ctx: int) -> float:
     d = ctypes.c_double()
     _check(ctx, lib().bs_last_count_dev(ctx, ctypes.byref(d)))
     return d.value
+
+
+def field_desc(n: int, nc: int, kind: int = BS_K_CUBIC, sigma: float = 0.5, f_ng: float = 0.5,
+               pk_index: float = -2.0, du_lambda: float = 1.0, r_mpc: float = 1.0,
+               rprime_mpc_per_mhz: float = 1.0, dnu_mhz: float = 1.0) -> bs_field_desc:
+    return bs_field_desc(n, nc, kind, sigma, f_ng, pk_index, du_lambda, r_mpc, rprime_mpc_per_mhz, dnu_mhz)
+
+
+def bs_generate_cube(ctx: int, desc: bs_field_desc, seed: int, realization: int, vis, chan_w=None) -> None:
+    """vis: complex64 device tensor [nc][n][n/2+1] (written)."""
+    _check(ctx, lib().bs_generate_cube(ctx, ctypes.byref(desc), seed, realization, _ptr(chan_w), _ptr(vis)))
+
+
+_mc_ctx = {}
+
+
+def bs_mc_create(ctx: int, bins: int, desc: bs_field_desc, precision: int, norm: float = 1.0,
+                 uv_mask=None, chan_w=None) -> int:
+    w = bs_weights(None, _ptr(uv_mask), _ptr(chan_w))
+    h = ctypes.c_void_p()
+    _check(ctx, lib().bs_mc_create(ctx, bins, ctypes.byref(desc), ctypes.byref(w), precision, norm, ctypes.byref(h)))
+    _mc_ctx[h.value] = ctx
+    return h.value
+
+
+def bs_mc_run(mc: int, seed: int, first_realization: int, count: int, use_graph: bool = True) -> None:
+    _check(_mc_ctx.get(mc), lib().bs_mc_run(mc, seed, first_realization, count, 1 if use_graph else 0))
+
+
+def bs_mc_stats(mc: int, n_cand: int):
+    """(count int64, mean float64, var float64) per candidate triangle, as NumPy arrays."""
+    import numpy as np
+    cnt = np.zeros(n_cand, dtype=np.int64)
+    mean = np.zeros(n_cand, dtype=np.float64)
+    var = np.zeros(n_cand, dtype=np.float64)
+    _check(_mc_ctx.get(mc), lib().bs_mc_stats(mc, cnt.ctypes.data, mean.ctypes.data, var.ctypes.data))
+    return cnt, mean, var
+
+
+def bs_mc_last(mc: int, n_cand: int):
+    import numpy as np
+    B = np.zeros(n_cand, dtype=np.float64)
+    N = np.zeros(n_cand, dtype=np.int64)
+    _check(_mc_ctx.get(mc), lib().bs_mc_last(mc, B.ctypes.data, N.ctypes.data))
+    return B, N
+
+
+def bs_mc_reset(mc: int) -> None:
+    _check(_mc_ctx.get(mc), lib().bs_mc_reset(mc))
+
+
+def bs_mc_destroy(mc: int) -> None:
+    lib().bs_mc_destroy(mc)
+    _mc_ctx.pop(mc, None)

@@ -9,6 +9,7 @@
 
 #include "bs_ctx.h"
 #include "bs_kernels.h"
+#include "bs_est3.h"
 
 #define HIPCHK(ctx, call)                                                                         \
   do {                                                                                            \
@@ -22,21 +23,6 @@
     hipError_t e_ = hipGetLastError();                                                            \
     if (e_ != hipSuccess) return ctx_fail(ctx, BS_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
   } while (0)
-
-namespace {
-
-// Host-side description of the shell blocks a 3D call works on.
-struct Plan3 {
-  std::vector<int> blocks;        // shell id per block
-  std::vector<int> hj;            // largest |eta| per block
-  std::vector<long long> offT, offG;
-  long long totT = 0, totG = 0;
-  int H = 0;
-  std::vector<Work3> wv, wu, we;
-  int NLv = 16, NLu = 16, NLe = 16, NLd = 8;
-};
-
-const int kMaxFields = 32, kMaxPairs = 112;
 
 void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp64, Plan3& p) {
   const int n = P.n, nub = 2 * P.vmax + 1;
@@ -65,82 +51,101 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
   }
 }
 
+namespace {
+
 template <typename X>
-X* upload(bs_ctx* c, const char* name, const std::vector<X>& v, int& rc) {
-  X* d = (X*)ctx_ws(c, name, std::max<size_t>(v.size() * sizeof(X), 16));
-  if (!d) { rc = ctx_fail(c, BS_ENOMEM, std::string("workspace ") + name); return nullptr; }
+X* upload(bs_ctx* c, const std::string& name, const std::vector<X>& v, int& rc) {
+  X* d = (X*)ctx_ws(c, name.c_str(), std::max<size_t>(v.size() * sizeof(X), 16));
+  if (!d) { rc = ctx_fail(c, BS_ENOMEM, "workspace " + name); return nullptr; }
   if (!v.empty() && hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-    rc = ctx_fail(c, BS_EHIP, std::string("upload ") + name);
+    rc = ctx_fail(c, BS_EHIP, "upload " + name);
     return nullptr;
   }
   rc = BS_OK;
   return d;
 }
 
-// Runs the field pipeline for `blocks`; fields land in `F` ([block][M n^2], type by fp64).
-// indicator: unit indicator of shell and support instead of data (no delay transform).
-int run_fields3(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64, bool indicator,
-                Plan3& p, void* F, const char* tag, void** G_out = nullptr, long long** offG_out = nullptr,
-                int** hj_out = nullptr) {
+int fields3_prepare(bs_ctx* c, const bs_bins* b, bool fp64, bool indicator, const Plan3& p, const std::string& t,
+                    Fields3Dev& fd) {
   const auto& P = b->P;
   const int n = P.n, nc = P.nc, nh = P.nh, nub = 2 * P.vmax + 1, nvb = P.vmax + 1;
   const size_t cz = fp64 ? 16 : 8;
   int rc = BS_OK;
-  std::string t(tag);
-  Shell3Geom g{};
+  fd.fp64 = fp64;
+  fd.indicator = indicator;
+  Shell3Geom& g = fd.g;
   g.n = n; g.nh = nh; g.nc = nc; g.vmax = P.vmax; g.nub = nub; g.nvb = nvb;
   g.H = p.H; g.smax = P.smax; g.S1 = P.smax + 1;
   g.lut = b->d_lut;
-  g.uvm = w ? w->uv_mask : nullptr;
-  const void* tw_nc = ctx_twiddle(c, nc, fp64);
-  const void* tw_n = ctx_twiddle(c, n, fp64);
-  if (!tw_nc || !tw_n) return ctx_fail(c, BS_ENOMEM, "twiddle tables");
-  void* D = nullptr;
+  g.uvm = nullptr;
+  fd.tw_nc = ctx_twiddle(c, nc, fp64);
+  fd.tw_n = ctx_twiddle(c, n, fp64);
+  if (!fd.tw_nc || !fd.tw_n) return ctx_fail(c, BS_ENOMEM, "twiddle tables");
+  fd.D = nullptr;
   if (!indicator) {
-    D = ctx_ws(c, (t + "_D").c_str(), (size_t)(2 * p.H + 1) * nub * nvb * cz);
-    if (!D) return ctx_fail(c, BS_ENOMEM, "workspace (delay)");
+    fd.D = ctx_ws(c, (t + "_D").c_str(), (size_t)(2 * p.H + 1) * nub * nvb * cz);
+    if (!fd.D) return ctx_fail(c, BS_ENOMEM, "workspace (delay)");
+  }
+  fd.Tm = ctx_ws(c, (t + "_T").c_str(), (size_t)p.totT * cz);
+  fd.Gm = ctx_ws(c, (t + "_G").c_str(), (size_t)p.totG * cz);
+  if (!fd.Tm || !fd.Gm) return ctx_fail(c, BS_ENOMEM, "workspace (3D passes)");
+  fd.d_shell = upload(c, t + "_shell", p.blocks, rc); if (rc) return rc;
+  fd.d_hj = upload(c, t + "_hj", p.hj, rc); if (rc) return rc;
+  fd.d_offT = upload(c, t + "_offT", p.offT, rc); if (rc) return rc;
+  fd.d_offG = upload(c, t + "_offG", p.offG, rc); if (rc) return rc;
+  fd.d_wv = upload(c, t + "_wv", p.wv, rc); if (rc) return rc;
+  fd.d_wu = upload(c, t + "_wu", p.wu, rc); if (rc) return rc;
+  fd.d_we = upload(c, t + "_we", p.we, rc); if (rc) return rc;
+  return BS_OK;
+}
+
+// Launches the field pipeline prepared in `fd` (no allocation, copy or synchronisation).
+// With F != NULL the eta pass writes the real fields F ([block][nc n^2]); with F == NULL the
+// pipeline stops after the u pass and the caller consumes the line-major spectra fd.Gm.
+int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3& p, Fields3Dev& fd, void* F) {
+  const int n = fd.g.n, nc = fd.g.nc;
+  const size_t cz = fd.fp64 ? 16 : 8;
+  Shell3Geom g = fd.g;
+  g.uvm = w ? w->uv_mask : nullptr;
+  if (!fd.indicator) {
     Delay3Args d{};
-    d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = D; d.tw = tw_nc;
+    d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = fd.D; d.tw = fd.tw_nc;
     d.plan = make_fft_plan(nc); d.NL = p.NLd;
     size_t lds = 2 * (size_t)p.NLd * (nc + 1) * cz;
-    if (fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
+    if (fd.fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
     LAUNCHCHK(c, "delay transform");
   }
-  void* Tm = ctx_ws(c, (t + "_T").c_str(), (size_t)p.totT * cz);
-  void* Gm = ctx_ws(c, (t + "_G").c_str(), (size_t)p.totG * cz);
-  if (!Tm || !Gm) return ctx_fail(c, BS_ENOMEM, "workspace (3D passes)");
-  int* d_shell = upload(c, (t + "_shell").c_str(), p.blocks, rc); if (rc) return rc;
-  int* d_hj = upload(c, (t + "_hj").c_str(), p.hj, rc); if (rc) return rc;
-  long long* d_offT = upload(c, (t + "_offT").c_str(), p.offT, rc); if (rc) return rc;
-  long long* d_offG = upload(c, (t + "_offG").c_str(), p.offG, rc); if (rc) return rc;
-  Work3* d_wv = upload(c, (t + "_wv").c_str(), p.wv, rc); if (rc) return rc;
-  Work3* d_wu = upload(c, (t + "_wu").c_str(), p.wu, rc); if (rc) return rc;
-  Work3* d_we = upload(c, (t + "_we").c_str(), p.we, rc); if (rc) return rc;
   Pass3Args a{};
-  a.g = g; a.shell_of_block = d_shell; a.hj = d_hj;
+  a.g = g; a.shell_of_block = fd.d_shell; a.hj = fd.d_hj;
   // v pass
-  a.work = d_wv; a.off_in = nullptr; a.off_out = d_offT; a.in = D; a.out = Tm; a.tw = tw_n;
-  a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = indicator ? 1 : 0;
-  launch_vpass3(a, (int)p.wv.size(), fp64, c->stream, 2 * (size_t)p.NLv * (n + 1) * cz);
+  a.work = fd.d_wv; a.off_in = nullptr; a.off_out = fd.d_offT; a.in = fd.D; a.out = fd.Tm; a.tw = fd.tw_n;
+  a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = fd.indicator ? 1 : 0;
+  launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, 2 * (size_t)p.NLv * (n + 1) * cz);
   LAUNCHCHK(c, "v pass");
   // u pass
-  a.work = d_wu; a.off_in = d_offT; a.off_out = d_offG; a.in = Tm; a.out = Gm; a.NL = p.NLu;
-  launch_upass3(a, (int)p.wu.size(), fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
+  a.work = fd.d_wu; a.off_in = fd.d_offT; a.off_out = fd.d_offG; a.in = fd.Tm; a.out = fd.Gm; a.NL = p.NLu;
+  launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
   LAUNCHCHK(c, "u pass");
-  if (G_out) {  // the caller fuses the eta pass with the contraction
-    *G_out = Gm; *offG_out = d_offG; *hj_out = d_hj;
-    return BS_OK;
-  }
+  if (!F) return BS_OK;
   // eta pass (C2R), output length nc
   const int M = nc;
-  if (M % 2) return ctx_fail(c, BS_EUNSUPPORTED, "3D fields need an even number of channels");
-  a.work = d_we; a.off_in = d_offG; a.off_out = nullptr; a.in = Gm; a.out = F;
-  a.tw = tw_nc; a.plan = make_fft_plan(M / 2); a.NL = p.NLe; a.M = M;
+  a.work = fd.d_we; a.off_in = fd.d_offG; a.off_out = nullptr; a.in = fd.Gm; a.out = F;
+  a.tw = fd.tw_nc; a.plan = make_fft_plan(M / 2); a.NL = p.NLe; a.M = M;
   a.scale = 1.0 / ((double)M * (double)n * (double)n);
   a.fstride = (long long)M * n * n;
-  launch_etapass3(a, (int)p.we.size(), fp64, c->stream, 2 * (size_t)p.NLe * (M / 2 + 1) * cz);
+  launch_etapass3(a, (int)p.we.size(), fd.fp64, c->stream, 2 * (size_t)p.NLe * (M / 2 + 1) * cz);
   LAUNCHCHK(c, "eta pass");
   return BS_OK;
+}
+
+// Both steps at once (fields output, count pass).
+int run_fields3(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64, bool indicator,
+                const Plan3& p, void* F, const std::string& tag) {
+  if (b->P.nc % 2) return ctx_fail(c, BS_EUNSUPPORTED, "3D fields need an even number of channels");
+  Fields3Dev fd;
+  int rc = fields3_prepare(c, b, fp64, indicator, p, tag, fd);
+  if (rc) return rc;
+  return fields3_enqueue(c, vis, w, p, fd, F);
 }
 
 int check_3d_inputs(bs_ctx* c, const bs_bins* b, const bs_weights* w) {
@@ -186,25 +191,24 @@ int filter_fields_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weig
   return BS_OK;
 }
 
-extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, int32_t precision,
-                              double norm, double* B, int64_t* N_tri, double* N_eff) {
-  if (!c || !b || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_estimate_3d: NULL context or host-only bins");
-  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t precision, const std::string& tag,
+                 Est3& e) {
   int rc = check_3d_inputs(c, b, w);
   if (rc) return rc;
-  if (!vis || !B || !N_tri) return ctx_fail(c, BS_EINVAL, "vis, B and N_tri must be non-NULL");
   if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
   const auto& P = b->P;
-  const int ntri = (int)(P.tri.size() / 3);
-  if (ntri == 0) return BS_OK;
-  const bool fp64 = precision == BS_FP64;
-  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  e.tag = tag;
+  e.precision = precision;
+  e.fp64 = precision == BS_FP64;
+  e.ntri = (int)(P.tri.size() / 3);
+  if (e.ntri == 0) return BS_OK;
+  const int ntri = e.ntri;
   // ---- blocks, pairs, triangle -> (pair, column) ----
   std::map<int, int> blk;
   for (int x : P.tri) blk.emplace(x, 0);
-  std::vector<int> blocks;
-  for (auto& kv : blk) { kv.second = (int)blocks.size(); blocks.push_back(kv.first); }
-  if ((int)blocks.size() > kMaxFields) return ctx_fail(c, BS_EUNSUPPORTED, "more than 32 shells in use");
+  e.blocks.clear();
+  for (auto& kv : blk) { kv.second = (int)e.blocks.size(); e.blocks.push_back(kv.first); }
+  if ((int)e.blocks.size() > kMaxFields) return ctx_fail(c, BS_EUNSUPPORTED, "more than 32 shells in use");
   std::map<std::pair<int, int>, int> pr;
   std::vector<int> pairs, tpair(ntri), tcol(ntri);
   for (int t = 0; t < ntri; ++t) {
@@ -218,26 +222,26 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     tpair[t] = it->second;
     tcol[t] = blk[P.tri[3 * t + 2]];
   }
-  const int npairs = (int)(pairs.size() / 2);
-  if (npairs > kMaxPairs) return ctx_fail(c, BS_EUNSUPPORTED, "more than 112 shell pairs in use");
-  const long long nvox = (long long)P.nc * P.n * P.n;
-  int* d_pairs = upload(c, "c3_pairs", pairs, rc); if (rc) return rc;
-  int* d_tp = upload(c, "c3_tpair", tpair, rc); if (rc) return rc;
-  int* d_tc = upload(c, "c3_tcol", tcol, rc); if (rc) return rc;
-  long long nblk = std::min<long long>(2048, (nvox + 127) / 128);
-  long long chunk = ((nvox + nblk - 1) / nblk + 127) / 128 * 128;
-  nblk = (nvox + chunk - 1) / chunk;
-  double* partial = (double*)ctx_ws(c, "c3_partial", (size_t)std::max<long long>(nblk, 1024) * 112 * 32 * 8);
-  double* reduced = (double*)ctx_ws(c, "c3_reduced", (size_t)112 * 32 * 8);
-  if (!partial || !reduced) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
-  double rho3 = 1.0;
+  e.npairs = (int)(pairs.size() / 2);
+  if (e.npairs > kMaxPairs) return ctx_fail(c, BS_EUNSUPPORTED, "more than 112 shell pairs in use");
+  e.nvox = (long long)P.nc * P.n * P.n;
+  e.d_pairs = upload(c, tag + "_pairs", pairs, rc); if (rc) return rc;
+  e.d_tp = upload(c, tag + "_tpair", tpair, rc); if (rc) return rc;
+  e.d_tc = upload(c, tag + "_tcol", tcol, rc); if (rc) return rc;
+  e.nblk = std::min<long long>(2048, (e.nvox + 127) / 128);
+  e.chunk = ((e.nvox + e.nblk - 1) / e.nblk + 127) / 128 * 128;
+  e.nblk = (e.nvox + e.chunk - 1) / e.chunk;
+  e.partial = (double*)ctx_ws(c, (tag + "_partial").c_str(), (size_t)std::max<long long>(e.nblk, 1024) * 112 * 32 * 8);
+  e.reduced = (double*)ctx_ws(c, (tag + "_reduced").c_str(), (size_t)112 * 32 * 8);
+  if (!e.partial || !e.reduced) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
+  e.rho3 = 1.0;
   if (w && w->chan_w) {
     std::vector<float> hw(P.nc);
     HIPCHK(c, hipMemcpyAsync(hw.data(), w->chan_w, P.nc * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double s = 0;
     for (float x : hw) s += (double)x * x * x;
-    rho3 = s / P.nc;
+    e.rho3 = s / P.nc;
   }
   // ---- counts (FP64, cached per geometry and uv support) ----
   uint64_t key = P.hash ^ 0x3d3d3d3d3d3d3d3dULL;
@@ -249,24 +253,25 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   }
   auto it = c->counts.find(key);
   if (it == c->counts.end()) {
+    const long long nvox = e.nvox;
     Plan3 pc;
-    build_plan3(P, blocks, true, pc);
-    void* F64 = ctx_ws(c, "c3_F64", (size_t)blocks.size() * nvox * 8);
+    build_plan3(P, e.blocks, true, pc);
+    void* F64 = ctx_ws(c, "c3_F64", (size_t)e.blocks.size() * nvox * 8);
     if (!F64) return ctx_fail(c, BS_ENOMEM, "workspace (count fields)");
     rc = run_fields3(c, b, nullptr, w, true, true, pc, F64, "c3c");
     if (rc) return rc;
     Con3Args ca{};
-    ca.F = F64; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
-    ca.chunk = chunk; ca.partial = partial;
-    launch_contract3(ca, 0, (int)nblk, c->stream);
+    ca.F = F64; ca.vox = nvox; ca.nbu = (int)e.blocks.size(); ca.pairs = e.d_pairs; ca.npairs = e.npairs;
+    ca.chunk = e.chunk; ca.partial = e.partial;
+    launch_contract3(ca, 0, (int)e.nblk, c->stream);
     LAUNCHCHK(c, "count contraction");
     double* Ssum = (double*)ctx_ws(c, "c3_Ssum", (size_t)ntri * 8 + 16);
     unsigned long long* bad = (unsigned long long*)ctx_ws(c, "count_dev", 256);
     if (!Ssum || !bad) return ctx_fail(c, BS_ENOMEM, "workspace (count sums)");
     Fin3Args f{};
-    f.partial = partial; f.nparts = (int)nblk; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
+    f.partial = e.partial; f.nparts = (int)e.nblk; f.tri_pair = e.d_tp; f.tri_col = e.d_tc; f.ntri = ntri;
     f.T3D = nullptr; f.Ssum = Ssum; f.sfac = (double)nvox * (double)nvox;
-    launch_fin3(f, reduced, c->stream);
+    launch_fin3(f, e.reduced, c->stream);
     LAUNCHCHK(c, "count finalize");
     CountCache cc;
     if (hipMalloc(&cc.d_counts, (size_t)ntri * 8) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "count cache"); }
@@ -281,12 +286,11 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     cc.dev = dev;
     cc.tri.assign(P.tri.begin(), P.tri.end());
     it = c->counts.emplace(key, std::move(cc)).first;
-    if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
   }
-  c->last_count_dev = it->second.dev;
+  e.d_counts = it->second.d_counts;
+  e.count_dev = it->second.dev;
   // ---- data fields and contraction ----
-  Plan3 pd;
-  build_plan3(P, blocks, fp64, pd);
+  build_plan3(P, e.blocks, e.fp64, e.pd);
   // Delay-axis grid of the fused path.  With true closure (3 H < nc) any grid M > 3 H closes the
   // same triangles as the nc grid, so the smallest FFT-friendly multiple of 128 above 3 H is used
   // and the sums are rescaled by (M / nc)^2 (sum over M n^2 voxels of fields normalised by
@@ -296,59 +300,94 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
     for (int m = 128; m < P.nc; m += 128)
       if (m > 3 * P.eta_max && fft_len_ok(m) && P.nc % 2 == 0) { M = m; break; }
   }
-  const bool fused = !fp64 && (M % 128 == 0) && !getenv("BS_3D_UNFUSED");
-  if (!fused) M = P.nc;
-  const double sfac = ((double)M / P.nc) * ((double)M / P.nc);
-  int nparts = (int)nblk;
-  if (fused) {
-    void* G = nullptr;
-    long long* d_offG = nullptr;
-    int* d_hj = nullptr;
-    rc = run_fields3(c, b, vis, w, false, false, pd, nullptr, "c3d", &G, &d_offG, &d_hj);
-    if (rc) return rc;
-    if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  e.fused = !e.fp64 && (M % 128 == 0) && !getenv("BS_3D_UNFUSED");
+  if (!e.fused) M = P.nc;
+  e.M = M;
+  e.sfac = ((double)M / P.nc) * ((double)M / P.nc);
+  rc = fields3_prepare(c, b, e.fp64, false, e.pd, tag + "d", e.fd);
+  if (rc) return rc;
+  if (e.fused) {
     const long long nlines = (long long)P.n * P.n;
-    const int fblocks = (int)std::min<long long>(nlines, 512);
-    Fused3Args fa{};
-    fa.G = G; fa.offG = d_offG; fa.hj = d_hj; fa.nbu = (int)blocks.size(); fa.nlines = nlines; fa.M = M;
+    e.fblocks = (int)std::min<long long>(nlines, 512);
+    Fused3Args& fa = e.fa;
+    fa = Fused3Args{};
+    fa.G = e.fd.Gm; fa.offG = e.fd.d_offG; fa.hj = e.fd.d_hj; fa.nbu = (int)e.blocks.size(); fa.nlines = nlines;
+    fa.M = M;
     fa.plan = make_fft_plan(M / 2);
     fa.tw = ctx_twiddle(c, M, false);
     if (!fa.tw) return ctx_fail(c, BS_ENOMEM, "twiddle table");
     fa.scale = 1.0 / ((double)M * (double)P.n * (double)P.n);
-    fa.pairs = d_pairs; fa.npairs = npairs;
-    fa.lines_per_block = (nlines + fblocks - 1) / fblocks;
-    fa.partial = partial;
+    fa.pairs = e.d_pairs; fa.npairs = e.npairs;
+    fa.lines_per_block = (nlines + e.fblocks - 1) / e.fblocks;
+    fa.partial = e.partial;
     const size_t ld = (size_t)M / 2 + 2;
     int stage_len = 0;
-    for (int h : pd.hj) stage_len += h + 1;
+    for (int h : e.pd.hj) stage_len += h + 1;
     if (stage_len > 512) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction: more than 512 delay modes per line");
     // FFT buffers, twiddles, two spectrum stages, pair table, prefix and slot tables
     size_t lds = 2 * fa.nbu * ld * 8 + (size_t)M * 8 + 2 * 512 * 8 + (224 + 33 + 512) * 4;
     lds = std::max<size_t>(lds, 112 * 32 * 8);
     if (lds > 160 * 1024) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction does not fit in LDS");
-    launch_fused3(fa, precision == BS_FP32 ? 1 : 2, fblocks, lds, c->stream);
-    LAUNCHCHK(c, "fused contraction");
-    nparts = fblocks;
+    e.lds = lds;
   } else {
-    void* F = ctx_ws(c, "c3_F", (size_t)blocks.size() * nvox * (fp64 ? 8 : 4));
-    if (!F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
-    rc = run_fields3(c, b, vis, w, fp64, false, pd, F, "c3d");
+    e.F = ctx_ws(c, (tag + "_F").c_str(), (size_t)e.blocks.size() * e.nvox * (e.fp64 ? 8 : 4));
+    if (!e.F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
+  }
+  return BS_OK;
+}
+
+// Launches one estimate of the prepared plan on `vis` (no allocation, copy or synchronisation,
+// so it may be captured into a graph).
+int est3_enqueue(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, Est3& e, double norm, double* B,
+                 int64_t* N_tri, double* N_eff) {
+  if (e.ntri == 0) return BS_OK;
+  int rc;
+  int nparts = (int)e.nblk;
+  if (e.fused) {
+    rc = fields3_enqueue(c, vis, w, e.pd, e.fd, nullptr);
+    if (rc) return rc;
+    if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+    launch_fused3(e.fa, e.precision == BS_FP32 ? 1 : 2, e.fblocks, e.lds, c->stream);
+    LAUNCHCHK(c, "fused contraction");
+    nparts = e.fblocks;
+  } else {
+    rc = fields3_enqueue(c, vis, w, e.pd, e.fd, e.F);
     if (rc) return rc;
     if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
     Con3Args ca{};
-    ca.F = F; ca.vox = nvox; ca.nbu = (int)blocks.size(); ca.pairs = d_pairs; ca.npairs = npairs;
-    ca.chunk = chunk; ca.partial = partial;
-    launch_contract3(ca, fp64 ? 0 : (precision == BS_FP32 ? 1 : 2), (int)nblk, c->stream);
+    ca.F = e.F; ca.vox = e.nvox; ca.nbu = (int)e.blocks.size(); ca.pairs = e.d_pairs; ca.npairs = e.npairs;
+    ca.chunk = e.chunk; ca.partial = e.partial;
+    launch_contract3(ca, e.fp64 ? 0 : (e.precision == BS_FP32 ? 1 : 2), (int)e.nblk, c->stream);
     LAUNCHCHK(c, "contraction");
   }
   if (c->timing) (void)hipEventRecord(c->ev[3], c->stream);
   Fin3Args f{};
-  f.partial = partial; f.nparts = nparts; f.tri_pair = d_tp; f.tri_col = d_tc; f.ntri = ntri;
-  f.T3D = it->second.d_counts; f.rho3 = rho3; f.nvox = (double)nvox; f.norm = norm; f.sfac = sfac;
+  f.partial = e.partial; f.nparts = nparts; f.tri_pair = e.d_tp; f.tri_col = e.d_tc; f.ntri = e.ntri;
+  f.T3D = e.d_counts; f.rho3 = e.rho3; f.nvox = (double)e.nvox; f.norm = norm; f.sfac = e.sfac;
   f.B = B; f.N = N_tri; f.Neff = N_eff;
-  c->last_grid_M = M;
-  launch_fin3(f, reduced, c->stream);
+  launch_fin3(f, e.reduced, c->stream);
   LAUNCHCHK(c, "finalize");
+  (void)b;
+  return BS_OK;
+}
+
+extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, int32_t precision,
+                              double norm, double* B, int64_t* N_tri, double* N_eff) {
+  if (!c || !b || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_estimate_3d: NULL context or host-only bins");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  int rc = check_3d_inputs(c, b, w);
+  if (rc) return rc;
+  if (!vis || !B || !N_tri) return ctx_fail(c, BS_EINVAL, "vis, B and N_tri must be non-NULL");
+  if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  Est3 e;
+  rc = est3_prepare(c, b, w, precision, "c3", e);
+  if (rc) return rc;
+  if (e.ntri == 0) return BS_OK;
+  c->last_count_dev = e.count_dev;
+  rc = est3_enqueue(c, b, vis, w, e, norm, B, N_tri, N_eff);
+  if (rc) return rc;
+  c->last_grid_M = e.M;
   if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
   return BS_OK;
 }
