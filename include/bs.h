@@ -210,6 +210,46 @@ int bs_mc_last(bs_mc* mc, double* B_host, int64_t* N_host);
 int bs_mc_reset(bs_mc* mc);
 void bs_mc_destroy(bs_mc* mc);
 
+/* ---- learned variance surrogate ----
+ * Not part of the paper, which takes error bars from the scatter of independent realizations
+ * (Sec. 4, Sec. 5): a 4 -> 256 -> 256 -> 256 -> 1 MLP with SiLU hidden units predicts log Var(B)
+ * of a triangle from (log k1, log k2, log k3, rho), k_i the geometric centres of its shells
+ * (Mpc^-1) and rho = sum_nu w(nu) / nc the flag summary, relative to the Gaussian-shaped baseline
+ * log(N_vox / T3D) + n_s sum_i log k_i (P ~ k^n_s).  Training runs on the GPU in FP32 (hand-written
+ * forward, backward and Adam kernels, one training step captured into a hipGraph and replayed);
+ * prediction runs in FP32 or BF16 (MFMA).  Monte Carlo (bs_mc_*) makes the labels and judges it.
+ * State: BS_MLP_NSTATE floats on the device: the 133,121 parameters (W1 [256][4], b1, W2 [256][256],
+ *   b2, W3 [256][256], b3, w4 [256], b4, row-major) then mu_x[4], s_x[4], mu_t, s_t (normalisation
+ *   x' = (x - mu_x) / s_x, t' = (t - mu_t) / s_t, fitted by bs_mlp_set_data).
+ * bs_mlp_read_state / bs_mlp_write_state: copy the state to / from a host array (synchronising);
+ *   a written state replaces parameters and normalisation (e.g. a saved, trained surrogate).
+ * bs_mlp_create: parameters drawn from Philox4x64-10 with key (seed, 0x4D4C50), uniform in
+ *   +-1/sqrt(fan_in); Adam moments zero.  max_batch bounds the training and prediction batch sizes.
+ * bs_mlp_set_data: training inputs X (device float [n][4]) and targets t (device float [n]) are
+ *   normalised into the object (the caller's arrays are not kept).
+ * bs_mlp_loss_grad: loss = mean (y' - t')^2 and its gradient (device float [BS_MLP_NPARAM], nullable)
+ *   at the current parameters.
+ * bs_mlp_train: `steps` full-batch Adam steps (b1 0.9, b2 0.999, eps 1e-8; learning rate lr, or
+ *   lr (1 + cos(pi k / steps)) / 2 at step k of this call when cosine != 0).  loss_host: the loss
+ *   evaluated in the last step (before its update).
+ * bs_mlp_predict: t = mu_t + s_t y'(x') for X (device float [n][4]) into y (device float [n]);
+ *   bf16 != 0 evaluates layers 2-4 with bfloat16 weights and activations (FP32 accumulation).
+ * bs_var_features (host only): X_host [n_cand][4] and, when T3D_host is given, base_host [n_cand]
+ *   (the baseline above; -inf where T3D = 0) for the candidate triangles of 3D bins. */
+#define BS_MLP_NPARAM 133121
+#define BS_MLP_NSTATE 133131
+typedef struct bs_mlp bs_mlp;
+int bs_mlp_create(bs_ctx* ctx, uint64_t seed, int32_t max_batch, bs_mlp** out);
+int bs_mlp_read_state(bs_mlp* mlp, float* state_host);
+int bs_mlp_write_state(bs_mlp* mlp, const float* state_host);
+int bs_mlp_set_data(bs_mlp* mlp, const float* X, const float* t, int32_t n);
+int bs_mlp_loss_grad(bs_mlp* mlp, float* grad, double* loss_host);
+int bs_mlp_train(bs_mlp* mlp, int32_t steps, double lr, int32_t cosine, double* loss_host);
+int bs_mlp_predict(bs_mlp* mlp, const float* X, int32_t n, int32_t bf16, float* y);
+void bs_mlp_destroy(bs_mlp* mlp);
+int bs_var_features(const bs_bins* bins, const int64_t* T3D_host, double pk_index, double rho, float* X_host,
+                    double* base_host);
+
 /* ---- diagnostics ----
  * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP
  * events on the context's stream: out_ms_host[0] = whole call, [1] = the dominant contraction kernel,

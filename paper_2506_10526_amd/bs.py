@@ -22,8 +22,10 @@ EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
     "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
-    "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy",
+    "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
+    "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
 ]
+BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
 
 
@@ -97,8 +99,18 @@ def lib() -> ctypes.CDLL:
     L.bs_mc_reset.argtypes = [vp]
     L.bs_mc_destroy.argtypes = [vp]
     L.bs_mc_destroy.restype = None
+    L.bs_mlp_create.argtypes = [vp, u64, i32, ctypes.POINTER(vp)]
+    L.bs_mlp_read_state.argtypes = [vp, vp]
+    L.bs_mlp_write_state.argtypes = [vp, vp]
+    L.bs_mlp_set_data.argtypes = [vp, vp, vp, i32]
+    L.bs_mlp_loss_grad.argtypes = [vp, vp, ctypes.POINTER(dbl)]
+    L.bs_mlp_train.argtypes = [vp, i32, dbl, i32, ctypes.POINTER(dbl)]
+    L.bs_mlp_predict.argtypes = [vp, vp, i32, i32, vp]
+    L.bs_mlp_destroy.argtypes = [vp]
+    L.bs_mlp_destroy.restype = None
+    L.bs_var_features.argtypes = [vp, vp, dbl, dbl, vp, vp]
     for name in EXPORTED:
-        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy"):
+        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy", "bs_mlp_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -276,3 +288,66 @@ def bs_mc_reset(mc: int) -> None:
 def bs_mc_destroy(mc: int) -> None:
     lib().bs_mc_destroy(mc)
     _mc_ctx.pop(mc, None)
+
+
+_mlp_ctx = {}
+
+
+def bs_mlp_create(ctx: int, seed: int, max_batch: int) -> int:
+    h = ctypes.c_void_p()
+    _check(ctx, lib().bs_mlp_create(ctx, seed, max_batch, ctypes.byref(h)))
+    _mlp_ctx[h.value] = ctx
+    return h.value
+
+
+def bs_mlp_read_state(mlp: int):
+    """Host copy (float32 [BS_MLP_NSTATE]) of the parameters followed by the normalisation."""
+    import numpy as np
+    out = np.zeros(BS_MLP_NSTATE, dtype=np.float32)
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_read_state(mlp, out.ctypes.data))
+    return out
+
+
+def bs_mlp_write_state(mlp: int, state) -> None:
+    import numpy as np
+    st = np.ascontiguousarray(state, dtype=np.float32)
+    assert st.size == BS_MLP_NSTATE
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_write_state(mlp, st.ctypes.data))
+
+
+def bs_mlp_set_data(mlp: int, X, t) -> None:
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_set_data(mlp, _ptr(X), _ptr(t), int(t.shape[0])))
+
+
+def bs_mlp_loss_grad(mlp: int, grad=None) -> float:
+    loss = ctypes.c_double()
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_loss_grad(mlp, _ptr(grad), ctypes.byref(loss)))
+    return loss.value
+
+
+def bs_mlp_train(mlp: int, steps: int, lr: float, cosine: bool = False) -> float:
+    loss = ctypes.c_double()
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_train(mlp, steps, lr, 1 if cosine else 0, ctypes.byref(loss)))
+    return loss.value
+
+
+def bs_mlp_predict(mlp: int, X, y, bf16: bool = False) -> None:
+    _check(_mlp_ctx.get(mlp), lib().bs_mlp_predict(mlp, _ptr(X), int(X.shape[0]), 1 if bf16 else 0, _ptr(y)))
+
+
+def bs_mlp_destroy(mlp: int) -> None:
+    lib().bs_mlp_destroy(mlp)
+    _mlp_ctx.pop(mlp, None)
+
+
+def bs_var_features(bins: int, n_cand: int, T3D=None, pk_index: float = -2.0, rho: float = 1.0):
+    """(X float32 [n_cand][4], baseline float64 [n_cand] or None) for 3D candidate triangles."""
+    import numpy as np
+    X = np.zeros((n_cand, 4), dtype=np.float32)
+    base = np.zeros(n_cand, dtype=np.float64) if T3D is not None else None
+    T = None if T3D is None else np.ascontiguousarray(T3D, dtype=np.int64)
+    rc = lib().bs_var_features(bins, None if T is None else T.ctypes.data, pk_index, rho, X.ctypes.data,
+                               None if base is None else base.ctypes.data)
+    if rc != BS_OK:
+        raise BsError(rc, "bs_var_features failed")
+    return X, base

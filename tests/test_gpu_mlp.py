@@ -1,0 +1,222 @@
+"""The variance-surrogate MLP on the GPU (C ABI) against the FP64 oracle, and what it gains.
+
+Parity: Philox initialisation, normalisation, forward, loss and gradient, Adam trajectories
+(constant and cosine learning rate), BF16 inference against FP32.
+Gain: on the flagged MWA-shaped cube the surrogate, trained on Monte Carlo labels of four flag
+patterns, is judged against fresh Monte Carlo runs of a training pattern and of an unseen one,
+next to small Monte Carlo runs and the Gaussian-shaped baseline alone.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp as om
+from paper_2506_10526_amd import bs, surrogate, synth
+
+from gpu_common import Ctx, cuda, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Ctx()
+    yield c.h
+    c.close()
+
+
+def data(n, seed=0):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(-6, 0, n), rng.uniform(-6, 0, n), rng.uniform(-6, 0, n),
+                         rng.uniform(0.7, 1.0, n)])
+    t = np.sin(X[:, 0]) + 0.3 * X[:, 1] * X[:, 2] - 2.0 * X[:, 3] + 0.1 * rng.normal(size=n)
+    return X, t
+
+
+def oracle_norm(X, t):
+    mx, sx, mt, st = om.normalisation(X.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64))
+    return (X.astype(np.float32) - mx) / sx, (t.astype(np.float32) - mt) / st, (mx, sx, mt, st)
+
+
+def groups():
+    o = np.cumsum([0] + [int(np.prod(s)) for _, s in om.SHAPES])
+    return [(name, o[i], o[i + 1]) for i, (name, _) in enumerate(om.SHAPES)]
+
+
+def test_init_and_normalisation_match_oracle(ctx):
+    m = bs.bs_mlp_create(ctx, 11, 512)
+    try:
+        st = bs.bs_mlp_read_state(m)
+        ref = om.init_params(11)
+        assert np.array_equal(st[:bs.BS_MLP_NPARAM], ref.astype(np.float32))
+        assert np.array_equal(st[bs.BS_MLP_NPARAM:], np.array([0, 0, 0, 0, 1, 1, 1, 1, 0, 1], np.float32))
+        X, t = data(333)
+        bs.bs_mlp_set_data(m, cuda(X, np.float32), cuda(t, np.float32))
+        st = bs.bs_mlp_read_state(m)
+        _, _, (mx, sx, mt, st_) = oracle_norm(X, t)
+        got = st[bs.BS_MLP_NPARAM:]
+        assert np.allclose(got[:4], mx, rtol=1e-6, atol=1e-6) and np.allclose(got[4:8], sx, rtol=1e-6)
+        assert np.isclose(got[8], mt, rtol=1e-6, atol=1e-6) and np.isclose(got[9], st_, rtol=1e-6)
+    finally:
+        bs.bs_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("n", [1, 97, 333, 1784])
+def test_forward_loss_grad_match_oracle(ctx, n):
+    """Ragged batches (1 row, and sizes that are not multiples of the 64-row tile)."""
+    m = bs.bs_mlp_create(ctx, 5, 2048)
+    try:
+        X, t = data(max(n, 2), seed=n)
+        Xf, tf = X.astype(np.float32), t.astype(np.float32)
+        if n >= 2:
+            bs.bs_mlp_set_data(m, cuda(Xf), cuda(tf))
+            st = bs.bs_mlp_read_state(m)
+            theta = st[:bs.BS_MLP_NPARAM].astype(np.float64)
+            xn, tn, (mx, sx, mt, sd) = oracle_norm(X, t)
+            L_ref, g_ref = om.loss_and_grad(theta, xn, tn)
+            g = torch.empty(bs.BS_MLP_NPARAM, dtype=torch.float32, device="cuda")
+            L = bs.bs_mlp_loss_grad(m, g)
+            gg = g.cpu().numpy().astype(np.float64)
+            assert abs(L - L_ref) <= 1e-5 * L_ref
+            for name, a, b in groups():
+                err = np.linalg.norm(gg[a:b] - g_ref[a:b]) / max(np.linalg.norm(g_ref[a:b]), 1e-30)
+                assert err <= 2e-5, (name, err)
+        # prediction (FP32) of de-normalised outputs
+        st = bs.bs_mlp_read_state(m)
+        theta = st[:bs.BS_MLP_NPARAM].astype(np.float64)
+        nm = st[bs.BS_MLP_NPARAM:].astype(np.float64)
+        Xq = Xf[:n]
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        bs.bs_mlp_predict(m, cuda(Xq), y)
+        yref = nm[8] + nm[9] * om.forward(theta, (Xq.astype(np.float64) - nm[:4]) / nm[4:8])
+        assert np.allclose(y.cpu().numpy(), yref, rtol=1e-5, atol=1e-5 * max(1.0, np.abs(yref).max()))
+    finally:
+        bs.bs_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("cosine", [False, True])
+def test_adam_trajectory_matches_oracle(ctx, cosine):
+    n, steps, lr = 300, 25, 3e-3
+    X, t = data(n, seed=3)
+    m = bs.bs_mlp_create(ctx, 2, 512)
+    try:
+        bs.bs_mlp_set_data(m, cuda(X, np.float32), cuda(t, np.float32))
+        loss_first = bs.bs_mlp_train(m, 1, lr, cosine=False)
+        loss_last = bs.bs_mlp_train(m, steps - 1, lr, cosine=cosine)   # graph replays of one step
+        st = bs.bs_mlp_read_state(m)[:bs.BS_MLP_NPARAM].astype(np.float64)
+    finally:
+        bs.bs_mlp_destroy(m)
+    xn, tn, _ = oracle_norm(X, t)
+    theta = om.init_params(2)
+    opt = om.Adam(theta.size, lr=lr)
+    losses = []
+    for k in range(steps):
+        if cosine and k >= 1:
+            opt.lr = lr * 0.5 * (1 + np.cos(np.pi * (k - 1) / (steps - 1)))
+        L, g = om.loss_and_grad(theta, xn, tn)
+        losses.append(L)
+        theta = opt.step(theta, g)
+    assert abs(loss_first - losses[0]) <= 1e-5 * losses[0]
+    assert abs(loss_last - losses[-1]) <= 1e-3 * losses[-1]
+    d = np.abs(st - theta)
+    # Adam normalises each gradient component, so components whose gradient is at rounding level
+    # may move by up to lr per step differently; the bulk must agree closely
+    assert np.median(d) <= 1e-6
+    assert np.mean(d > 1e-4) <= 0.01
+    assert np.linalg.norm(st - theta) <= 1e-3 * np.linalg.norm(theta)
+
+
+def test_bf16_inference_close_to_fp32(ctx):
+    n = 1000
+    X, t = data(n, seed=4)
+    m = bs.bs_mlp_create(ctx, 3, 1024)
+    try:
+        bs.bs_mlp_set_data(m, cuda(X, np.float32), cuda(t, np.float32))
+        bs.bs_mlp_train(m, 200, 3e-3, cosine=True)
+        y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+        y16 = torch.empty(n, dtype=torch.float32, device="cuda")
+        bs.bs_mlp_predict(m, cuda(X, np.float32), y32)
+        bs.bs_mlp_predict(m, cuda(X, np.float32), y16, bf16=True)
+        sd = bs.bs_mlp_read_state(m)[bs.BS_MLP_NPARAM + 9]
+    finally:
+        bs.bs_mlp_destroy(m)
+    a, b = y32.cpu().numpy(), y16.cpu().numpy()
+    err = np.abs(a - b) / sd          # in units of the normalised output
+    print(f"bf16 vs fp32: max {err.max():.3e}, median {np.median(err):.3e} (normalised units)")
+    assert np.max(err) <= 0.05 and np.median(err) <= 0.01
+
+
+def test_errors(ctx):
+    m = bs.bs_mlp_create(ctx, 1, 16)
+    try:
+        with pytest.raises(bs.BsError):
+            bs.bs_mlp_train(m, 10, 1e-3)                        # no data yet
+        X, t = data(32)
+        with pytest.raises(bs.BsError):
+            bs.bs_mlp_set_data(m, cuda(X, np.float32), cuda(t, np.float32))   # above max_batch
+    finally:
+        bs.bs_mlp_destroy(m)
+
+
+# ------------------------------------------------------------------------------------ gain
+def rel_err(pred, ref):
+    ok = np.isfinite(ref) & (ref > 0)
+    e = np.abs(pred[ok] - ref[ok]) / ref[ok]
+    return float(np.median(e)), float(np.percentile(e, 90))
+
+
+def test_surrogate_gain_on_flagged_mwa_cube(ctx):
+    """Train on 4 flag patterns x 256 realizations of the 256 x 256 x 768 cube; judge against 1024
+    fresh realizations of a training pattern (e = 1) and of an unseen one (e = 3)."""
+    w = synth.config2()
+    edges = w.shell_edges(20)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_SHELL_K, w.n, w.nc, edges, du_lambda=w.du, r_mpc=w.r_mpc,
+                               rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    desc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, du_lambda=w.du, r_mpc=w.r_mpc,
+                         rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    sur = None
+    try:
+        V = torch.empty((w.nc, w.n, w.nh), dtype=torch.complex64, device="cuda")
+        bs.bs_generate_cube(ctx, desc, 1, 0, V)
+        B = torch.empty(ncand, dtype=torch.float64, device="cuda")
+        N = torch.empty(ncand, dtype=torch.int64, device="cuda")
+        bs.bs_estimate_3d(ctx, h, V, bs.BS_SPLIT_BF16, B, N)
+        T3D = N.cpu().numpy()
+        flags = {e: synth.mwa_flags(w.nc, surrogate.edge_flags(e)) for e in (0, 1, 2, 3, 4)}
+        train = [surrogate.mc_run(ctx, h, ncand, desc, flags[e], 256, 100 + e) for e in (0, 1, 2, 4)]
+        t_labels = sum(r.seconds for r in train)
+        X, tgt = surrogate.training_set(h, ncand, T3D, train, -2.0)
+        sur = surrogate.Surrogate(ctx, seed=1)
+        fit = sur.fit(X, tgt, steps=4000, lr=3e-3, cosine=True)
+        judge1 = surrogate.mc_run(ctx, h, ncand, desc, flags[1], 1024, 1000)
+        judge3 = surrogate.mc_run(ctx, h, ncand, desc, flags[3], 1024, 2000)
+        small = {R: surrogate.mc_run(ctx, h, ncand, desc, flags[1], R, 3000 + R) for R in (50, 200)}
+        t0 = time.perf_counter()
+        p1 = surrogate.predict_var(sur, h, ncand, T3D, judge1.rho, -2.0)
+        t_pred = time.perf_counter() - t0
+        p3 = surrogate.predict_var(sur, h, ncand, T3D, judge3.rho, -2.0)
+        p1b = surrogate.predict_var(sur, h, ncand, T3D, judge1.rho, -2.0, bf16=True)
+        # the Gaussian-shaped baseline alone, its constant fitted on the training labels
+        _, base = bs.bs_var_features(h, ncand, T3D, -2.0, judge1.rho)
+        g1 = np.where(T3D > 0, np.exp(base + np.mean(tgt)), np.nan)
+    finally:
+        if sur:
+            sur.close()
+        bs.bs_free_bins(h)
+    e_s1, e_s3, e_b = rel_err(p1, judge1.var), rel_err(p3, judge3.var), rel_err(p1b, judge1.var)
+    e_g = rel_err(g1, judge1.var)
+    e50, e200 = rel_err(small[50].var, judge1.var), rel_err(small[200].var, judge1.var)
+    print(f"labels: 4 x 256 realizations in {t_labels:.2f} s; training {fit['steps']} steps in {fit['seconds']:.2f} s "
+          f"(loss {fit['final_loss']:.3e}); prediction of {ncand} triangles in {t_pred * 1e3:.2f} ms")
+    print(f"median / p90 relative error vs 1024-realization Monte Carlo:")
+    print(f"  surrogate, training pattern e=1 : {e_s1[0]:.3f} / {e_s1[1]:.3f}  (bf16 {e_b[0]:.3f} / {e_b[1]:.3f})")
+    print(f"  surrogate, unseen pattern e=3   : {e_s3[0]:.3f} / {e_s3[1]:.3f}")
+    print(f"  Gaussian-shaped baseline alone  : {e_g[0]:.3f} / {e_g[1]:.3f}")
+    print(f"  Monte Carlo, 50 realizations    : {e50[0]:.3f} / {e50[1]:.3f} ({small[50].seconds:.2f} s)")
+    print(f"  Monte Carlo, 200 realizations   : {e200[0]:.3f} / {e200[1]:.3f} ({small[200].seconds:.2f} s)")
+    assert e_s1[0] <= 0.10                  # within 10 % of Monte Carlo (median) on held-out realizations
+    assert e_s3[0] <= 0.15                  # and close on a flag pattern it never saw
+    assert e_s1[0] < e50[0] and e_s1[1] < e50[1]   # better than 50 fresh realizations, at no new realization
+    assert e_s1[0] < 0.5 * e_g[0]           # the network adds to the Gaussian-shaped scaling
+    assert abs(e_b[0] - e_s1[0]) <= 0.02    # BF16 inference keeps the accuracy
