@@ -210,6 +210,41 @@ int bs_mc_last(bs_mc* mc, double* B_host, int64_t* N_host);
 int bs_mc_reset(bs_mc* mc);
 void bs_mc_destroy(bs_mc* mc);
 
+/* ---- batches of uneven cubes through the MABS (split-BF16 MFMA contraction) ----
+ * Each cube i of `cubes` (n x n uv, n % 8 == 0, n >= 16; nc channels; the generator's size rules) is
+ * generated from (seed, realization) with the field description `field` (its n and nc ignored),
+ * binned in nrings log rings geomspace(1, umax + 1, nrings + 1) cells (umax = floor((n - 1) / 3)),
+ * and estimated for every candidate triangle, the nu1 subset nu1_host (NULL = all channels) and all
+ * (nu2, nu3), with unit weights and norm 1.  The output per cube is the ergodic collapse over the nu1
+ * subset (Sec. 3.2 before Eq. dft, Sec. 5): Bbar[t][d1 + nc - 1][d2 + nc - 1] = mean over selected nu1
+ * with nu1 - d1 and nu1 - d1 + d2 in the band of B(nu1, nu1 - d1 + d2, nu1 - d1) (NaN if none, or if
+ * the triangle has no closed grid triangle), and N_nu[d1'][d2'] the number averaged.
+ * bs_batch_create does every host-side step (bins, channel-independent counts, device tables) and
+ * picks the pixel-chunk count of each cube shape by timing candidates on the device (cached in the
+ * context); cubes are packed in order into waves whose workspaces fit budget_gib; every wave's
+ * contraction is one grouped launch over all its cubes; the whole batch is captured into one hipGraph.
+ * bs_batch_run: one graph launch (ordered after earlier work on the context's stream; later work on
+ *   that stream waits for it).
+ * bs_batch_info: candidate count, wave, pixel chunks and products (valid triangles x n_nu1 x nc^2 x n^2)
+ *   of cube i.  bs_batch_result: host copies of Bbar [n_cand][2nc-1][2nc-1], N_nu [2nc-1][2nc-1],
+ *   T_perp [n_cand] and the candidate ring triples [n_cand][3] (each nullable; synchronises).
+ * The batch owns its device memory (outputs of all cubes plus one arena of the largest wave). */
+typedef struct {
+  int32_t n, nc;
+  uint64_t seed, realization;
+  int32_t n_nu1;
+  const int32_t* nu1_host;
+} bs_batch_cube;
+typedef struct bs_batch bs_batch;
+int bs_batch_create(bs_ctx* ctx, const bs_batch_cube* cubes, int32_t ncubes, int32_t nrings,
+                    const bs_field_desc* field, double budget_gib, bs_batch** out);
+int bs_batch_run(bs_batch* batch);
+int bs_batch_info(const bs_batch* batch, int32_t cube, int32_t* n_cand, int32_t* wave, int32_t* kchunks,
+                  int64_t* products);
+int bs_batch_result(bs_batch* batch, int32_t cube, double* Bbar_host, int32_t* N_nu_host, int64_t* T_perp_host,
+                    int32_t* tri3_host);
+void bs_batch_destroy(bs_batch* batch);
+
 /* ---- learned variance surrogate ----
  * Not part of the paper, which takes error bars from the scatter of independent realizations
  * (Sec. 4, Sec. 5): a 4 -> 256 -> 256 -> 256 -> 1 MLP with SiLU hidden units predicts log Var(B)

@@ -24,6 +24,7 @@ EXPORTED = [
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
+    "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
 ]
 BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
@@ -57,6 +58,12 @@ class bs_field_desc(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("f_ng", ctypes.c_double), ("pk_index", ctypes.c_double),
                 ("du_lambda", ctypes.c_double), ("r_mpc", ctypes.c_double),
                 ("rprime_mpc_per_mhz", ctypes.c_double), ("dnu_mhz", ctypes.c_double)]
+
+
+class bs_batch_cube(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nc", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("realization", ctypes.c_uint64), ("n_nu1", ctypes.c_int32),
+                ("nu1_host", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -109,8 +116,16 @@ def lib() -> ctypes.CDLL:
     L.bs_mlp_destroy.argtypes = [vp]
     L.bs_mlp_destroy.restype = None
     L.bs_var_features.argtypes = [vp, vp, dbl, dbl, vp, vp]
+    L.bs_batch_create.argtypes = [vp, ctypes.POINTER(bs_batch_cube), i32, i32, ctypes.POINTER(bs_field_desc), dbl,
+                                  ctypes.POINTER(vp)]
+    L.bs_batch_run.argtypes = [vp]
+    L.bs_batch_info.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.bs_batch_result.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.bs_batch_destroy.argtypes = [vp]
+    L.bs_batch_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy", "bs_mlp_destroy"):
+        if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy", "bs_mlp_destroy",
+                        "bs_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -351,3 +366,55 @@ def bs_var_features(bins: int, n_cand: int, T3D=None, pk_index: float = -2.0, rh
     if rc != BS_OK:
         raise BsError(rc, "bs_var_features failed")
     return X, base
+
+
+_batch = {}
+
+
+def bs_batch_create(ctx: int, cubes, nrings: int, field: bs_field_desc, budget_gib: float = 64.0) -> int:
+    """cubes: sequence of (n, nc, seed, realization, nu1 list or None)."""
+    arr = (bs_batch_cube * len(cubes))()
+    keep = []
+    for i, (n, nc, seed, real, nu1) in enumerate(cubes):
+        if nu1 is None:
+            arr[i] = bs_batch_cube(n, nc, seed, real, 0, None)
+        else:
+            a = (ctypes.c_int32 * len(nu1))(*nu1)
+            keep.append(a)
+            arr[i] = bs_batch_cube(n, nc, seed, real, len(nu1), ctypes.cast(a, ctypes.POINTER(ctypes.c_int32)))
+    h = ctypes.c_void_p()
+    _check(ctx, lib().bs_batch_create(ctx, arr, len(cubes), nrings, ctypes.byref(field), budget_gib, ctypes.byref(h)))
+    _batch[h.value] = (ctx, [(c[0], c[1]) for c in cubes])
+    return h.value
+
+
+def bs_batch_run(batch: int) -> None:
+    _check(_batch[batch][0], lib().bs_batch_run(batch))
+
+
+def bs_batch_info(batch: int, cube: int):
+    """(n_candidates, wave, pixel_chunks, products) of one cube."""
+    a, b, c_, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_batch[batch][0], lib().bs_batch_info(batch, cube, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c_),
+                                                 ctypes.byref(d)))
+    return a.value, b.value, c_.value, d.value
+
+
+def bs_batch_result(batch: int, cube: int):
+    """(Bbar [n_cand][2nc-1][2nc-1], N_nu [2nc-1][2nc-1], T_perp [n_cand], triangles [n_cand][3])."""
+    import numpy as np
+    ncand = bs_batch_info(batch, cube)[0]
+    n, nc = _batch[batch][1][cube]
+    D = 2 * nc - 1
+    B = np.zeros((ncand, D, D), dtype=np.float64)
+    Nnu = np.zeros((D, D), dtype=np.int32)
+    T = np.zeros(ncand, dtype=np.int64)
+    tri = np.zeros((ncand, 3), dtype=np.int32)
+    _check(_batch[batch][0], lib().bs_batch_result(batch, cube, B.ctypes.data, Nnu.ctypes.data, T.ctypes.data,
+                                                   tri.ctypes.data))
+    return B, Nnu, T, tri
+
+
+def bs_batch_destroy(batch: int) -> None:
+    lib().bs_batch_destroy(batch)
+    _batch.pop(batch, None)

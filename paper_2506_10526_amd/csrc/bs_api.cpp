@@ -228,22 +228,20 @@ RingFieldLaunch ring_field_geometry(int n, int vmax, size_t esz) {
   return r;
 }
 
-// Launch ring-filtered fields for `blocks` (ring ids) over channels [0, nch) of `vis`.
-int run_ring_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64,
-                    bool count_mode, bool ignore_chan, int nch, const std::vector<int>& blocks,
-                    void* out, long long bin_stride) {
+}  // namespace
+
+// Arguments of the ring-field kernel for ring ids already on the device (no upload, no launch).
+int ring_fields_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, bool fp64, bool count_mode,
+                        bool ignore_chan, const int* d_bins, void* out, long long bin_stride, MabsFieldArgs& a,
+                        size_t& lds) {
   const auto& P = b->P;
   const int n = P.n;
-  if (blocks.empty()) return BS_OK;
-  int* d_bins = (int*)ctx_ws(c, count_mode ? "ring_bins_c" : "ring_bins_d", blocks.size() * sizeof(int));
-  if (!d_bins) return ctx_fail(c, BS_ENOMEM, "workspace (ring ids)");
-  HIPCHK(c, hipMemcpyAsync(d_bins, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
   const void* tw = ctx_twiddle(c, n, fp64);
   if (!tw) return ctx_fail(c, BS_ENOMEM, "twiddle table");
   RingFieldLaunch g = ring_field_geometry(n, P.vmax, fp64 ? 16 : 8);
   if (g.lds > 160 * 1024) return ctx_fail(c, BS_EUNSUPPORTED, "ring field transform does not fit in LDS");
-  MabsFieldArgs a{};
-  a.vis = vis;
+  a = MabsFieldArgs{};
+  a.vis = nullptr;
   a.ng = w ? w->ng : nullptr;
   a.uvm = w ? w->uv_mask : nullptr;
   a.chw = w ? w->chan_w : nullptr;
@@ -261,14 +259,37 @@ int run_ring_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weigh
   a.pcol = make_fft_plan(n / g.G);
   a.prow = make_fft_plan(n / 2);
   a.scale = 1.0 / ((double)n * (double)n);
-  // grid.y is limited to 65535: split the channel range
+  lds = g.lds;
+  return BS_OK;
+}
+
+// Launches the ring-field kernel over `nblocks` rings and channels [0, nch) (grid.y <= 65535 each).
+void ring_fields_launch(MabsFieldArgs a, bool fp64, int nblocks, int nch, size_t lds, hipStream_t s) {
   for (int c0 = 0; c0 < nch; c0 += 65535) {
     a.chan_offset = c0;
     int cn = std::min(65535, nch - c0);
-    if (fp64) launch_mabs_fields_f64(a, (int)blocks.size(), cn, g.lds, c->stream);
-    else launch_mabs_fields_f32(a, (int)blocks.size(), cn, g.lds, c->stream);
-    LAUNCHCHK(c, "ring field kernel");
+    if (fp64) launch_mabs_fields_f64(a, nblocks, cn, lds, s);
+    else launch_mabs_fields_f32(a, nblocks, cn, lds, s);
   }
+}
+
+namespace {
+
+// Launch ring-filtered fields for `blocks` (ring ids) over channels [0, nch) of `vis`.
+int run_ring_fields(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w, bool fp64,
+                    bool count_mode, bool ignore_chan, int nch, const std::vector<int>& blocks,
+                    void* out, long long bin_stride) {
+  if (blocks.empty()) return BS_OK;
+  int* d_bins = (int*)ctx_ws(c, count_mode ? "ring_bins_c" : "ring_bins_d", blocks.size() * sizeof(int));
+  if (!d_bins) return ctx_fail(c, BS_ENOMEM, "workspace (ring ids)");
+  HIPCHK(c, hipMemcpyAsync(d_bins, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  MabsFieldArgs a;
+  size_t lds = 0;
+  int rc = ring_fields_prepare(c, b, w, fp64, count_mode, ignore_chan, d_bins, out, bin_stride, a, lds);
+  if (rc) return rc;
+  a.vis = vis;
+  ring_fields_launch(a, fp64, (int)blocks.size(), nch, lds, c->stream);
+  LAUNCHCHK(c, "ring field kernel");
   return BS_OK;
 }
 

@@ -39,6 +39,7 @@ struct bs_ctx {
   bool have_timing = false;
   double last_count_dev = 0.0;
   int last_grid_M = 0;   // delay-axis grid of the last 3D contraction
+  std::map<std::string, int> tuned;       // autotuned launch parameters, by shape key
 };
 
 struct bs_bins {
@@ -53,3 +54,8 @@ void* ctx_ws(bs_ctx* c, const char* name, size_t bytes);       // grow-only; NUL
 const void* ctx_twiddle(bs_ctx* c, int L, bool fp64);          // NULL on failure
 FftPlan make_fft_plan(int L);
 bool fft_len_ok(int L);
+struct MabsFieldArgs;
+int ring_fields_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, bool fp64, bool count_mode,
+                        bool ignore_chan, const int* d_bins, void* out, long long bin_stride, MabsFieldArgs& a,
+                        size_t& lds);
+void ring_fields_launch(MabsFieldArgs a, bool fp64, int nblocks, int nch, size_t lds, hipStream_t s);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/bs.h"
 #include "fft_lds.h"
 
 struct GenArgs {
@@ -33,3 +34,6 @@ void launch_gen_set_state(unsigned long long* state, unsigned long long seed, un
 void launch_mc_accumulate(const double* B, int ntri, long long* cnt, double* mean, double* m2,
                           unsigned long long* state, hipStream_t s);
 void launch_mc_zero(long long* cnt, double* mean, double* m2, int ntri, hipStream_t s);
+// Checks a field description and fills the shape-dependent part of a GenArgs (plans, twiddles,
+// wave-vector scales); the device buffers are the caller's.
+int gen_prepare(bs_ctx* c, const bs_field_desc* d, GenArgs& a);

@@ -68,6 +68,13 @@ size_t part_len(const GenArgs& a) { return (size_t)std::max(a.nc, gen_row_blocks
 
 }  // namespace
 
+int gen_prepare(bs_ctx* c, const bs_field_desc* d, GenArgs& a) {
+  int rc = check_field_desc(c, d);
+  if (rc) return rc;
+  a = gen_args(c, d, rc);
+  return rc;
+}
+
 extern "C" int bs_generate_cube(bs_ctx* c, const bs_field_desc* d, uint64_t seed, uint64_t realization,
                                 const float* chan_w, void* vis) {
   if (!c) return BS_EINVAL;

@@ -364,17 +364,18 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int swz(int r, int chunk) { return (chunk ^ ((r >> 2) & 3)); }
 
+// One block tile of GEMM `a`; b0 is the block's index within this GEMM's nb = rtiles ctiles ntri
+// kchunks blocks.
 template <bool UNI>
-__global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+__device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
   uint16_t* lds = (uint16_t*)smem_raw;   // [2][S_BUF]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int nrows = a.n_nu1 * a.nc;
   const int rtiles = (nrows + S_TM - 1) / S_TM, ctiles = (a.nc + S_TN - 1) / S_TN;
   const int nb = rtiles * ctiles * a.ntri * a.kchunks;
-  // XCD-aware remap of the linear block id
-  int b = blockIdx.x;
+  // XCD-aware remap of the linear block id (blocks are dealt to the eight XCDs round-robin)
+  int b = b0;
   const int full = (nb / 8) * 8;
   if (b < full) b = (b & 7) * (full / 8) + (b >> 3);
   const int rt = b % rtiles;
@@ -544,6 +545,29 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
   }
 }
 
+template <bool UNI>
+__global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  split2_tile<UNI>(a, blockIdx.x, smem_raw);
+}
+
+// Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
+// [offs[g], offs[g+1]); offsets are multiples of 8 so that the XCD remap of each group holds.
+template <bool UNI>
+__global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemmArgs* __restrict__ groups,
+                                                                  const int* __restrict__ offs, int ngroups) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  int g = 0;
+  while (g + 1 < ngroups && offs[g + 1] <= b) ++g;
+  const MabsGemmArgs a = groups[g];
+  const int nrows = a.n_nu1 * a.nc;
+  const int nb = ((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
+  const int lb = b - offs[g];
+  if (lb >= nb) return;   // alignment padding
+  split2_tile<UNI>(a, lb, smem_raw);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 contraction on the vector ALUs (data in BS_FP64 mode, counts for per-cell N_g).
 // 64 x 64 tile, 256 threads, 4 x 4 outputs per thread (strided by 16), K staged by 16.
@@ -686,6 +710,35 @@ __global__ __launch_bounds__(256) void k_mabs_finalize(MabsFinalArgs a) {
   }
 }
 
+// Ergodic collapse over a nu1 subset (unit channel weights): Bbar[t][d1'][d2'] is the mean of
+// B(nu1, nu1 - d1 + d2, nu1 - d1) over the selected nu1 for which both other channels lie in the
+// band (d' = d + nc - 1); Nnu[d1'][d2'] counts them.  B = norm npix S / Tperp as for full output.
+__global__ __launch_bounds__(256) void k_mabs_collapse_subset(MabsSubsetArgs a) {
+  const int nc = a.nc, D = 2 * nc - 1;
+  const int nrows = a.n_nu1 * nc;
+  const size_t total = (size_t)a.ntri * D * D;
+  const size_t chunk_stride = (size_t)a.ntri * nrows * nc;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int j2 = (int)(e % D);
+    const size_t rest = e / D;
+    const int j1 = (int)(rest % D);
+    const int t = (int)(rest / D);
+    const int d1 = j1 - (nc - 1), d2 = j2 - (nc - 1);
+    double acc = 0.0;
+    int cnt = 0;
+    for (int i = 0; i < a.n_nu1; ++i) {
+      const int n1 = a.nu1[i], n3 = n1 - d1, n2 = n3 + d2;
+      if (n3 < 0 || n3 >= nc || n2 < 0 || n2 >= nc) continue;
+      const size_t idx = ((size_t)t * nrows + (size_t)i * nc + n2) * nc + n3;
+      acc += sum_chunks(a.S, a.kchunks, chunk_stride, idx);
+      ++cnt;
+    }
+    const int64_t T = a.Tperp[t];
+    a.B[e] = (cnt > 0 && T > 0) ? a.norm * a.npix * (acc / cnt) / (double)T : __builtin_nan("");
+    if (t == 0) a.Nnu[(size_t)j1 * D + j2] = cnt;
+  }
+}
+
 // Ergodic collapse: mean over valid nu3 of B(nu3 + d1, nu3 + d2, nu3) (rows R = nu1*nc + nu2).
 __global__ __launch_bounds__(256) void k_mabs_collapse(MabsCollapseArgs a) {
   const int nc = a.nc;
@@ -754,6 +807,23 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_mabs_gemm_split2<false>, dim3((unsigned)nb), dim3(256), lds, s, a);
   }
 }
+int mabs_split_blocks(const MabsGemmArgs& a) {
+  const int nrows = a.n_nu1 * a.nc;
+  return ((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
+}
+bool mabs_split_uni(int nc) { return nc % S_TM == 0; }
+void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* offs_dev, int ngroups, int nblocks,
+                                    bool uni, hipStream_t s) {
+  if (nblocks <= 0) return;
+  const size_t lds = 2 * (size_t)S_BUF * 2;
+  if (uni) {
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_mabs_gemm_split2_grouped<true>, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_mabs_gemm_split2_grouped<false>, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
+  }
+}
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
 }
@@ -771,6 +841,12 @@ void launch_mabs_finalize(const MabsFinalArgs& a, hipStream_t s) {
   size_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (total) hipLaunchKernelGGL(k_mabs_finalize, dim3((unsigned)blocks), dim3(256), 0, s, a);
+}
+void launch_mabs_collapse_subset(const MabsSubsetArgs& a, hipStream_t s) {
+  size_t total = (size_t)a.ntri * (2 * a.nc - 1) * (2 * a.nc - 1);
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (total) hipLaunchKernelGGL(k_mabs_collapse_subset, dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 void launch_mabs_collapse(const MabsCollapseArgs& a, hipStream_t s) {
   int D = a.circular ? a.nc : 2 * a.nc - 1;
