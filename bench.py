@@ -30,7 +30,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
+# HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
+# were taken on; None once that kernel changes until the counters are taken again.
+TRAFFIC_BYTES = {"k3_fused<split-bf16>": (216.3e6 + 14.7e6)}
 
 
 def log(*a):
@@ -46,6 +50,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-mabs", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-mc", action="store_true")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-surrogate", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     return p.parse_args()
@@ -74,7 +81,7 @@ def time_steps(fn, steps, warmup, torch):
 
 def cpu_baseline(w, V, edges, gpu_B, tri_all):
     """The FP64 oracle on a bounded sample of the same workload: the delay transform, the
-    fields of the three largest shells and every candidate triangle among them.  The full-
+    fields of the six largest shells and every candidate triangle among them.  The full-
     workload time is extrapolated from the per-field and per-triangle times."""
     import threading
     from oracle import bins as ob
@@ -83,7 +90,7 @@ def cpu_baseline(w, V, edges, gpu_B, tri_all):
     t0 = time.perf_counter()
     sf = oe.ShellFields(b, V.astype(np.complex128))
     t_delay = time.perf_counter() - t0
-    shells = [17, 18, 19]
+    shells = [14, 15, 16, 17, 18, 19]
     t0 = time.perf_counter()
     for j in shells:
         sf.data(j)
@@ -110,12 +117,112 @@ def cpu_baseline(w, V, edges, gpu_B, tri_all):
         "cores": 1,
         "kind": "oracle",
         "sample": (f"float64 NumPy oracle (single thread) on the same cube: delay transform ({t_delay:.1f} s), "
-                   f"3 of 20 shell fields ({t_field:.1f} s each), {len(sel)} of {len(tri_all)} triangles "
+                   f"{len(shells)} of 20 shell fields ({t_field:.1f} s each), {len(sel)} of {len(tri_all)} triangles "
                    f"({t_tri:.2f} s each); full step extrapolated as delay + 20 fields + all triangles "
                    f"= {t_full:.0f} s, counts excluded as on the GPU"),
         "max_rel_err_vs_gpu_on_sample": float(np.nanmax(err)) if len(sel) else None,
         "sample_valid_triangles": n_valid,
     }
+
+
+def mc_block(bs, ctx, bins, ncand, w, torch, R=64):
+    """Monte Carlo of the flagged cube (channels {0,16,31} of every 32): generator + 3D estimate
+    + FP64 accumulators per realization, replayed from one captured graph."""
+    from paper_2506_10526_amd import synth
+    desc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, du_lambda=w.du, r_mpc=w.r_mpc,
+                         rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    cw = torch.from_numpy(synth.mwa_flags(w.nc, (0, 16, 31)).astype(np.float32)).cuda()
+    m = bs.bs_mc_create(ctx, bins, desc, bs.BS_SPLIT_BF16, chan_w=cw)
+    try:
+        bs.bs_mc_run(m, 7, 0, 2)
+        bs.bs_mc_reset(m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs.bs_mc_run(m, 7, 2, R)
+        c, mu, v = bs.bs_mc_stats(m, ncand)
+        dt = time.perf_counter() - t0
+    finally:
+        bs.bs_mc_destroy(m)
+    nval = int(np.count_nonzero(c))
+    return {"workload": "flagged 256x256x768 cube (channels {0,16,31} mod 32), split-BF16, one hipGraph per realization",
+            "realizations": R, "seconds": dt, "ms_per_realization": dt / R * 1e3,
+            "products_per_s": nval * w.nc * w.n * w.n * R / dt, "valid_triangles": nval}
+
+
+def batch_block(bs, ctx, torch, ncubes=64, seed=4):
+    """64 seeded cubes of uneven size (n in {128,192,256}, nc in {384,576,768}), 8 log rings, all
+    candidate triangles, a seeded subset of 32 nu1 channels with all (nu2, nu3), split-BF16; one
+    hipGraph launch for the whole batch (one grouped contraction launch per wave)."""
+    rng = np.random.default_rng(seed)
+    cubes = []
+    for i in range(ncubes):
+        n = int(rng.choice([128, 192, 256]))
+        nc = int(rng.choice([384, 576, 768]))
+        nu1 = sorted(int(x) for x in rng.choice(nc, size=32, replace=False))
+        cubes.append((n, nc, 1000 + i, i, nu1))
+    desc = bs.field_desc(128, 384, bs.BS_K_CUBIC)
+    t0 = time.perf_counter()
+    h = bs.bs_batch_create(ctx, cubes, 8, desc, 48.0)
+    t_create = time.perf_counter() - t0
+    try:
+        info = [bs.bs_batch_info(h, i) for i in range(ncubes)]
+        bs.bs_batch_run(h)          # warm-up launch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs.bs_batch_run(h)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        bs.bs_batch_destroy(h)
+    products = sum(x[3] for x in info)
+    cand = sum(x[0] * 32 * c[1] * c[1] * c[0] * c[0] for x, c in zip(info, cubes))
+    flops = 6.0 * cand
+    return {"workload": "64 seeded cubes, n in {128,192,256}, nc in {384,576,768}, 8 log rings, 32 seeded nu1 "
+                        "x all (nu2, nu3), split-BF16, ergodic collapse over the nu1 subset",
+            "seconds_per_launch": dt, "products": products, "products_per_s": products / dt,
+            "mfma_tflops_incl_generation_and_fields": flops / dt / 1e12,
+            "waves": 1 + max(x[1] for x in info), "pixel_chunks": sorted({x[2] for x in info}),
+            "create_seconds": t_create}
+
+
+def surrogate_block(bs, ctx, bins, ncand, w, torch):
+    """Labels (4 flag patterns x 256 realizations), GPU training, judge against 1024 fresh
+    realizations of a training pattern and of an unseen one; next to 200-realization Monte Carlo."""
+    from paper_2506_10526_amd import surrogate, synth
+    desc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, du_lambda=w.du, r_mpc=w.r_mpc,
+                         rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    V = torch.empty((w.nc, w.n, w.nh), dtype=torch.complex64, device="cuda")
+    bs.bs_generate_cube(ctx, desc, 1, 0, V)
+    B = torch.empty(ncand, dtype=torch.float64, device="cuda")
+    N = torch.empty(ncand, dtype=torch.int64, device="cuda")
+    bs.bs_estimate_3d(ctx, bins, V, bs.BS_SPLIT_BF16, B, N)
+    T3D = N.cpu().numpy()
+    flags = {e: synth.mwa_flags(w.nc, surrogate.edge_flags(e)) for e in (0, 1, 2, 3, 4)}
+    train = [surrogate.mc_run(ctx, bins, ncand, desc, flags[e], 256, 100 + e) for e in (0, 1, 2, 4)]
+    X, tgt = surrogate.training_set(bins, ncand, T3D, train, -2.0)
+    sur = surrogate.Surrogate(ctx, seed=1)
+    try:
+        fit = sur.fit(X, tgt, steps=4000, lr=3e-3, cosine=True)
+        j1 = surrogate.mc_run(ctx, bins, ncand, desc, flags[1], 1024, 1000)
+        j3 = surrogate.mc_run(ctx, bins, ncand, desc, flags[3], 1024, 2000)
+        m200 = surrogate.mc_run(ctx, bins, ncand, desc, flags[1], 200, 3200)
+        t0 = time.perf_counter()
+        p1 = surrogate.predict_var(sur, bins, ncand, T3D, j1.rho, -2.0, bf16=True)
+        t_pred = time.perf_counter() - t0
+        p3 = surrogate.predict_var(sur, bins, ncand, T3D, j3.rho, -2.0, bf16=True)
+    finally:
+        sur.close()
+
+    def err(p, ref):
+        ok = np.isfinite(ref) & (ref > 0)
+        e = np.abs(p[ok] - ref[ok]) / ref[ok]
+        return {"median": float(np.median(e)), "p90": float(np.percentile(e, 90))}
+    return {"labels": "4 flag patterns (e = 0, 1, 2, 4 edge channels + centre) x 256 realizations",
+            "label_seconds": sum(r.seconds for r in train), "train_steps": fit["steps"],
+            "train_seconds": fit["seconds"], "predict_ms_bf16": t_pred * 1e3,
+            "rel_err_vs_mc1024_training_pattern": err(p1, j1.var),
+            "rel_err_vs_mc1024_unseen_pattern": err(p3, j3.var),
+            "rel_err_mc200_vs_mc1024": err(m200.var, j1.var), "mc200_seconds": m200.seconds}
 
 
 def main():
@@ -134,11 +241,15 @@ def main():
     dev = torch.device("cuda:0")
     w = synth.config2()
     edges = w.shell_edges(20)
-    log(f"[bench] generating {w.n}x{w.n}x{w.nc} cube (seed {args.seed})")
-    V = synth.make_cube(w, seed=args.seed, dtype=np.complex64)
-    Vd = torch.from_numpy(V).to(dev)
+    log(f"[bench] generating the {w.n}x{w.n}x{w.nc} cube on the GPU (seed {args.seed})")
     stream = torch.cuda.current_stream()
     ctx = bs.bs_create(0, stream.cuda_stream)
+    # the seeded cube is generated on the GPU (Philox stream; the oracle's generator makes the same cube)
+    gdesc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, sigma=w.sigma, f_ng=w.f_ng, pk_index=w.pk_index,
+                          du_lambda=w.du, r_mpc=w.r_mpc, rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
+    Vd = torch.empty((w.nc, w.n, w.nh), dtype=torch.complex64, device=dev)
+    bs.bs_generate_cube(ctx, gdesc, args.seed, 0, Vd)
+    torch.cuda.synchronize()
     bins, ncand = bs.bs_make_bins(ctx, bs.BS_SHELL_K, w.n, w.nc, edges, du_lambda=w.du, r_mpc=w.r_mpc,
                                   rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
     tri, modes = bs.bs_bins_triangles(bins, ncand, 20)
@@ -187,7 +298,7 @@ def main():
     ach = flops_per_vox * vox_c / (con_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": "k3_fused<split-bf16> (eta C2R + contraction)", "achieved": ach,
             "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
-            "traffic": None, "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
+            "traffic": TRAFFIC_BYTES.get("k3_fused<split-bf16>"), "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
             "delay_grid_M": M, "avg_ms": con_ms,
             "fields_kernels_ms": fld_ms}
     mabs = None
@@ -219,10 +330,26 @@ def main():
         mabs = res
         bs.bs_free_bins(rb)
         del Bm, Nm
+    mc = None
+    if not args.no_mc:
+        log("[bench] Monte Carlo: 64 flagged realizations from one graph")
+        mc = mc_block(bs, ctx, bins, ncand, w, torch)
+        log(f"[bench] mc: {mc['ms_per_realization']:.2f} ms/realization")
+    batch = None
+    if not args.no_batch:
+        log("[bench] batch: 64 uneven cubes, one graph launch")
+        batch = batch_block(bs, ctx, torch)
+        log(f"[bench] batch: {batch['seconds_per_launch']:.2f} s/launch, {batch['products_per_s']:.3e} products/s, "
+            f"{batch['mfma_tflops_incl_generation_and_fields']:.0f} TFLOP/s")
+    sur = None
+    if not args.no_surrogate:
+        log("[bench] variance surrogate: labels, training, judge")
+        sur = surrogate_block(bs, ctx, bins, ncand, w, torch)
+        log(f"[bench] surrogate: {sur['rel_err_vs_mc1024_training_pattern']}, unseen {sur['rel_err_vs_mc1024_unseen_pattern']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w, V, edges, Bs, tri)
+        cpu = cpu_baseline(w, Vd.cpu().numpy(), edges, Bs, tri)
     out = {
         "metric": "bin-triangle·voxel products/s, split-BF16 MFMA vs FP32 at ≤1e-4 rel err",
         "value": products / t_split,
@@ -245,6 +372,9 @@ def main():
         "kernel_ms": {"step_events": tim_split[0], "contraction": tim_split[1], "fields": tim_split[2]},
         "fp32": fp32,
         "mabs": mabs,
+        "mc": mc,
+        "batch": batch,
+        "surrogate": sur,
         "cpu_baseline": cpu,
     }
     bs.bs_free_bins(bins)
