@@ -34,7 +34,7 @@ FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (pack
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {"k3_fused<split-bf16>": (216.3e6 + 14.7e6)}
+TRAFFIC_BYTES = {"k3_fused<split-bf16>": None}
 
 
 def log(*a):

@@ -319,8 +319,11 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     fa.scale = 1.0 / ((double)M * (double)P.n * (double)P.n);
     fa.pairs = e.d_pairs; fa.npairs = e.npairs;
     fa.lines_per_block = (nlines + e.fblocks - 1) / e.fblocks;
+    // leading blocks whose delay support is narrow are summed directly in the kernel
+    fa.nlow = 0;
+    while (fa.nlow < fa.nbu && e.pd.hj[fa.nlow] <= FUSED_DIRECT_H && !getenv("BS_3D_ALLFFT")) ++fa.nlow;
     fa.partial = e.partial;
-    const size_t ld = (size_t)M / 2 + 2;
+    const size_t ld = (size_t)M / 2 + (size_t)M / 32 + 2;   // the kernel's padded FFT line
     int stage_len = 0;
     for (int h : e.pd.hj) stage_len += h + 1;
     if (stage_len > 512) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction: more than 512 delay modes per line");

@@ -133,6 +133,12 @@ int pick_kchunks(bs_ctx* c, bs_batch* bt, BCube& q, hipStream_t s) {
   snprintf(key, sizeof key, "mabs_split_kchunks:%d:%d:%d:%d", q.n, q.nc, q.n_nu1, q.ntri);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) { q.kchunks = it->second; return BS_OK; }
+  {
+    // a GEMM that already fills the chip many times over gains nothing from splitting K
+    MabsGemmArgs g1{};
+    g1.nc = q.nc; g1.n_nu1 = q.n_nu1; g1.ntri = q.ntri; g1.kchunks = 1;
+    if (mabs_split_blocks(g1) >= 4096) cand.resize(1);
+  }
   if (cand.size() == 1) { q.kchunks = cand[0]; c->tuned[key] = cand[0]; return BS_OK; }
   // temporary slots for one cube at the largest candidate
   BCube t = q;

@@ -180,7 +180,9 @@ struct Fused3Args {
   const int* pairs; int npairs;
   long long lines_per_block;
   double* partial;             // [gridDim.x][112][32]
+  int nlow;                    // leading blocks (H_j <= FUSED_DIRECT_H) summed directly instead of an FFT
 };
+constexpr int FUSED_DIRECT_H = 6;
 
 // Reduces the per-block partials into `reduced` ([112][32]) and finalises every triangle.
 void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s);

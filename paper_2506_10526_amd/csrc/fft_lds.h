@@ -99,8 +99,14 @@ __device__ __forceinline__ void dft8(Cx<T>* v) {
   v[3] = cadd(e[3], t3); v[7] = csub(e[3], t3);
 }
 
+// LDS position of element i of a line in a padded intermediate buffer: one spare slot after every
+// 16 elements, which spreads the stride-R writes of the early Stockham passes over the banks
+// (radix-8 first pass: 12-way -> 3-way conflicts on 32 four-byte banks).
+__device__ __forceinline__ int fft_pad(int i) { return i + (i >> 4); }
+
 // One Stockham pass of radix R over nl lines, butterflies spread over the work-group.
-template <int SIGN, int R, typename T>
+// PIN / POUT: the source / destination lines use the padded layout fft_pad().
+template <int SIGN, int R, typename T, bool PIN = false, bool POUT = false>
 __device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<T>* __restrict__ dst, int L,
                                               int Ns, int nl, int ld, const Cx<T>* __restrict__ tw, int tws) {
   const int nbf = L / R;
@@ -115,7 +121,10 @@ __device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<
     Cx<T>* out = dst + (size_t)line * ld;
     Cx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[j + r * nbf];
+    for (int r = 0; r < R; ++r) {
+      const int i = j + r * nbf;
+      v[r] = in[PIN ? fft_pad(i) : i];
+    }
     if (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -130,14 +139,27 @@ __device__ __forceinline__ void stockham_pass(const Cx<T>* __restrict__ src, Cx<
     else dft8<SIGN>(v);
     int o = jq * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+    for (int r = 0; r < R; ++r) {
+      const int i = o + r * Ns;
+      out[POUT ? fft_pad(i) : i] = v[r];
+    }
   }
+}
+
+template <int SIGN, typename T, bool PIN, bool POUT>
+__device__ __forceinline__ void stockham_any(int R, const Cx<T>* src, Cx<T>* dst, int L, int Ns, int nl, int ld,
+                                             const Cx<T>* __restrict__ tw, int tws) {
+  if (R == 8) stockham_pass<SIGN, 8, T, PIN, POUT>(src, dst, L, Ns, nl, ld, tw, tws);
+  else if (R == 4) stockham_pass<SIGN, 4, T, PIN, POUT>(src, dst, L, Ns, nl, ld, tw, tws);
+  else if (R == 3) stockham_pass<SIGN, 3, T, PIN, POUT>(src, dst, L, Ns, nl, ld, tw, tws);
+  else stockham_pass<SIGN, 2, T, PIN, POUT>(src, dst, L, Ns, nl, ld, tw, tws);
 }
 
 // Transform nl lines held in `a` (line i at a + i*ld, ld >= L; ld = L when omitted).
 // `b` is scratch of the same size.  Returns the buffer holding the result (a or b).
-// Ends with a barrier.
-template <int SIGN, typename T>
+// Ends with a barrier.  PAD: intermediate passes use the padded layout fft_pad() (input and
+// result keep the plain layout); needs ld >= L + L/16.
+template <int SIGN, typename T, bool PAD = false>
 __device__ Cx<T>* lds_fft(Cx<T>* a, Cx<T>* b, const FftPlan& p, int nl, const Cx<T>* __restrict__ tw, int tws,
                           int ld = 0) {
   if (ld <= 0) ld = p.L;
@@ -145,11 +167,12 @@ __device__ Cx<T>* lds_fft(Cx<T>* a, Cx<T>* b, const FftPlan& p, int nl, const Cx
   Cx<T>* src = a;
   Cx<T>* dst = b;
   for (int s = 0; s < p.nr; ++s) {
-    int R = p.rad[s];
-    if (R == 8) stockham_pass<SIGN, 8>(src, dst, p.L, Ns, nl, ld, tw, tws);
-    else if (R == 4) stockham_pass<SIGN, 4>(src, dst, p.L, Ns, nl, ld, tw, tws);
-    else if (R == 3) stockham_pass<SIGN, 3>(src, dst, p.L, Ns, nl, ld, tw, tws);
-    else stockham_pass<SIGN, 2>(src, dst, p.L, Ns, nl, ld, tw, tws);
+    const int R = p.rad[s];
+    const bool first = s == 0, last = s == p.nr - 1;
+    if (!PAD || (first && last)) stockham_any<SIGN, T, false, false>(R, src, dst, p.L, Ns, nl, ld, tw, tws);
+    else if (first) stockham_any<SIGN, T, false, true>(R, src, dst, p.L, Ns, nl, ld, tw, tws);
+    else if (last) stockham_any<SIGN, T, true, false>(R, src, dst, p.L, Ns, nl, ld, tw, tws);
+    else stockham_any<SIGN, T, true, true>(R, src, dst, p.L, Ns, nl, ld, tw, tws);
     __syncthreads();
     Cx<T>* t = src; src = dst; dst = t;
     Ns *= R;

@@ -360,7 +360,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nbu = a.nbu, M = a.M, Mh = M / 2, ld = Mh + 2;   // padded rows stagger LDS banks
+  const int nbu = a.nbu, M = a.M, Mh = M / 2, ld = Mh + Mh / 16 + 2;   // room for the padded FFT layout
   Cx<float>* A = (Cx<float>*)smem_raw;
   Cx<float>* Bf = A + (size_t)nbu * ld;
   Cx<float>* tw = Bf + (size_t)nbu * ld;                    // [M]
@@ -393,7 +393,10 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
       for (int q = 0; q < 4; ++q) { acc[i][j][q] = 0; acc64[i][j][q] = 0.0; }
   const Cx<float>* G = (const Cx<float>*)a.G;
   const float sc = (float)a.scale;
-  const float rMh = 1.0f / (float)Mh;
+  const float rMh = 1.0f / (float)Mh, rM = 1.0f / (float)M;
+  const int nlow = a.nlow, nfft = nbu - nlow;
+  // the FFT result buffer: A after an even number of Stockham passes, Bf after an odd one
+  float* Rf = (float*)((a.plan.nr & 1) ? Bf : A);
   const long long l_beg = (long long)blockIdx.x * a.lines_per_block;
   const long long l_end = l_beg + a.lines_per_block < a.nlines ? l_beg + a.lines_per_block : a.nlines;
   __syncthreads();
@@ -417,17 +420,35 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
       if (tid + 256 < L) pf1 = *slot_src(tid + 256, line + 1);
     }
     const Cx<float>* st = stage + cur * FUSED_STAGE;
-    for (int e = tid; e < nbu * Mh; e += 256) {
-      int j, k;
-      fdivmod(e, Mh, rMh, j, k);
+    // shells with a wide delay support: C2R packing, then the M/2-point FFT of all of them at once
+    for (int e = tid; e < nfft * Mh; e += 256) {
+      int jj, k;
+      fdivmod(e, Mh, rMh, jj, k);
+      const int j = nlow + jj;
       const int p0 = pre[j], hp1 = pre[j + 1] - p0;
       auto get = [&](int eta) -> Cx<float> { return eta < hp1 ? st[p0 + eta] : cmk(0.f, 0.f); };
       Cx<float> z = c2r_pack<float>(k, Mh, get, tw, 1);
       A[(size_t)j * ld + k] = cmk(z.x * sc, z.y * sc);
     }
+    // shells with |eta| <= FUSED_DIRECT_H: x(t) = sc (Re G_0 + 2 sum_q Re(G_q e^{+2 pi i q t / M})),
+    // written straight into the rows of the buffer the FFT result lands in
+    for (int e = tid; e < nlow * M; e += 256) {
+      int j, t;
+      fdivmod(e, M, rM, j, t);
+      const int p0 = pre[j], h = pre[j + 1] - p0 - 1;
+      float x = st[p0].x;
+      int m = 0;
+      for (int q = 1; q <= h; ++q) {
+        m += t;
+        if (m >= M) m -= M;
+        const Cx<float> g = st[p0 + q], w = tw[m];   // w = e^{-2 pi i m / M}
+        x += 2.0f * (g.x * w.x + g.y * w.y);          // Re(g conj(w))
+      }
+      Rf[2 * (size_t)j * ld + t] = x * sc;
+    }
     __syncthreads();
-    Cx<float>* r = lds_fft<+1, float>(A, Bf, a.plan, nbu, tw, 2, ld);
-    const float* Fl = (const float*)r;   // row j: floats [2 j ld, 2 j ld + M)
+    if (nfft > 0) lds_fft<+1, float, true>(A + (size_t)nlow * ld, Bf + (size_t)nlow * ld, a.plan, nfft, tw, 2, ld);
+    const float* Fl = Rf;   // row j: floats [2 j ld, 2 j ld + M)
     for (int v0 = wave * 32; v0 < M; v0 += 128) con3_step<MODE, float>(Fl, 2 * ld, nbu, v0, sp, RT, CT, acc);
     if (more) {
       Cx<float>* nx = stage + (cur ^ 1) * FUSED_STAGE;
@@ -446,11 +467,22 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 }
 
 // Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
+// Two fixed-order stages: first every group of RGROUP consecutive parts is summed into the group's
+// first slot (in place), then the group sums are added in group order.
+constexpr int RGROUP = 32;
+__global__ void k3_reduce_groups(double* __restrict__ partial, int nparts) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 112 * 32) return;
+  const int p0 = blockIdx.y * RGROUP, p1 = min(nparts, p0 + RGROUP);
+  double s = 0.0;
+  for (int p = p0; p < p1; ++p) s += partial[(size_t)p * 112 * 32 + e];
+  partial[(size_t)p0 * 112 * 32 + e] = s;
+}
 __global__ void k3_reduce_parts(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 112 * 32) return;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * 112 * 32 + e];
+  for (int p = 0; p < nparts; p += RGROUP) s += partial[(size_t)p * 112 * 32 + e];
   out[e] = s;
 }
 
@@ -508,6 +540,8 @@ void launch_contract3(const Con3Args& a, int mode, int nblocks, hipStream_t s) {
   else hipLaunchKernelGGL((k3_contract<2, float>), dim3(nblocks), dim3(256), 0, s, a);
 }
 void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
+  const int groups = (a.nparts + RGROUP - 1) / RGROUP;
+  hipLaunchKernelGGL(k3_reduce_groups, dim3((112 * 32 + 255) / 256, groups), dim3(256), 0, s, (double*)a.partial, a.nparts);
   hipLaunchKernelGGL(k3_reduce_parts, dim3((112 * 32 + 255) / 256), dim3(256), 0, s, a.partial, a.nparts, reduced);
   Fin3Args b = a;
   b.partial = reduced;
