@@ -207,3 +207,23 @@ def test_error_paths(ctx):
             bs.bs_estimate_mabs(ctx, h, V, bs.BS_FP32, B, N, collapse=1)       # no N_nu
     finally:
         bs.bs_free_bins(h)
+
+
+def test_full_row_tiles(ctx):
+    """nc = 256 (a multiple of the 128-row tile): every row tile shares one nu1, which selects the
+    kernel whose F1 chunk is loaded straight into LDS; the pixel count 48^2 = 2304 is not a
+    multiple of the 4096-pixel FP64 flush."""
+    n, nc = 48, 256
+    w = synth.small_workload(n, nc)
+    edges = np.geomspace(1.0, synth.default_umax(n) + 1.0, 5)
+    V = synth.make_cube(w, seed=31)
+    b = ob.make_bins(ob.RING_U, n, nc, edges)
+    nu1 = [0, 77, 255]
+    Bref, Nref, scale = oracle_full(b, V, None, nu1=nu1)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, n, nc, edges)
+    try:
+        Bg, Ng = run_gpu(ctx, h, V, bs.BS_SPLIT_BF16, ncand, len(nu1), nc, nu1=nu1)
+    finally:
+        bs.bs_free_bins(h)
+    assert np.array_equal(Ng, Nref)
+    compare_B(Bg, Bref, Nref, scale, TOL[bs.BS_SPLIT_BF16], "full row tiles")
