@@ -71,7 +71,7 @@ struct bs_batch {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   int nwaves = 0;
-  std::vector<MabsGemmArgs*> d_groups;   // per wave and kind (uni, general)
+  std::vector<MabsGemmArgs*> d_groups;   // per wave
   std::vector<int*> d_offs;
   std::vector<int> ngroups, nblocks;
   hipGraph_t graph = nullptr;
@@ -173,7 +173,7 @@ int pick_kchunks(bs_ctx* c, bs_batch* bt, BCube& q, hipStream_t s) {
     float ms = 0.f, tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
       (void)hipEventRecord(e0, s);
-      launch_mabs_gemm_split_grouped(dg, doffs, 1, offs[1], mabs_split_uni(q.nc), s);
+      launch_mabs_gemm_split_grouped(dg, doffs, 1, offs[1], s);
       (void)hipEventRecord(e1, s);
       (void)hipEventSynchronize(e1);
       (void)hipEventElapsedTime(&ms, e0, e1);
@@ -347,24 +347,22 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
   b->arena = (char*)balloc(b, maxw);
   b->arena_bytes = maxw;
   if (!b->arena) return restore_fail(ctx_fail(c, BS_ENOMEM, "batch arena (lower the budget)"));
-  // ---- group tables: per wave, UNI cubes and general cubes ----
+  // ---- group tables: one per wave ----
   for (int wv = 0; wv < b->nwaves; ++wv) {
-    for (int uni = 1; uni >= 0; --uni) {
-      std::vector<MabsGemmArgs> gs;
-      std::vector<int> offs{0};
-      for (auto& q : b->cubes) {
-        if (q.wave != wv || mabs_split_uni(q.nc) != (bool)uni) continue;
-        MabsGemmArgs g = gemm_args(q, b->arena, q.kchunks);
-        gs.push_back(g);
-        offs.push_back(offs.back() + (mabs_split_blocks(g) + 7) / 8 * 8);
-      }
-      b->ngroups.push_back((int)gs.size());
-      b->nblocks.push_back(offs.back());
-      b->d_groups.push_back(gs.empty() ? nullptr : upload(b, gs));
-      b->d_offs.push_back(gs.empty() ? nullptr : upload(b, offs));
-      if (!gs.empty() && (!b->d_groups.back() || !b->d_offs.back()))
-        return restore_fail(ctx_fail(c, BS_ENOMEM, "group tables"));
+    std::vector<MabsGemmArgs> gs;
+    std::vector<int> offs{0};
+    for (auto& q : b->cubes) {
+      if (q.wave != wv) continue;
+      MabsGemmArgs g = gemm_args(q, b->arena, q.kchunks);
+      gs.push_back(g);
+      offs.push_back(offs.back() + (mabs_split_blocks(g) + 7) / 8 * 8);
     }
+    b->ngroups.push_back((int)gs.size());
+    b->nblocks.push_back(offs.back());
+    b->d_groups.push_back(gs.empty() ? nullptr : upload(b, gs));
+    b->d_offs.push_back(gs.empty() ? nullptr : upload(b, offs));
+    if (!gs.empty() && (!b->d_groups.back() || !b->d_offs.back()))
+      return restore_fail(ctx_fail(c, BS_ENOMEM, "group tables"));
   }
   HIPCHK(c, hipStreamSynchronize(b->s));
   // ---- capture the whole batch ----
@@ -373,11 +371,8 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
   for (int wv = 0; wv < b->nwaves; ++wv) {
     for (auto& q : b->cubes)
       if (q.wave == wv) enqueue_front(q, b->arena, b->s);
-    for (int k = 0; k < 2; ++k) {
-      const int gi = 2 * wv + k;
-      if (b->ngroups[gi])
-        launch_mabs_gemm_split_grouped(b->d_groups[gi], b->d_offs[gi], b->ngroups[gi], b->nblocks[gi], k == 0, b->s);
-    }
+    if (b->ngroups[wv])
+      launch_mabs_gemm_split_grouped(b->d_groups[wv], b->d_offs[wv], b->ngroups[wv], b->nblocks[wv], b->s);
     for (auto& q : b->cubes) {
       if (q.wave != wv) continue;
       MabsSubsetArgs a{};

@@ -86,9 +86,8 @@ void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s);
 // Grouped split-BF16 contraction: groups_dev[g] owns blocks [offs_dev[g], offs_dev[g+1]) (offsets
 // multiples of 8, each group's range >= mabs_split_blocks of it); all groups UNI or all not.
 int mabs_split_blocks(const MabsGemmArgs& a);
-bool mabs_split_uni(int nc);
 void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* offs_dev, int ngroups, int nblocks,
-                                    bool uni, hipStream_t s);
+                                    hipStream_t s);
 void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s);
 // Tsum[t] = npix^2 * sum_p I_b1 I_b2 I_b3 over channel-independent FP64 count fields [nb][P].
 void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s);

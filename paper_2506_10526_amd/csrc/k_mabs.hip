@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <cstdlib>
 
 #include "bs_kernels.h"
@@ -342,31 +343,41 @@ __global__ __launch_bounds__(256) void k_mabs_gemm(MabsGemmArgs a) {
 // ---------------------------------------------------------------------------
 // Split-BF16 contraction, large tiles.  Block tile 128 x 256 (rows R = i*nc + nu2, columns nu3),
 // four waves of 64 x 128 (2 x 4 MFMA 32x32x16 tiles, 128 FP32 accumulators per lane), pixel
-// stages of 32, double-buffered LDS with one barrier per stage:
-//  * the pre-split B rows (bf16 hi/lo of F_b3) go from global memory straight into the next
-//    LDS buffer with 16-byte global_load_lds (lane l lands at byte 16 l of the wave's window);
-//  * A = F_b1(nu1) .* F_b2(nu2) is formed and split into bf16 hi/lo by the VALU from F2 values
-//    prefetched into registers and, when the whole tile shares one nu1 (UNI), an F1 chunk that
-//    each wave also loads straight into LDS;
-//  * the MFMAs of the current stage run while those loads are in flight.
-// LDS rows hold 32 bf16 as four 16-byte chunks XOR-swizzled by row.  The block's FP32 tile is
-// added into its FP64 output every SFLUSH pixels.  Blocks are mapped to tiles so that tiles
-// sharing a B column block and neighbouring A rows run on the same XCD (blocks are dealt to the
-// eight XCDs round-robin).
+// stages of 32 in two LDS buffers, software-pipelined around the MFMAs:
+//  * the pre-split B rows (bf16 hi/lo of F_b3) of stage s+1 go from global memory straight into
+//    the other LDS buffer with 16-byte global_load_lds, issued during stage s;
+//  * the F1 and F2 values of stage s+2 are loaded into registers during stage s, and the A
+//    operand of stage s+1 (A = F_b1(nu1) .* F_b2(nu2), split into bf16 hi/lo) is formed from
+//    the registers loaded one stage earlier and written into the other buffer, interleaved with
+//    the MFMAs of stage s;
+//  * the fragments of the second half of a stage are read while the first half's MFMAs run,
+//    and the last twelve MFMAs of a stage are issued after the stage barrier, covering the
+//    reads of the next stage's first fragments.
+// Each stage ends with a wait for all of this wave's memory operations and one barrier.  LDS rows
+// hold 32 bf16 as four 16-byte chunks XOR-swizzled by row.  The block's FP32 tile is added into
+// its FP64 output every SFLUSH pixels.  Blocks are mapped to tiles so that tiles sharing a B
+// column block and neighbouring A rows run on the same XCD (blocks are dealt to the eight XCDs
+// round-robin).
 // ---------------------------------------------------------------------------
 constexpr int S_TM = 128, S_TN = 256, S_TK = 32, SFLUSH = 4096;
 // uint16 offsets inside one stage buffer
 constexpr int S_AH = 0, S_AL = S_TM * S_TK, S_BH = 2 * S_TM * S_TK, S_BL = S_BH + S_TN * S_TK;
-constexpr int S_F1 = S_BL + S_TN * S_TK;           // 4 waves x 1 KB of F1 staging
-constexpr int S_BUF = S_F1 + 4 * 512;
+constexpr int S_BUF = S_BL + S_TN * S_TK;
 
 typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(3))) const char lds_cchar;
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(uintptr_t)(lds_cchar*)p; }
 
 __device__ __forceinline__ int swz(int r, int chunk) { return (chunk ^ ((r >> 2) & 3)); }
 
+struct SplitFrags {
+  bf16x8 ah[2], al[2], bh[4], bl[4];
+};
+
 // One block tile of GEMM `a`; b0 is the block's index within this GEMM's nb = rtiles ctiles ntri
 // kchunks blocks.
-template <bool UNI>
 __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
   uint16_t* lds = (uint16_t*)smem_raw;   // [2][S_BUF]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -388,8 +399,10 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   const int b1 = a.tri[3 * t], b2 = a.tri[3 * t + 1], b3 = a.tri[3 * t + 2];
   const int kbeg = kc * a.kchunk;
   const int kend = min(a.P, kbeg + a.kchunk);
+  const int nst = (kend - kbeg) / S_TK;   // >= 1; pixel ranges are multiples of S_TK
+  const int klast = kend - S_TK;          // loads past the range re-read the last stage
 
-  // A loader: row ar (16 pixels starting at ahalf)
+  // A operand: thread (ar, ahalf) owns row ar, pixels ahalf .. ahalf+15 of each stage
   const int ar = tid >> 1, ahalf = (tid & 1) * 16;
   const int R = row0 + ar;
   const bool rok = R < nrows;
@@ -397,64 +410,91 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   const int ia = Rc / a.nc, nu2 = Rc - ia * a.nc;
   const float* f1 = a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[ia] * a.P + ahalf;
   const float* f2 = a.F + (size_t)b2 * a.bin_stride + (size_t)nu2 * a.P + ahalf;
-  // F1 chunk for the whole tile (UNI): lanes 0..7 cover 32 floats, the others repeat chunk 7
-  const float* f1u = a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[row0 / a.nc] * a.P + 4 * min(lane, 7);
-  // B DMA: this wave's rows w*64 .. w*64+63, 16 rows per instruction
-  const uint16_t* bsrc[4];
+  // LDS uint16 offsets of this thread's two A chunks
+  int aoff[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) aoff[c] = ar * S_TK + swz(ar, (ahalf >> 3) + c) * 8;
+  // B copies: this wave's rows w*64 .. w*64+63, 16 rows per instruction
+  size_t boff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int br = wave * 64 + q * 16 + (lane >> 2);
     const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
-    bsrc[q] = (const uint16_t*)0 + ((size_t)b3 * a.bin_stride + (size_t)col * a.P) +
-              8 * swz(br, lane & 3);
+    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 8 * swz(br, lane & 3);
+  }
+  // fragment offsets (uint16, inside a stage buffer) per half-stage kk
+  int oa[2][2], ob[2][4];
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int chunk = kk * 2 + (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 64 + i * 32 + (lane & 31);
+      oa[kk][i] = r * S_TK + swz(r, chunk) * 8;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = wn * 128 + j * 32 + (lane & 31);
+      ob[kk][j] = c * S_TK + swz(c, chunk) * 8;
+    }
   }
 
-  float4 pa1[4], pa2[4];
-  auto issue = [&](int k0, uint16_t* buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      __builtin_amdgcn_global_load_lds((const void*)(a.Fh + ((bsrc[q] - (const uint16_t*)0) + k0)),
-                                       (lds_void*)(buf + S_BH + (wave * 64 + q * 16) * S_TK), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void*)(a.Fl + ((bsrc[q] - (const uint16_t*)0) + k0)),
-                                       (lds_void*)(buf + S_BL + (wave * 64 + q * 16) * S_TK), 16, 0, 0);
-    }
-    if (UNI) {
-      __builtin_amdgcn_global_load_lds((const void*)(f1u + k0), (lds_void*)(buf + S_F1 + wave * 512), 16, 0, 0);
-    } else {
-      const float4* p1 = (const float4*)(f1 + k0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) pa1[q] = p1[q];
-    }
-    const float4* p2 = (const float4*)(f2 + k0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pa2[q] = p2[q];
+  auto copy_b1 = [&](int m, int k0, uint16_t* buf) {   // copy m of 8: rows q = m/2, hi or lo
+    const int q = m >> 1;
+    __builtin_amdgcn_global_load_lds((const void*)((m & 1 ? a.Fl : a.Fh) + boff[q] + k0),
+                                     (lds_void*)(buf + (m & 1 ? S_BL : S_BH) + (wave * 64 + q * 16) * S_TK),
+                                     16, 0, 0);
   };
-  auto form = [&](uint16_t* buf) {
-    uint16_t* Ah = buf + S_AH;
-    uint16_t* Al = buf + S_AL;
-    if (UNI) {
-      const float4* fw = (const float4*)(buf + S_F1 + wave * 512) + (ahalf >> 2);
+  auto load_a1 = [&](int m, int k0, float4* p1, float4* p2) {   // load m of 8: F1 (m < 4) or F2
+    if (m < 4) p1[m] = ((const float4*)(f1 + k0))[m];
+    else p2[m - 4] = ((const float4*)(f2 + k0))[m - 4];
+  };
+  // A formation piece m of 8: products 2m, 2m+1 of this thread's 16, split into packed hi / lo words
+  auto form1 = [&](int m, const float4* p1, const float4* p2, uint32_t (&hw)[2][4], uint32_t (&lw)[2][4]) {
+    const int g = m >> 1, u = (m & 1) * 2;   // float4 index, component
+    const float4 x = p1[g], y = p2[g];
+    const float v0 = u ? x.z * y.z : x.x * y.x;
+    const float v1 = u ? x.w * y.w : x.y * y.y;
+    uint32_t hp = 0, lp = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) pa1[q] = fw[q];
+    for (int e = 0; e < 2; ++e) {
+      const float vv = rok ? (e ? v1 : v0) : 0.f;
+      const uint32_t hb = bf16_bits(vv);
+      const uint32_t lb = bf16_bits(vv - bf16_float((uint16_t)hb));
+      hp |= hb << (16 * e);
+      lp |= lb << (16 * e);
     }
+    hw[g >> 1][(g & 1) * 2 + (u >> 1)] = hp;
+    lw[g >> 1][(g & 1) * 2 + (u >> 1)] = lp;
+  };
+  // The A stores are written in asm: the compiler cannot tell them apart from the B copies into
+  // the same buffer and would otherwise wait for every memory operation in flight before them.
+  // They touch only the A region; the wait at the end of the stage covers their completion.
+  auto store_a = [&](int c, const uint32_t (&hw)[2][4], const uint32_t (&lw)[2][4], uint16_t* buf) {
+    const v4u h = {hw[c][0], hw[c][1], hw[c][2], hw[c][3]};
+    const v4u l = {lw[c][0], lw[c][1], lw[c][2], lw[c][3]};
+    asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:%3"
+                 :
+                 : "v"(lds_addr(buf + S_AH + aoff[c])), "v"(h), "v"(l), "n"(2 * (S_AL - S_AH))
+                 : "memory");
+  };
+  auto form = [&](const float4* p1, const float4* p2, uint16_t* buf) {
+    uint32_t hw[2][4], lw[2][4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint16_t h[8], l[8];
+    for (int m = 0; m < 8; ++m) form1(m, p1, p2, hw, lw);
+    store_a(0, hw, lw, buf);
+    store_a(1, hw, lw, buf);
+  };
+  // fragment m of 12 of half-stage kk: A hi (0, 1), A lo (2, 3), B hi (4..7), B lo (8..11)
+  auto read_frag1 = [&](SplitFrags& f, const uint16_t* buf, int kk, int m) {
+    if (m < 2) f.ah[m] = *(const bf16x8*)&buf[S_AH + oa[kk][m]];
+    else if (m < 4) f.al[m - 2] = *(const bf16x8*)&buf[S_AL + oa[kk][m - 2]];
+    else if (m < 8) f.bh[m - 4] = *(const bf16x8*)&buf[S_BH + ob[kk][m - 4]];
+    else f.bl[m - 8] = *(const bf16x8*)&buf[S_BL + ob[kk][m - 8]];
+  };
+  auto read_frags = [&](SplitFrags& f, const uint16_t* buf, int kk) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        float4 x = pa1[2 * c + q], y = pa2[2 * c + q];
-        float v[4] = {x.x * y.x, x.y * y.y, x.z * y.z, x.w * y.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          float vv = rok ? v[u] : 0.f;
-          h[4 * q + u] = bf16_bits(vv);
-          l[4 * q + u] = bf16_bits(vv - bf16_float(h[4 * q + u]));
-        }
-      }
-      const int pc = swz(ar, (ahalf >> 3) + c);
-      *(uint4*)&Ah[ar * S_TK + pc * 8] = *(uint4*)h;
-      *(uint4*)&Al[ar * S_TK + pc * 8] = *(uint4*)l;
-    }
+    for (int m = 0; m < 12; ++m) read_frag1(f, buf, kk, m);
   };
 
   f32x16 acc[2][4];
@@ -464,75 +504,31 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  // MFMA m of the 24 of a half stage: products (lo, hi), (hi, lo), (hi, hi) of the (i, j) tiles,
+  // eight apart
+  auto mfma1 = [&](const SplitFrags& f, int m) {
+    const int p = m >> 3, i = (m >> 2) & 1, j = m & 3;
+    const bf16x8 x = p == 0 ? f.al[i] : f.ah[i];
+    const bf16x8 y = p == 1 ? f.bl[j] : f.bh[j];
+    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc[i][j], 0, 0, 0);
+  };
 
   double* S = a.S + ((size_t)kc * a.ntri + t) * (size_t)nrows * a.nc;
   const bool interior = row0 + S_TM <= nrows && col0 + S_TN <= a.nc;
   bool first_flush = true;
-
-  issue(kbeg, lds);
-  __builtin_amdgcn_s_waitcnt(0);
-  form(lds);
-  __syncthreads();
-  int cur = 0;
-  // outer loop: FP64 flush of the block's tile every SFLUSH pixels; inner loop: stages (MFMA only)
-  for (int kf = kbeg; kf < kend; kf += SFLUSH) {
-    const int kfe = min(kend, kf + SFLUSH);
-    for (int k0 = kf; k0 < kfe; k0 += S_TK) {
-      const bool more = k0 + S_TK < kend;
-      uint16_t* nxt = lds + (cur ^ 1) * S_BUF;
-      if (more) issue(k0 + S_TK, nxt);
-      const uint16_t* buf = lds + cur * S_BUF;
-      const uint16_t* Ah = buf + S_AH;
-      const uint16_t* Al = buf + S_AL;
-      const uint16_t* Bh = buf + S_BH;
-      const uint16_t* Bl = buf + S_BL;
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        const int chunk = kk * 2 + (lane >> 5);
-        bf16x8 ah[2], al[2], bh[4], bl[4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int r = wm * 64 + i * 32 + (lane & 31);
-          const int off = r * S_TK + swz(r, chunk) * 8;
-          ah[i] = *(const bf16x8*)&Ah[off];
-          al[i] = *(const bf16x8*)&Al[off];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = wn * 128 + j * 32 + (lane & 31);
-          const int off = c * S_TK + swz(c, chunk) * 8;
-          bh[j] = *(const bf16x8*)&Bh[off];
-          bl[j] = *(const bf16x8*)&Bl[off];
-        }
-        // the three products of a tile are issued eight MFMAs apart (no back-to-back dependence)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
-      if (more) {
-        __builtin_amdgcn_s_waitcnt(0);   // this wave's DMA and register loads of the next stage
-        form(nxt);
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
+  auto flush = [&]() {
+    // the lane index passes through an empty asm so that the 128 output addresses are computed
+    // here and not hoisted out of the pixel loop (where they would hold 256 registers)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int col = col0 + wn * 128 + j * 32 + (lane & 31);
+        const int col = col0 + wn * 128 + j * 32 + (ln & 31);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int row = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+          const int row = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (ln >> 5) * 4 + (e & 3);
           if (interior || (row < nrows && col < a.nc)) {
             double* d = &S[(size_t)row * a.nc + col];
             double v = (double)acc[i][j][e];
@@ -542,18 +538,95 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
         }
       }
     first_flush = false;
+  };
+
+  SplitFrags F0, F1;
+  auto zero_frags = [&](SplitFrags& f) {
+    const bf16x8 z = {};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) f.ah[i] = f.al[i] = z;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.bh[j] = f.bl[j] = z;
+  };
+  zero_frags(F1);   // the first stage's deferred MFMAs add zeros
+  float4 P[2][2][4];   // [set][F1 / F2][4]: register-staged A inputs, set = stage parity
+
+  // prologue: stage 0 into buffer 0, registers of stage 1 in flight
+#pragma unroll
+  for (int m = 0; m < 8; ++m) copy_b1(m, kbeg, lds);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) load_a1(m, kbeg, P[0][0], P[0][1]);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) load_a1(m, min(kbeg + S_TK, klast), P[1][0], P[1][1]);
+  form(P[0][0], P[0][1], lds);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+  read_frags(F0, lds, 0);
+
+  // Stage s (buffer s&1, its kk = 0 fragments in F0, the deferred MFMAs of stage s-1 in F1), as
+  // 48 issue slots of one MFMA each plus, in program order: the B copies of stage s+1 and the
+  // register loads of stage s+2 (slots 0-11), the kk = 1 fragment reads (12-23), the A formation
+  // of stage s+1 (24-33); sched_barrier keeps every slot's instructions in place.
+  auto stage = [&](int s, auto par) {
+    constexpr int PAR = decltype(par)::value;
+    uint16_t* cur = lds + PAR * S_BUF;
+    uint16_t* nxt = lds + (PAR ^ 1) * S_BUF;
+    const int kb = min(kbeg + (s + 1) * S_TK, klast), ka = min(kbeg + (s + 2) * S_TK, klast);
+    uint32_t hw[2][4], lw[2][4];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+      mfma1(F1, 12 + m);   // deferred, stage s-1
+      if (m < 8) {
+        copy_b1(m, kb, nxt);
+      } else {
+        load_a1(2 * (m - 8), ka, P[PAR][0], P[PAR][1]);
+        load_a1(2 * (m - 8) + 1, ka, P[PAR][0], P[PAR][1]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < 24; ++m) {
+      mfma1(F0, m);
+      if (m < 12) read_frag1(F1, cur, 1, m);
+      else if (m < 20) form1(m - 12, P[PAR ^ 1][0], P[PAR ^ 1][1], hw, lw);
+      else if (m < 22) store_a(m - 20, hw, lw, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+      mfma1(F1, m);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // B of stage s+1 and the registers of stage s+2 landed, A stored
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    read_frags(F0, nxt, 0);
+  };
+
+  for (int s = 0; s < nst;) {
+    const int se = min(nst, s + SFLUSH / S_TK);   // s is even here
+    while (true) {
+      stage(s, std::integral_constant<int, 0>{});
+      if (++s >= se) break;
+      stage(s, std::integral_constant<int, 1>{});
+      if (++s >= se) break;
+    }
+#pragma unroll
+    for (int m = 12; m < 24; ++m) mfma1(F1, m);
+    flush();
+    zero_frags(F1);
   }
+  __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS may outlive the block
 }
 
-template <bool UNI>
 __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  split2_tile<UNI>(a, blockIdx.x, smem_raw);
+  split2_tile(a, blockIdx.x, smem_raw);
 }
 
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
 // [offs[g], offs[g+1]); offsets are multiples of 8 so that the XCD remap of each group holds.
-template <bool UNI>
 __global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemmArgs* __restrict__ groups,
                                                                   const int* __restrict__ offs, int ngroups) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -565,7 +638,7 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemm
   const int nb = ((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
   const int lb = b - offs[g];
   if (lb >= nb) return;   // alignment padding
-  split2_tile<UNI>(a, lb, smem_raw);
+  split2_tile(a, lb, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,30 +872,19 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
   const int nrows = a.n_nu1 * a.nc;
   const long long nb = (long long)((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
   const size_t lds = 2 * (size_t)S_BUF * 2;
-  if (a.nc % S_TM == 0) {
-    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_mabs_gemm_split2<true>, dim3((unsigned)nb), dim3(256), lds, s, a);
-  } else {
-    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_mabs_gemm_split2<false>, dim3((unsigned)nb), dim3(256), lds, s, a);
-  }
+  (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_mabs_gemm_split2, dim3((unsigned)nb), dim3(256), lds, s, a);
 }
 int mabs_split_blocks(const MabsGemmArgs& a) {
   const int nrows = a.n_nu1 * a.nc;
   return ((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
 }
-bool mabs_split_uni(int nc) { return nc % S_TM == 0; }
 void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* offs_dev, int ngroups, int nblocks,
-                                    bool uni, hipStream_t s) {
+                                    hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t lds = 2 * (size_t)S_BUF * 2;
-  if (uni) {
-    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_mabs_gemm_split2_grouped<true>, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
-  } else {
-    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_mabs_gemm_split2_grouped<false>, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
-  }
+  (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_mabs_gemm_split2_grouped, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
 }
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);

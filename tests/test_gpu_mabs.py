@@ -210,9 +210,9 @@ def test_error_paths(ctx):
 
 
 def test_full_row_tiles(ctx):
-    """nc = 256 (a multiple of the 128-row tile): every row tile shares one nu1, which selects the
-    kernel whose F1 chunk is loaded straight into LDS; the pixel count 48^2 = 2304 is not a
-    multiple of the 4096-pixel FP64 flush."""
+    """nc = 256 (a multiple of the 128-row tile, so every row tile lies within one nu1 and no tile
+    row is padding); the pixel count 48^2 = 2304 is not a multiple of the 4096-pixel FP64 flush,
+    and its 72 stages exercise both LDS buffer parities and the final partial flush."""
     n, nc = 48, 256
     w = synth.small_workload(n, nc)
     edges = np.geomspace(1.0, synth.default_umax(n) + 1.0, 5)
