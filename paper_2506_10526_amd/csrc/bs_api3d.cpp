@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -209,18 +211,43 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
   e.blocks.clear();
   for (auto& kv : blk) { kv.second = (int)e.blocks.size(); e.blocks.push_back(kv.first); }
   if ((int)e.blocks.size() > kMaxFields) return ctx_fail(c, BS_EUNSUPPORTED, "more than 32 shells in use");
-  std::map<std::pair<int, int>, int> pr;
-  std::vector<int> pairs, tpair(ntri), tcol(ntri);
-  for (int t = 0; t < ntri; ++t) {
-    int a = blk[P.tri[3 * t]], bb = blk[P.tri[3 * t + 1]];
-    auto key = std::make_pair(a, bb);
-    auto it = pr.find(key);
-    if (it == pr.end()) {
-      it = pr.emplace(key, (int)(pairs.size() / 2)).first;
-      pairs.push_back(a); pairs.push_back(bb);
+  // The contraction forms one product row F_a F_b per shell pair and sums it against every shell
+  // c, so a triangle can be served by any of its three pairs (the triple product is symmetric).
+  // Pairs are chosen greedily (most still-unserved triangles first, ties to the smaller pair) to
+  // cover all triangles with few rows: each row costs one product per voxel.
+  std::vector<std::array<int, 3>> tb(ntri);
+  for (int t = 0; t < ntri; ++t)
+    for (int q = 0; q < 3; ++q) tb[t][q] = blk[P.tri[3 * t + q]];
+  auto pkey = [](int x, int y) { return x < y ? std::make_pair(x, y) : std::make_pair(y, x); };
+  std::vector<int> pairs, tpair(ntri, -1), tcol(ntri, -1);
+  int left = ntri;
+  while (left > 0) {
+    std::map<std::pair<int, int>, int> gain;
+    for (int t = 0; t < ntri; ++t) {
+      if (tpair[t] >= 0) continue;
+      std::set<std::pair<int, int>> seen;   // a triangle counts once per pair
+      for (int q = 0; q < 3; ++q) {
+        auto k = pkey(tb[t][q], tb[t][(q + 1) % 3]);
+        if (seen.insert(k).second) ++gain[k];
+      }
     }
-    tpair[t] = it->second;
-    tcol[t] = blk[P.tri[3 * t + 2]];
+    auto best = gain.begin();
+    for (auto it = gain.begin(); it != gain.end(); ++it)
+      if (it->second > best->second) best = it;
+    const int pi = (int)(pairs.size() / 2);
+    const int pa = best->first.first, pb = best->first.second;
+    pairs.push_back(pa); pairs.push_back(pb);
+    for (int t = 0; t < ntri; ++t) {
+      if (tpair[t] >= 0) continue;
+      for (int q = 0; q < 3; ++q) {
+        if (pkey(tb[t][q], tb[t][(q + 1) % 3]) == best->first) {
+          tpair[t] = pi;
+          tcol[t] = tb[t][(q + 2) % 3];
+          --left;
+          break;
+        }
+      }
+    }
   }
   e.npairs = (int)(pairs.size() / 2);
   if (e.npairs > kMaxPairs) return ctx_fail(c, BS_EUNSUPPORTED, "more than 112 shell pairs in use");
