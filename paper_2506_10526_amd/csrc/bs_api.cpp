@@ -115,6 +115,7 @@ extern "C" void bs_destroy(bs_ctx* c) {
   for (auto& kv : c->ws) if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : c->tw32) (void)hipFree(kv.second);
   for (auto& kv : c->tw64) (void)hipFree(kv.second);
+  for (auto& kv : c->dftw) (void)hipFree(kv.second);
   for (auto& kv : c->counts) if (kv.second.d_counts) (void)hipFree(kv.second.d_counts);
   for (auto& e : c->ev) if (e) (void)hipEventDestroy(e);
   delete c;

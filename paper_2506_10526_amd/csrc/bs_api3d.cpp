@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <array>
 #include <map>
 #include <set>
@@ -67,6 +68,54 @@ X* upload(bs_ctx* c, const std::string& name, const std::vector<X>& v, int& rc) 
   return d;
 }
 
+// B-fragments of v_mfma_f32_16x16x32_bf16 for the eta synthesis x(t) = sum_q a_q (Re G_q cos(2 pi q t / M)
+// - Im G_q sin(2 pi q t / M)): entry ((tt * Smax + s) * 2 + hl) * 64 + lane holds, for t = 16 tt +
+// lane % 16 and q = 16 s + 4 (lane / 16) + c (c = 0..3), the pairs (cos, -sin) as bf16 hi (hl = 0)
+// or lo (hl = 1) parts, hi = rne(x), lo = rne(x - hi).  Cached per (M, Smax).
+uint16_t host_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite values)
+  return (uint16_t)(u >> 16);
+}
+float host_bf16_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+const void* ctx_dft_twiddle(bs_ctx* c, int M, int Smax) {
+  const long long key = (long long)M * 64 + Smax;
+  auto it = c->dftw.find(key);
+  if (it != c->dftw.end()) return it->second;
+  const int ntt = M / 16;
+  std::vector<uint16_t> h((size_t)ntt * Smax * 2 * 64 * 8);
+  const long double tp = 2.0L * 3.14159265358979323846264338327950288L;
+  for (int tt = 0; tt < ntt; ++tt)
+    for (int s = 0; s < Smax; ++s)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int t = 16 * tt + (lane & 15);
+        for (int cq = 0; cq < 4; ++cq) {
+          const long long q = 16LL * s + 4 * (lane >> 4) + cq;
+          const long long m = (q * t) % M;   // exact angle reduction
+          const long double ang = tp * (long double)m / (long double)M;
+          const float v[2] = {(float)cosl(ang), (float)-sinl(ang)};
+          for (int e = 0; e < 2; ++e) {
+            const uint16_t hi = host_bf16(v[e]);
+            const uint16_t lo = host_bf16(v[e] - host_bf16_float(hi));
+            const size_t base = (((size_t)(tt * Smax + s) * 2) * 64 + lane) * 8 + 2 * cq + e;
+            h[base] = hi;
+            h[base + 64 * 8] = lo;
+          }
+        }
+      }
+  void* d = nullptr;
+  if (hipMalloc(&d, h.size() * 2) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  if (hipMemcpy(d, h.data(), h.size() * 2, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
+  c->dftw[key] = d;
+  return d;
+}
+
 int fields3_prepare(bs_ctx* c, const bs_bins* b, bool fp64, bool indicator, const Plan3& p, const std::string& t,
                     Fields3Dev& fd) {
   const auto& P = b->P;
@@ -126,8 +175,10 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   LAUNCHCHK(c, "v pass");
   // u pass
   a.work = fd.d_wu; a.off_in = fd.d_offT; a.off_out = fd.d_offG; a.in = fd.Tm; a.out = fd.Gm; a.NL = p.NLu;
+  a.gs = fd.Gs; a.off_gs = fd.d_offGs; a.scale = fd.gscale;
   launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
   LAUNCHCHK(c, "u pass");
+  a.gs = nullptr; a.off_gs = nullptr;
   if (!F) return BS_OK;
   // eta pass (C2R), output length nc
   const int M = nc;
@@ -359,6 +410,38 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     lds = std::max<size_t>(lds, 112 * 32 * 8);
     if (lds > 160 * 1024) return ctx_fail(c, BS_EUNSUPPORTED, "fused 3D contraction does not fit in LDS");
     e.lds = lds;
+    // split-BF16: eta synthesis on MFMA over line groups of 16 x_u (fragments written by the u pass)
+    std::vector<int> Sj, kb{0};
+    int Smax = 0;
+    for (int h : e.pd.hj) { Sj.push_back((h + 16) / 16); kb.push_back(kb.back() + Sj.back()); Smax = std::max(Smax, Sj.back()); }
+    const size_t dlds = (size_t)2 * kb.back() * 1024 + (size_t)4 * DFT_MAX_FIELDS * DFT_LD * 4 + 224 * 4;
+    e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
+            std::max(dlds, (size_t)112 * 32 * 8) <= 160 * 1024 && e.pd.NLu == 16 && !getenv("BS_3D_FFT");
+    if (e.dft) {
+      const long long ngroups = nlines / 16;
+      std::vector<long long> offGs;
+      long long tot = 0;
+      for (int sj : Sj) { offGs.push_back(tot); tot += ngroups * sj * 128; }
+      e.fd.Gs = ctx_ws(c, (tag + "_Gs").c_str(), (size_t)tot * 16);
+      if (!e.fd.Gs) return ctx_fail(c, BS_ENOMEM, "workspace (spectrum fragments)");
+      e.fd.d_offGs = upload(c, tag + "_offGs", offGs, rc); if (rc) return rc;
+      e.fd.gscale = fa.scale;
+      Dft3Args& da = e.da;
+      da = Dft3Args{};
+      da.Gs = e.fd.Gs; da.offGs = e.fd.d_offGs;
+      da.Sj = upload(c, tag + "_Sj", Sj, rc); if (rc) return rc;
+      da.kb = upload(c, tag + "_kb", kb, rc); if (rc) return rc;
+      da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;
+      da.W = ctx_dft_twiddle(c, M, Smax);
+      if (!da.W) return ctx_fail(c, BS_ENOMEM, "eta twiddle fragments");
+      da.pairs = e.d_pairs; da.npairs = e.npairs;
+      da.ngroups = (int)ngroups;
+      e.dblocks = (int)std::min<long long>(ngroups, 256);
+      da.groups_per_block = (int)((ngroups + e.dblocks - 1) / e.dblocks);
+      e.dblocks = (int)((ngroups + da.groups_per_block - 1) / da.groups_per_block);
+      da.partial = e.partial;
+      e.dlds = std::max(dlds, (size_t)112 * 32 * 8);
+    }
   } else {
     e.F = ctx_ws(c, (tag + "_F").c_str(), (size_t)e.blocks.size() * e.nvox * (e.fp64 ? 8 : 4));
     if (!e.F) return ctx_fail(c, BS_ENOMEM, "workspace (fields)");
@@ -377,9 +460,15 @@ int est3_enqueue(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights*
     rc = fields3_enqueue(c, vis, w, e.pd, e.fd, nullptr);
     if (rc) return rc;
     if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
-    launch_fused3(e.fa, e.precision == BS_FP32 ? 1 : 2, e.fblocks, e.lds, c->stream);
-    LAUNCHCHK(c, "fused contraction");
-    nparts = e.fblocks;
+    if (e.dft) {
+      launch_dft3(e.da, e.dblocks, e.dlds, c->stream);
+      LAUNCHCHK(c, "eta synthesis and contraction");
+      nparts = e.dblocks;
+    } else {
+      launch_fused3(e.fa, e.precision == BS_FP32 ? 1 : 2, e.fblocks, e.lds, c->stream);
+      LAUNCHCHK(c, "fused contraction");
+      nparts = e.fblocks;
+    }
   } else {
     rc = fields3_enqueue(c, vis, w, e.pd, e.fd, e.F);
     if (rc) return rc;

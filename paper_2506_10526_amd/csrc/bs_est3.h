@@ -36,6 +36,9 @@ struct Fields3Dev {
   long long* d_offT = nullptr;
   long long* d_offG = nullptr;
   Work3 *d_wv = nullptr, *d_wu = nullptr, *d_we = nullptr;
+  void* Gs = nullptr;                // when set, the u pass writes bf16 A-fragments here
+  long long* d_offGs = nullptr;
+  double gscale = 1.0;               // folded into the fragments: 1 / (M n^2)
 };
 
 // Everything one 3D estimate needs besides the cube: resolved on the host once (plans, tables,
@@ -61,6 +64,10 @@ struct Est3 {
   Fused3Args fa{};
   size_t lds = 0;
   int fblocks = 0;
+  bool dft = false;            // split-BF16: eta synthesis on MFMA (k3_dft) instead of the FFT
+  Dft3Args da{};
+  size_t dlds = 0;
+  int dblocks = 0;
 };
 
 void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp64, Plan3& p);

@@ -136,8 +136,11 @@ struct Pass3Args {
   int NL;
   int indicator;               // v pass: 1 = unit indicator of shell and support, 0 = data
   int M;                       // eta pass: output length along eta
-  double scale;                // eta pass: overall 1 / (M n^2)
+  double scale;                // eta pass: overall 1 / (M n^2); u pass with gs: the same, folded into gs
   long long fstride;           // eta pass: elements per output field (M n^2)
+  void* gs;                    // u pass: when set, the spectra are written as bf16 MFMA fragments
+                               // (layout of Dft3Args::Gs) instead of `out`
+  const long long* off_gs;     // u pass: per block offset into gs (16-byte units)
 };
 
 struct Con3Args {
@@ -182,6 +185,29 @@ struct Fused3Args {
   int nlow;                    // leading blocks (H_j <= FUSED_DIRECT_H) summed directly instead of an FFT
 };
 constexpr int FUSED_DIRECT_H = 6;
+
+// Split-BF16 synthesis along eta on MFMA + contraction.  The delay spectra arrive as bf16 hi/lo
+// A-fragments of v_mfma_f32_16x16x32_bf16: for block j, line group g = x_v * (n / 16) + x_u / 16
+// and K-step s (modes 16 s .. 16 s + 15), two 1 KB fragments (hi, lo) at
+// Gs[offGs[j] + (g * S_j + s) * 128 + hl * 64 + lane]; lane l holds line x_u = 16 (x_u / 16) + l % 16
+// and the reals (Re, Im) of modes 16 s + 4 (l / 16) + c, c = 0..3, scaled by a_q / (M n^2)
+// (a_0 = 1 with Im dropped, a_q = 2).  W holds the matching B-fragments of cos / -sin
+// (2 pi q t / M) for t-tile tt: W[((tt * Smax + s) * 2 + hl) * 64 + lane], t = 16 tt + l % 16.
+struct Dft3Args {
+  const void* Gs;              // uint4 fragments
+  const long long* offGs;      // per block (16-byte units)
+  const int* Sj;               // per block: K-steps ceil((H_j + 1) / 16)
+  const int* kb;               // per block: prefix of Sj
+  int nbu;                     // fields (<= DFT_MAX_FIELDS)
+  int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
+  const void* W;               // uint4 twiddle fragments
+  const int* pairs; int npairs;
+  int ngroups;                 // line groups n * n / 16
+  int groups_per_block;
+  double* partial;             // [gridDim.x][112][32]
+};
+constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LD = 136;
+void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s);
 
 // Reduces the per-block partials into `reduced` ([112][32]) and finalises every triangle.
 void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s);

@@ -16,6 +16,9 @@
 namespace {
 
 __device__ __forceinline__ int sidx(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+// bf16 bits (round to nearest even) of x, and the float value of bf16 bits
+__device__ __forceinline__ uint32_t dft_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float dft_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
 __device__ __forceinline__ int wrap(int q, int n) { return q < 0 ? q + n : q; }
 
 // --------------------------------------------------------------- delay transform
@@ -126,6 +129,38 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   }
   __syncthreads();
   Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.gs) {
+      // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column
+      const int S = (hp1 + 15) >> 4, s = e0 >> 4, nxub = n >> 4;
+      uint4* out = (uint4*)a.gs + a.off_gs[w.j];
+      const float sc = (float)a.scale;
+      for (int e = threadIdx.x; e < nxub * 64; e += blockDim.x) {
+        const int xub = e >> 6, lane = e & 63;
+        const int xu = xub * 16 + (lane & 15), q0 = 4 * (lane >> 4);
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int q = q0 + c;   // mode e0 + q
+          float re = 0.f, im = 0.f;
+          if (q < nl) {
+            const Cx<float> z = r[(size_t)q * ld + xu];
+            const bool dc = e0 + q == 0;
+            re = z.x * (dc ? sc : 2.f * sc);
+            im = dc ? 0.f : z.y * (2.f * sc);
+          }
+          const uint32_t rh = dft_bf16(re), ih = dft_bf16(im);
+          const uint32_t rl = dft_bf16(re - dft_f32(rh)), il = dft_bf16(im - dft_f32(ih));
+          hw[c] = rh | (ih << 16);
+          lw[c] = rl | (il << 16);
+        }
+        uint4* o = out + ((size_t)(xv * nxub + xub) * S + s) * 128;
+        o[lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        o[64 + lane] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+      }
+      return;
+    }
+  }
   Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     int i = e / nl, l = e - i * nl;
@@ -466,6 +501,98 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
   con3_store<MODE>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
 }
 
+// Split-BF16 fused kernel: the C2R along eta as MFMA GEMMs against a twiddle-fragment table, then
+// the pair x field contraction.  A block owns a range of line groups (16 consecutive x_u of one
+// x_v).  For each group it copies the group's spectrum fragments (all fields, all K-steps) into
+// LDS with 16-byte global_load_lds; each wave then takes t-tiles of 16 delay samples and computes,
+// for every field j, F_j[16 lines][16 t] = sum over K-steps of three MFMAs (lo.hi, hi.lo, hi.hi).
+// Lane l then holds F_j at lines 4 (l / 16) + i, t = l % 16 (i = 0..3): the halves i < 2 and
+// i >= 2 pass in turn through the wave's own LDS rows (voxel 2 l + (i & 1)) into con3_step.
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nbu = a.nbu, nfr = 2 * a.kb[nbu];
+  v4u_t* stage = (v4u_t*)smem_raw;                                         // [nfr][64]
+  float* sF = (float*)(stage + (size_t)nfr * 64) + (size_t)wave * DFT_MAX_FIELDS * DFT_LD;  // this wave's rows
+  int* sp = (int*)((float*)(stage + (size_t)nfr * 64) + 4 * DFT_MAX_FIELDS * DFT_LD);    // [224]
+  for (int e = tid; e < 2 * 112; e += 256) sp[e] = e < 2 * a.npairs ? a.pairs[e] : -1;
+  const int RT = (a.npairs + 15) / 16, CT = (nbu + 15) / 16;
+  acc_t<2> acc[C3_RT][C3_CT];
+  double acc64[C3_RT][C3_CT][4];
+#pragma unroll
+  for (int i = 0; i < C3_RT; ++i)
+#pragma unroll
+    for (int j = 0; j < C3_CT; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { acc[i][j][q] = 0.f; acc64[i][j][q] = 0.0; }
+  const v4u_t* Gs = (const v4u_t*)a.Gs;
+  const v4u_t* W = (const v4u_t*)a.W;
+  const int ntt = a.M >> 4;
+  const int g_beg = blockIdx.x * a.groups_per_block;
+  const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
+  int since = 0;
+  for (int g = g_beg; g < g_end; ++g) {
+    __syncthreads();   // every wave is done with the previous group's fragments
+    for (int j = 0; j < nbu; ++j) {
+      const int S = a.Sj[j], f0 = 2 * a.kb[j];
+      const v4u_t* src = Gs + a.offGs[j] + (size_t)g * S * 128 + lane;
+      for (int s2 = (wave - f0) & 3; s2 < 2 * S; s2 += 4)
+        __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
+                                         16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int tt = wave; tt < ntt; tt += 4) {
+      bf16x8 wh[DFT_MAX_STEPS], wl[DFT_MAX_STEPS];
+#pragma unroll
+      for (int s = 0; s < DFT_MAX_STEPS; ++s) {
+        if (s < a.Smax) {
+          const v4u_t* wp = W + ((size_t)(tt * a.Smax + s) * 2) * 64 + lane;
+          wh[s] = __builtin_bit_cast(bf16x8, wp[0]);
+          wl[s] = __builtin_bit_cast(bf16x8, wp[64]);
+        }
+      }
+      float keep[DFT_MAX_FIELDS][2];
+#pragma unroll
+      for (int j = 0; j < DFT_MAX_FIELDS; ++j) {
+        if (j < nbu) {
+          f32x4 d = {0.f, 0.f, 0.f, 0.f};
+          const int S = a.Sj[j];
+          const v4u_t* fr = stage + (size_t)2 * a.kb[j] * 64 + lane;
+#pragma unroll
+          for (int s = 0; s < DFT_MAX_STEPS; ++s) {
+            if (s < S) {
+              const bf16x8 gh = __builtin_bit_cast(bf16x8, fr[2 * s * 64]);
+              const bf16x8 gl = __builtin_bit_cast(bf16x8, fr[(2 * s + 1) * 64]);
+              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, wh[s], d, 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, wl[s], d, 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, wh[s], d, 0, 0, 0);
+            }
+          }
+          *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(d[0], d[1]);
+          keep[j][0] = d[2];
+          keep[j][1] = d[3];
+        }
+      }
+      for (int v0 = 0; v0 < 128; v0 += 32) con3_step<2, float>(sF, DFT_LD, nbu, v0, sp, RT, CT, acc);
+#pragma unroll
+      for (int j = 0; j < DFT_MAX_FIELDS; ++j)
+        if (j < nbu) *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(keep[j][0], keep[j][1]);
+      for (int v0 = 0; v0 < 128; v0 += 32) con3_step<2, float>(sF, DFT_LD, nbu, v0, sp, RT, CT, acc);
+      since += 256;
+      if (since >= 512) { since = 0; con3_flush<2>(acc, acc64); }
+    }
+  }
+  __syncthreads();
+  double* red = (double*)smem_raw;   // reuse the fragment stage
+  for (int e = tid; e < 112 * 32; e += 256) red[e] = 0.0;
+  __syncthreads();
+  con3_store<2>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
+}
+
 // Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
 // Two fixed-order stages: first every group of RGROUP consecutive parts is summed into the group's
 // first slot (in place), then the group sums are added in group order.
@@ -546,6 +673,10 @@ void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
   Fin3Args b = a;
   b.partial = reduced;
   if (a.ntri > 0) hipLaunchKernelGGL(k3_fin, dim3((a.ntri + 127) / 128), dim3(128), 0, s, b);
+}
+void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k3_dft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k3_dft, dim3(nblocks), dim3(256), lds, s, a);
 }
 void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s) {
   if (mode == 1) {

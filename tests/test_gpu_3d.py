@@ -52,15 +52,24 @@ def run3(ctx, h, V, prec, ncand, **wk):
 
 @pytest.mark.parametrize("prec", PREC)
 @pytest.mark.parametrize("case", ["cubic16x8", "cubic32x24_flags", "cubic32x128_fused", "cubic32x128_unfused",
-                                  "cubic32x256_coarse", "cubic32x256_fullgrid"])
+                                  "cubic32x256_coarse", "cubic32x256_fullgrid", "cubic32x128_wide",
+                                  "cubic32x128_wide_fft"])
 def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
     """Small cubes: radix-2/3 delay axes, flags, and (nc = 128) the fused eta-C2R + contraction
-    kernel next to the path that materialises the fields (BS_3D_UNFUSED=1)."""
+    kernels (split-BF16: synthesis on MFMA, or the FFT form with BS_3D_FFT=1) next to the path that
+    materialises the fields (BS_3D_UNFUSED=1)."""
     if case.endswith("_unfused"):
         monkeypatch.setenv("BS_3D_UNFUSED", "1")
     if case.endswith("_fullgrid"):
         monkeypatch.setenv("BS_3D_FULLGRID", "1")
-    if case.startswith("cubic32x256"):
+    if case.endswith("_fft"):
+        monkeypatch.setenv("BS_3D_FFT", "1")
+    if case.startswith("cubic32x128_wide"):
+        # delay modes up to |eta| = 40: three 16-mode steps of the MFMA synthesis for the outer shells
+        n, nc, nb, kmax = 32, 128, 6, 40.0
+        wl = synth.small_workload(n, nc)
+        cw = None
+    elif case.startswith("cubic32x256"):
         # delay modes |eta| <= 9: the fused path contracts on a 128-point delay grid
         n, nc, nb, kmax = 32, 256, 6, 10.0
         wl = synth.small_workload(n, nc)
