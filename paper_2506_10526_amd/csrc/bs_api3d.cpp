@@ -414,7 +414,8 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     std::vector<int> Sj, kb{0};
     int Smax = 0;
     for (int h : e.pd.hj) { Sj.push_back((h + 16) / 16); kb.push_back(kb.back() + Sj.back()); Smax = std::max(Smax, Sj.back()); }
-    const size_t dlds = (size_t)2 * kb.back() * 1024 + (size_t)4 * DFT_MAX_FIELDS * DFT_LD * 4 + 224 * 4;
+    // fragment stage (+ one zero fragment) and four waves of field rows (+ one zero row each)
+    const size_t dlds = (size_t)(2 * kb.back() + 1) * 1024 + (size_t)4 * (DFT_MAX_FIELDS + 1) * DFT_LD * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
             std::max(dlds, (size_t)112 * 32 * 8) <= 160 * 1024 && e.pd.NLu == 16 && !getenv("BS_3D_FFT");
     if (e.dft) {

@@ -505,37 +505,89 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // the pair x field contraction.  A block owns a range of line groups (16 consecutive x_u of one
 // x_v).  For each group it copies the group's spectrum fragments (all fields, all K-steps) into
 // LDS with 16-byte global_load_lds; each wave then takes t-tiles of 16 delay samples and computes,
-// for every field j, F_j[16 lines][16 t] = sum over K-steps of three MFMAs (lo.hi, hi.lo, hi.hi).
-// Lane l then holds F_j at lines 4 (l / 16) + i, t = l % 16 (i = 0..3): the halves i < 2 and
-// i >= 2 pass in turn through the wave's own LDS rows (voxel 2 l + (i & 1)) into con3_step.
+// for every field j, F_j[16 lines][16 t] = sum over K-steps of three MFMAs (lo.hi, hi.lo, hi.hi),
+// four fields at a time so that consecutive MFMAs are independent (missing K-steps read a zero
+// fragment).  Lane l then holds F_j at lines 4 (l / 16) + i, t = l % 16 (i = 0..3): the halves
+// i < 2 and i >= 2 pass in turn through the wave's own LDS rows (voxel 2 l + (i & 1)) into the
+// contraction, whose pair rows and padding (a zero row) are resolved once per lane.  The copy of
+// the next group's fragments is issued once every wave has finished its last synthesis of the
+// current group, and lands while that tile is contracted.
 typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Contraction of 128 voxels held in rows sF[j * DFT_LD + v] (v < 128) into acc: RTN pair row tiles
+// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc).
+template <int RTN>
+__device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const int (&oa)[RTN], const int (&ob)[RTN],
+                                             const int (&oc)[2], f32x4 (&acc)[RTN][2]) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int vb = ks * 32 + kq * 8;
+    bf16x8 bh[2], bl[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const float4 x0 = *(const float4*)&sF[oc[ct] + vb], x1 = *(const float4*)&sF[oc[ct] + vb + 4];
+      const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      split8(v, bh[ct], bl[ct]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RTN; ++rt) {
+      const float4 a0 = *(const float4*)&sF[oa[rt] + vb], a1 = *(const float4*)&sF[oa[rt] + vb + 4];
+      const float4 b0 = *(const float4*)&sF[ob[rt] + vb], b1 = *(const float4*)&sF[ob[rt] + vb + 4];
+      const float v[8] = {a0.x * b0.x, a0.y * b0.y, a0.z * b0.z, a0.w * b0.w,
+                          a1.x * b1.x, a1.y * b1.y, a1.z * b1.z, a1.w * b1.w};
+      bf16x8 ah, al;
+      split8(v, ah, al);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int RTN>
 __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int ROWS = DFT_MAX_FIELDS + 1;   // fields + one zero row
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15;
   const int nbu = a.nbu, nfr = 2 * a.kb[nbu];
-  v4u_t* stage = (v4u_t*)smem_raw;                                         // [nfr][64]
-  float* sF = (float*)(stage + (size_t)nfr * 64) + (size_t)wave * DFT_MAX_FIELDS * DFT_LD;  // this wave's rows
-  int* sp = (int*)((float*)(stage + (size_t)nfr * 64) + 4 * DFT_MAX_FIELDS * DFT_LD);    // [224]
-  for (int e = tid; e < 2 * 112; e += 256) sp[e] = e < 2 * a.npairs ? a.pairs[e] : -1;
-  const int RT = (a.npairs + 15) / 16, CT = (nbu + 15) / 16;
-  acc_t<2> acc[C3_RT][C3_CT];
-  double acc64[C3_RT][C3_CT][4];
+  v4u_t* stage = (v4u_t*)smem_raw;                                      // [nfr + 1][64], last = zeros
+  float* fields = (float*)(stage + (size_t)(nfr + 1) * 64);
+  float* sF = fields + (size_t)wave * ROWS * DFT_LD;                    // this wave's rows
+  stage[(size_t)nfr * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
+  for (int e = lane; e < DFT_LD; e += 64) sF[DFT_MAX_FIELDS * DFT_LD + e] = 0.f;
+  // per-lane contraction rows: pair (a, b) of row rt * 16 + r16 and field c = ct * 16 + r16
+  int oa[RTN], ob[RTN], oc[2];
 #pragma unroll
-  for (int i = 0; i < C3_RT; ++i)
+  for (int rt = 0; rt < RTN; ++rt) {
+    const int p = rt * 16 + r16;
+    const bool ok = p < a.npairs;
+    oa[rt] = (ok ? a.pairs[2 * p] : DFT_MAX_FIELDS) * DFT_LD;
+    ob[rt] = (ok ? a.pairs[2 * p + 1] : DFT_MAX_FIELDS) * DFT_LD;
+  }
 #pragma unroll
-    for (int j = 0; j < C3_CT; ++j)
+  for (int ct = 0; ct < 2; ++ct) {
+    const int c = ct * 16 + r16;
+    oc[ct] = (c < nbu ? c : DFT_MAX_FIELDS) * DFT_LD;
+  }
+  f32x4 acc[RTN][2];
+  double acc64[RTN][2][4];
+#pragma unroll
+  for (int i = 0; i < RTN; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) { acc[i][j][q] = 0.f; acc64[i][j][q] = 0.0; }
   const v4u_t* Gs = (const v4u_t*)a.Gs;
   const v4u_t* W = (const v4u_t*)a.W;
-  const int ntt = a.M >> 4;
+  const int ntt = a.M >> 4;   // a multiple of 8: every wave takes ntt / 4 tiles per group
   const int g_beg = blockIdx.x * a.groups_per_block;
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
-  int since = 0;
-  for (int g = g_beg; g < g_end; ++g) {
-    __syncthreads();   // every wave is done with the previous group's fragments
+  auto copy_group = [&](int g) {
     for (int j = 0; j < nbu; ++j) {
       const int S = a.Sj[j], f0 = 2 * a.kb[j];
       const v4u_t* src = Gs + a.offGs[j] + (size_t)g * S * 128 + lane;
@@ -543,8 +595,12 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
         __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
                                          16, 0, 0);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+  };
+  if (g_beg < g_end) copy_group(g_beg);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int since = 0;
+  for (int g = g_beg; g < g_end; ++g) {
     for (int tt = wave; tt < ntt; tt += 4) {
       bf16x8 wh[DFT_MAX_STEPS], wl[DFT_MAX_STEPS];
 #pragma unroll
@@ -557,40 +613,91 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
       }
       float keep[DFT_MAX_FIELDS][2];
 #pragma unroll
-      for (int j = 0; j < DFT_MAX_FIELDS; ++j) {
-        if (j < nbu) {
-          f32x4 d = {0.f, 0.f, 0.f, 0.f};
-          const int S = a.Sj[j];
-          const v4u_t* fr = stage + (size_t)2 * a.kb[j] * 64 + lane;
+      for (int c = 0; c < DFT_MAX_FIELDS / 4; ++c) {
+        if (4 * c < nbu) {
+          int f0[4], S[4], nst = 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = 4 * c + u;
+            f0[u] = j < nbu ? 2 * a.kb[j] : nfr;
+            S[u] = j < nbu ? a.Sj[j] : 0;
+            nst = max(nst, S[u]);
+          }
+          f32x4 d[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) d[u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int s = 0; s < DFT_MAX_STEPS; ++s) {
-            if (s < S) {
-              const bf16x8 gh = __builtin_bit_cast(bf16x8, fr[2 * s * 64]);
-              const bf16x8 gl = __builtin_bit_cast(bf16x8, fr[(2 * s + 1) * 64]);
-              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, wh[s], d, 0, 0, 0);
-              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, wl[s], d, 0, 0, 0);
-              d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, wh[s], d, 0, 0, 0);
+            if (s < nst) {
+              bf16x8 gh[4], gl[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
+                const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
+                gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
+                gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh[s], d[u], 0, 0, 0);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl[s], d[u], 0, 0, 0);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh[s], d[u], 0, 0, 0);
             }
           }
-          *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(d[0], d[1]);
-          keep[j][0] = d[2];
-          keep[j][1] = d[3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = 4 * c + u;
+            *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(d[u][0], d[u][1]);
+            keep[j][0] = d[u][2];
+            keep[j][1] = d[u][3];
+          }
         }
       }
-      for (int v0 = 0; v0 < 128; v0 += 32) con3_step<2, float>(sF, DFT_LD, nbu, v0, sp, RT, CT, acc);
+      if (tt + 4 >= ntt) {
+        // the group's last synthesis on every wave: the fragments of the next group may land
+        __syncthreads();
+        if (g + 1 < g_end) copy_group(g + 1);
+      }
+      dft_contract<RTN>(sF, oa, ob, oc, acc);
 #pragma unroll
       for (int j = 0; j < DFT_MAX_FIELDS; ++j)
         if (j < nbu) *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(keep[j][0], keep[j][1]);
-      for (int v0 = 0; v0 < 128; v0 += 32) con3_step<2, float>(sF, DFT_LD, nbu, v0, sp, RT, CT, acc);
+      dft_contract<RTN>(sF, oa, ob, oc, acc);
       since += 256;
-      if (since >= 512) { since = 0; con3_flush<2>(acc, acc64); }
+      if (since >= 512) {
+        since = 0;
+#pragma unroll
+        for (int i = 0; i < RTN; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { acc64[i][j][q] += (double)acc[i][j][q]; acc[i][j][q] = 0.f; }
+      }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
-  __syncthreads();
+  // fixed-order reduction of the four waves into the block's partial sums
   double* red = (double*)smem_raw;   // reuse the fragment stage
   for (int e = tid; e < 112 * 32; e += 256) red[e] = 0.0;
   __syncthreads();
-  con3_store<2>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < RTN; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int p = i * 16 + (lane >> 4) * 4 + q, c = j * 16 + r16;
+            red[p * 32 + c] += acc64[i][j][q] + (double)acc[i][j][q];
+          }
+    }
+    __syncthreads();
+  }
+  double* out = a.partial + (size_t)blockIdx.x * 112 * 32;
+  for (int e = tid; e < 112 * 32; e += 256) out[e] = red[e];
 }
 
 // Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
@@ -674,9 +781,21 @@ void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
   b.partial = reduced;
   if (a.ntri > 0) hipLaunchKernelGGL(k3_fin, dim3((a.ntri + 127) / 128), dim3(128), 0, s, b);
 }
+template <int RTN>
+static void launch_dft3_rt(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k3_dft<RTN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k3_dft<RTN>, dim3(nblocks), dim3(256), lds, s, a);
+}
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s) {
-  (void)hipFuncSetAttribute((const void*)k3_dft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k3_dft, dim3(nblocks), dim3(256), lds, s, a);
+  switch ((a.npairs + 15) / 16) {
+    case 1: launch_dft3_rt<1>(a, nblocks, lds, s); break;
+    case 2: launch_dft3_rt<2>(a, nblocks, lds, s); break;
+    case 3: launch_dft3_rt<3>(a, nblocks, lds, s); break;
+    case 4: launch_dft3_rt<4>(a, nblocks, lds, s); break;
+    case 5: launch_dft3_rt<5>(a, nblocks, lds, s); break;
+    case 6: launch_dft3_rt<6>(a, nblocks, lds, s); break;
+    default: launch_dft3_rt<7>(a, nblocks, lds, s); break;
+  }
 }
 void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s) {
   if (mode == 1) {
