@@ -206,7 +206,7 @@ struct Dft3Args {
   int groups_per_block;
   double* partial;             // [gridDim.x][112][32]
 };
-constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LD = 136;
+constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LD = 132;   // row stride: 16 rows hit distinct banks
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s);
 
 // Reduces the per-block partials into `reduced` ([112][32]) and finalises every triangle.

@@ -516,25 +516,52 @@ typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Contraction of 128 voxels held in rows sF[j * DFT_LD + v] (v < 128) into acc: RTN pair row tiles
-// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc).
+// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc), in
+// steps (32 voxels, pair row tile); the LDS rows of the next step are read before the current
+// step's products and MFMAs.
 template <int RTN>
 __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const int (&oa)[RTN], const int (&ob)[RTN],
                                              const int (&oc)[2], f32x4 (&acc)[RTN][2]) {
-  const int lane = threadIdx.x & 63, kq = lane >> 4;
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
+  const int kq = (threadIdx.x & 63) >> 4;
+  float4 ra[2][2], rb[2][2], rc[2][2][2];
+  auto load_ab = [&](int ks, int rt, int buf) {
     const int vb = ks * 32 + kq * 8;
-    bf16x8 bh[2], bl[2];
+    ra[buf][0] = *(const float4*)&sF[oa[rt] + vb];
+    ra[buf][1] = *(const float4*)&sF[oa[rt] + vb + 4];
+    rb[buf][0] = *(const float4*)&sF[ob[rt] + vb];
+    rb[buf][1] = *(const float4*)&sF[ob[rt] + vb + 4];
+  };
+  auto load_c = [&](int ks, int buf) {
+    const int vb = ks * 32 + kq * 8;
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      const float4 x0 = *(const float4*)&sF[oc[ct] + vb], x1 = *(const float4*)&sF[oc[ct] + vb + 4];
-      const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-      split8(v, bh[ct], bl[ct]);
+      rc[buf][ct][0] = *(const float4*)&sF[oc[ct] + vb];
+      rc[buf][ct][1] = *(const float4*)&sF[oc[ct] + vb + 4];
     }
+  };
+  load_c(0, 0);
+  load_ab(0, 0, 0);
+  bf16x8 bh[2], bl[2];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
 #pragma unroll
     for (int rt = 0; rt < RTN; ++rt) {
-      const float4 a0 = *(const float4*)&sF[oa[rt] + vb], a1 = *(const float4*)&sF[oa[rt] + vb + 4];
-      const float4 b0 = *(const float4*)&sF[ob[rt] + vb], b1 = *(const float4*)&sF[ob[rt] + vb + 4];
+      const int i = ks * RTN + rt;
+      if (rt + 1 < RTN) {
+        load_ab(ks, rt + 1, (i + 1) & 1);
+      } else if (ks + 1 < 4) {
+        load_ab(ks + 1, 0, (i + 1) & 1);
+        load_c(ks + 1, (ks + 1) & 1);
+      }
+      if (rt == 0) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const float4 c0 = rc[ks & 1][ct][0], c1 = rc[ks & 1][ct][1];
+          const float v[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+          split8(v, bh[ct], bl[ct]);
+        }
+      }
+      const float4 a0 = ra[i & 1][0], a1 = ra[i & 1][1], b0 = rb[i & 1][0], b1 = rb[i & 1][1];
       const float v[8] = {a0.x * b0.x, a0.y * b0.y, a0.z * b0.z, a0.w * b0.w,
                           a1.x * b1.x, a1.y * b1.y, a1.z * b1.z, a1.w * b1.w};
       bf16x8 ah, al;
@@ -602,15 +629,7 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
   int since = 0;
   for (int g = g_beg; g < g_end; ++g) {
     for (int tt = wave; tt < ntt; tt += 4) {
-      bf16x8 wh[DFT_MAX_STEPS], wl[DFT_MAX_STEPS];
-#pragma unroll
-      for (int s = 0; s < DFT_MAX_STEPS; ++s) {
-        if (s < a.Smax) {
-          const v4u_t* wp = W + ((size_t)(tt * a.Smax + s) * 2) * 64 + lane;
-          wh[s] = __builtin_bit_cast(bf16x8, wp[0]);
-          wl[s] = __builtin_bit_cast(bf16x8, wp[64]);
-        }
-      }
+      const v4u_t* wt = W + (size_t)tt * a.Smax * 128 + lane;   // twiddle fragments of this t-tile
       float keep[DFT_MAX_FIELDS][2];
 #pragma unroll
       for (int c = 0; c < DFT_MAX_FIELDS / 4; ++c) {
@@ -626,23 +645,31 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
           f32x4 d[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) d[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+          // fragments of step s (zero fragment where a field has fewer steps), one step ahead
+          bf16x8 gh[2][4], gl[2][4], wh[2], wl[2];
+          auto fetch = [&](int s, int buf) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
+              const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
+              gh[buf][u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
+              gl[buf][u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
+            }
+            wh[buf] = __builtin_bit_cast(bf16x8, wt[s * 128]);
+            wl[buf] = __builtin_bit_cast(bf16x8, wt[s * 128 + 64]);
+          };
+          fetch(0, 0);
 #pragma unroll
           for (int s = 0; s < DFT_MAX_STEPS; ++s) {
             if (s < nst) {
-              bf16x8 gh[4], gl[4];
+              if (s + 1 < DFT_MAX_STEPS && s + 1 < nst) fetch(s + 1, (s + 1) & 1);
+              const int b = s & 1;
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
-                const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
-                gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
-                gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
-              }
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[b][u], wh[b], d[u], 0, 0, 0);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh[s], d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[b][u], wl[b], d[u], 0, 0, 0);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl[s], d[u], 0, 0, 0);
-#pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh[s], d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[b][u], wh[b], d[u], 0, 0, 0);
             }
           }
 #pragma unroll
