@@ -37,7 +37,7 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
   p.H = 0;
   p.NLe = fp64 ? 8 : 16;
   if (P.nc >= 1024) p.NLe = fp64 ? 4 : 8;
-  p.NLd = (P.nc > 512) ? (fp64 ? 4 : 8) : (fp64 ? 8 : 16);
+  p.NLd = (P.nc > 512) ? 4 : (fp64 ? 8 : 16);   // long delay axes: small blocks, several per CU
   for (size_t j = 0; j < blocks.size(); ++j) {
     int h = std::max(0, P.eta_hi[blocks[j]]);
     p.hj.push_back(h);
@@ -68,10 +68,9 @@ X* upload(bs_ctx* c, const std::string& name, const std::vector<X>& v, int& rc) 
   return d;
 }
 
-// B-fragments of v_mfma_f32_16x16x32_bf16 for the eta synthesis x(t) = sum_q a_q (Re G_q cos(2 pi q t / M)
-// - Im G_q sin(2 pi q t / M)): entry ((tt * Smax + s) * 2 + hl) * 64 + lane holds, for t = 16 tt +
-// lane % 16 and q = 16 s + 4 (lane / 16) + c (c = 0..3), the pairs (cos, -sin) as bf16 hi (hl = 0)
-// or lo (hl = 1) parts, hi = rne(x), lo = rne(x - hi).  Cached per (M, Smax).
+// Twiddle words of the eta synthesis x(t) = sum_q a_q (Re G_q cos(2 pi q t / M) - Im G_q sin(2 pi q t / M)):
+// entry m holds (cos | -sin << 16) of the bf16 hi parts and, second, of the lo parts of
+// e^{2 pi i m / M} (hi = rne(x), lo = rne(x - hi)).  Cached per M.
 uint16_t host_bf16(float x) {
   uint32_t u;
   std::memcpy(&u, &x, 4);
@@ -84,35 +83,28 @@ float host_bf16_float(uint16_t h) {
   std::memcpy(&x, &u, 4);
   return x;
 }
-const void* ctx_dft_twiddle(bs_ctx* c, int M, int Smax) {
-  const long long key = (long long)M * 64 + Smax;
-  auto it = c->dftw.find(key);
+const void* ctx_dft_twiddle(bs_ctx* c, int M) {
+  auto it = c->dftw.find(M);
   if (it != c->dftw.end()) return it->second;
-  const int ntt = M / 16;
-  std::vector<uint16_t> h((size_t)ntt * Smax * 2 * 64 * 8);
+  std::vector<uint32_t> h(2 * (size_t)M);
   const long double tp = 2.0L * 3.14159265358979323846264338327950288L;
-  for (int tt = 0; tt < ntt; ++tt)
-    for (int s = 0; s < Smax; ++s)
-      for (int lane = 0; lane < 64; ++lane) {
-        const int t = 16 * tt + (lane & 15);
-        for (int cq = 0; cq < 4; ++cq) {
-          const long long q = 16LL * s + 4 * (lane >> 4) + cq;
-          const long long m = (q * t) % M;   // exact angle reduction
-          const long double ang = tp * (long double)m / (long double)M;
-          const float v[2] = {(float)cosl(ang), (float)-sinl(ang)};
-          for (int e = 0; e < 2; ++e) {
-            const uint16_t hi = host_bf16(v[e]);
-            const uint16_t lo = host_bf16(v[e] - host_bf16_float(hi));
-            const size_t base = (((size_t)(tt * Smax + s) * 2) * 64 + lane) * 8 + 2 * cq + e;
-            h[base] = hi;
-            h[base + 64 * 8] = lo;
-          }
-        }
-      }
+  for (int m = 0; m < M; ++m) {
+    const long double ang = tp * (long double)m / (long double)M;
+    const float v[2] = {(float)cosl(ang), (float)-sinl(ang)};
+    uint32_t hi = 0, lo = 0;
+    for (int e = 0; e < 2; ++e) {
+      const uint16_t vh = host_bf16(v[e]);
+      const uint16_t vl = host_bf16(v[e] - host_bf16_float(vh));
+      hi |= (uint32_t)vh << (16 * e);
+      lo |= (uint32_t)vl << (16 * e);
+    }
+    h[2 * m] = hi;
+    h[2 * m + 1] = lo;
+  }
   void* d = nullptr;
-  if (hipMalloc(&d, h.size() * 2) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
-  if (hipMemcpy(d, h.data(), h.size() * 2, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
-  c->dftw[key] = d;
+  if (hipMalloc(&d, h.size() * 4) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  if (hipMemcpy(d, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
+  c->dftw[M] = d;
   return d;
 }
 
@@ -309,7 +301,8 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
   e.nblk = std::min<long long>(2048, (e.nvox + 127) / 128);
   e.chunk = ((e.nvox + e.nblk - 1) / e.nblk + 127) / 128 * 128;
   e.nblk = (e.nvox + e.chunk - 1) / e.chunk;
-  e.partial = (double*)ctx_ws(c, (tag + "_partial").c_str(), (size_t)std::max<long long>(e.nblk, 1024) * 112 * 32 * 8);
+  // partial sums: one slot per contraction block, or per wave of the MFMA synthesis kernel (8 x 256)
+  e.partial = (double*)ctx_ws(c, (tag + "_partial").c_str(), (size_t)std::max<long long>(e.nblk, 2048) * 112 * 32 * 8);
   e.reduced = (double*)ctx_ws(c, (tag + "_reduced").c_str(), (size_t)112 * 32 * 8);
   if (!e.partial || !e.reduced) return ctx_fail(c, BS_ENOMEM, "workspace (partials)");
   e.rho3 = 1.0;
@@ -415,9 +408,9 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     int Smax = 0;
     for (int h : e.pd.hj) { Sj.push_back((h + 16) / 16); kb.push_back(kb.back() + Sj.back()); Smax = std::max(Smax, Sj.back()); }
     // fragment stage (+ one zero fragment) and four waves of field rows (+ one zero row each)
-    const size_t dlds = (size_t)(2 * kb.back() + 1) * 1024 + (size_t)4 * (DFT_MAX_FIELDS + 1) * DFT_LD * 4;
+    const size_t dlds = (size_t)(2 * kb.back() + 1) * 1024 + (size_t)M * 8 + (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
-            std::max(dlds, (size_t)112 * 32 * 8) <= 160 * 1024 && e.pd.NLu == 16 && !getenv("BS_3D_FFT");
+            dlds <= 160 * 1024 && e.pd.NLu == 16 && (M / 16) % DFT_WAVES == 0 && !getenv("BS_3D_FFT");
     if (e.dft) {
       const long long ngroups = nlines / 16;
       std::vector<long long> offGs;
@@ -433,7 +426,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       da.Sj = upload(c, tag + "_Sj", Sj, rc); if (rc) return rc;
       da.kb = upload(c, tag + "_kb", kb, rc); if (rc) return rc;
       da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;
-      da.W = ctx_dft_twiddle(c, M, Smax);
+      da.W = ctx_dft_twiddle(c, M);
       if (!da.W) return ctx_fail(c, BS_ENOMEM, "eta twiddle fragments");
       da.pairs = e.d_pairs; da.npairs = e.npairs;
       da.ngroups = (int)ngroups;
@@ -441,7 +434,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       da.groups_per_block = (int)((ngroups + e.dblocks - 1) / e.dblocks);
       e.dblocks = (int)((ngroups + da.groups_per_block - 1) / da.groups_per_block);
       da.partial = e.partial;
-      e.dlds = std::max(dlds, (size_t)112 * 32 * 8);
+      e.dlds = dlds;
     }
   } else {
     e.F = ctx_ws(c, (tag + "_F").c_str(), (size_t)e.blocks.size() * e.nvox * (e.fp64 ? 8 : 4));
@@ -464,7 +457,7 @@ int est3_enqueue(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights*
     if (e.dft) {
       launch_dft3(e.da, e.dblocks, e.dlds, c->stream);
       LAUNCHCHK(c, "eta synthesis and contraction");
-      nparts = e.dblocks;
+      nparts = e.dblocks * DFT_WAVES;   // one partial slot per wave
     } else {
       launch_fused3(e.fa, e.precision == BS_FP32 ? 1 : 2, e.fblocks, e.lds, c->stream);
       LAUNCHCHK(c, "fused contraction");

@@ -32,7 +32,7 @@ struct bs_ctx {
   std::string err;
   std::map<std::string, DevBuf> ws;      // grow-only workspace slots
   std::map<int, void*> tw32, tw64;        // twiddle tables exp(-2 pi i m / L), by L
-  std::map<long long, void*> dftw;       // eta-synthesis twiddle fragments, by (M, K-steps)
+  std::map<long long, void*> dftw;       // eta-synthesis twiddle words, by M
   std::map<uint64_t, CountCache> counts;  // geometry-keyed count caches
   bool timing = false;
   hipEvent_t ev[8] = {};

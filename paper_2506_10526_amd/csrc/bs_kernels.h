@@ -191,8 +191,9 @@ constexpr int FUSED_DIRECT_H = 6;
 // and K-step s (modes 16 s .. 16 s + 15), two 1 KB fragments (hi, lo) at
 // Gs[offGs[j] + (g * S_j + s) * 128 + hl * 64 + lane]; lane l holds line x_u = 16 (x_u / 16) + l % 16
 // and the reals (Re, Im) of modes 16 s + 4 (l / 16) + c, c = 0..3, scaled by a_q / (M n^2)
-// (a_0 = 1 with Im dropped, a_q = 2).  W holds the matching B-fragments of cos / -sin
-// (2 pi q t / M) for t-tile tt: W[((tt * Smax + s) * 2 + hl) * 64 + lane], t = 16 tt + l % 16.
+// (a_0 = 1 with Im dropped, a_q = 2).  W holds, for m = 0..M-1, the words (cos | -sin << 16) of the
+// bf16 hi parts and of the lo parts of e^{2 pi i m / M}: the B-fragment word c of lane l for step s
+// and t = 16 tt + l % 16 is entry (16 s + 4 (l / 16) + c) t mod M.
 struct Dft3Args {
   const void* Gs;              // uint4 fragments
   const long long* offGs;      // per block (16-byte units)
@@ -200,13 +201,14 @@ struct Dft3Args {
   const int* kb;               // per block: prefix of Sj
   int nbu;                     // fields (<= DFT_MAX_FIELDS)
   int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
-  const void* W;               // uint4 twiddle fragments
+  const void* W;               // [M] uint2 twiddle words
   const int* pairs; int npairs;
   int ngroups;                 // line groups n * n / 16
   int groups_per_block;
-  double* partial;             // [gridDim.x][112][32]
+  double* partial;             // [gridDim.x * DFT_WAVES][112][32]: one slot per wave
 };
-constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LD = 132;   // row stride: 16 rows hit distinct banks
+constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LDQ = 68;   // row stride: 16 rows hit distinct banks
+constexpr int DFT_WAVES = 8;   // waves per block, two per SIMD (a power of two dividing M / 16)
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s);
 
 // Reduces the per-block partials into `reduced` ([112][32]) and finalises every triangle.

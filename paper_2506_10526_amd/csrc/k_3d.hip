@@ -502,23 +502,25 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 }
 
 // Split-BF16 fused kernel: the C2R along eta as MFMA GEMMs against a twiddle-fragment table, then
-// the pair x field contraction.  A block owns a range of line groups (16 consecutive x_u of one
-// x_v).  For each group it copies the group's spectrum fragments (all fields, all K-steps) into
-// LDS with 16-byte global_load_lds; each wave then takes t-tiles of 16 delay samples and computes,
-// for every field j, F_j[16 lines][16 t] = sum over K-steps of three MFMAs (lo.hi, hi.lo, hi.hi),
-// four fields at a time so that consecutive MFMAs are independent (missing K-steps read a zero
-// fragment).  Lane l then holds F_j at lines 4 (l / 16) + i, t = l % 16 (i = 0..3): the halves
-// i < 2 and i >= 2 pass in turn through the wave's own LDS rows (voxel 2 l + (i & 1)) into the
+// the pair x field contraction.  A block of DFT_WAVES waves owns a range of line groups
+// (16 consecutive x_u of one x_v).  For each group it copies the group's spectrum fragments (all
+// fields, all K-steps) into LDS with 16-byte global_load_lds; each wave then takes t-tiles of 16
+// delay samples and computes, for every field j, F_j[16 lines][16 t] = sum over K-steps of three
+// MFMAs (lo.hi, hi.lo, hi.hi), four fields at a time so that consecutive MFMAs are independent
+// (missing K-steps read a zero fragment).  Lane l then holds F_j at lines 4 (l / 16) + i,
+// t = l % 16 (i = 0..3); quarter i passes through the wave's own LDS rows (voxel l) into the
 // contraction, whose pair rows and padding (a zero row) are resolved once per lane.  The copy of
 // the next group's fragments is issued once every wave has finished its last synthesis of the
-// current group, and lands while that tile is contracted.
+// current group and lands while that tile is contracted.  Each wave adds its FP32 sums into its
+// own FP64 slot of `partial` every 512 voxels.
 typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Contraction of 128 voxels held in rows sF[j * DFT_LD + v] (v < 128) into acc: RTN pair row tiles
-// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc), in
-// steps (32 voxels, pair row tile); the LDS rows of the next step are read before the current
-// step's products and MFMAs.
+// Contraction of 64 voxels held in rows sF[j * DFT_LDQ + v] (v < 64) into acc: RTN pair row tiles
+// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc).  Steps
+// (32 voxels, pair row tile) are issued as: LDS reads of the next step, products and splits of this
+// step, its six MFMAs; sched_barrier keeps that order (the compiler would otherwise wait for every
+// read right before its use).
 template <int RTN>
 __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const int (&oa)[RTN], const int (&ob)[RTN],
                                              const int (&oc)[2], f32x4 (&acc)[RTN][2]) {
@@ -543,16 +545,18 @@ __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const
   load_ab(0, 0, 0);
   bf16x8 bh[2], bl[2];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
+  for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
     for (int rt = 0; rt < RTN; ++rt) {
       const int i = ks * RTN + rt;
+      __builtin_amdgcn_sched_barrier(0);
       if (rt + 1 < RTN) {
         load_ab(ks, rt + 1, (i + 1) & 1);
-      } else if (ks + 1 < 4) {
+      } else if (ks + 1 < 2) {
         load_ab(ks + 1, 0, (i + 1) & 1);
         load_c(ks + 1, (ks + 1) & 1);
       }
+      __builtin_amdgcn_sched_barrier(0);
       if (rt == 0) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
@@ -566,6 +570,7 @@ __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const
                           a1.x * b1.x, a1.y * b1.y, a1.z * b1.z, a1.w * b1.w};
       bf16x8 ah, al;
       split8(v, ah, al);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
@@ -574,51 +579,72 @@ __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const
       }
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int RTN>
-__global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
+__global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int ROWS = DFT_MAX_FIELDS + 1;   // fields + one zero row
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15;
   const int nbu = a.nbu, nfr = 2 * a.kb[nbu];
+  const int M = a.M;
   v4u_t* stage = (v4u_t*)smem_raw;                                      // [nfr + 1][64], last = zeros
-  float* fields = (float*)(stage + (size_t)(nfr + 1) * 64);
-  float* sF = fields + (size_t)wave * ROWS * DFT_LD;                    // this wave's rows
+  uint2* tw = (uint2*)(stage + (size_t)(nfr + 1) * 64);                 // [M] twiddle words
+  float* sF = (float*)(tw + M) + (size_t)wave * ROWS * DFT_LDQ;         // this wave's rows
   stage[(size_t)nfr * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
-  for (int e = lane; e < DFT_LD; e += 64) sF[DFT_MAX_FIELDS * DFT_LD + e] = 0.f;
+  for (int e = tid; e < M; e += DFT_WAVES * 64) tw[e] = ((const uint2*)a.W)[e];
+  for (int e = lane; e < DFT_LDQ; e += 64) sF[DFT_MAX_FIELDS * DFT_LDQ + e] = 0.f;
   // per-lane contraction rows: pair (a, b) of row rt * 16 + r16 and field c = ct * 16 + r16
   int oa[RTN], ob[RTN], oc[2];
 #pragma unroll
   for (int rt = 0; rt < RTN; ++rt) {
     const int p = rt * 16 + r16;
     const bool ok = p < a.npairs;
-    oa[rt] = (ok ? a.pairs[2 * p] : DFT_MAX_FIELDS) * DFT_LD;
-    ob[rt] = (ok ? a.pairs[2 * p + 1] : DFT_MAX_FIELDS) * DFT_LD;
+    oa[rt] = (ok ? a.pairs[2 * p] : DFT_MAX_FIELDS) * DFT_LDQ;
+    ob[rt] = (ok ? a.pairs[2 * p + 1] : DFT_MAX_FIELDS) * DFT_LDQ;
   }
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int c = ct * 16 + r16;
-    oc[ct] = (c < nbu ? c : DFT_MAX_FIELDS) * DFT_LD;
+    oc[ct] = (c < nbu ? c : DFT_MAX_FIELDS) * DFT_LDQ;
   }
+  // this wave's FP64 slot: rows past the pair tiles are zero; the owned entries are written on the
+  // first flush and accumulated afterwards (always by the owning lane)
+  double* slot = a.partial + ((size_t)blockIdx.x * DFT_WAVES + wave) * 112 * 32;
+  for (int e = RTN * 16 * 32 + lane; e < 112 * 32; e += 64) slot[e] = 0.0;
   f32x4 acc[RTN][2];
-  double acc64[RTN][2][4];
 #pragma unroll
   for (int i = 0; i < RTN; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bool first = true;
+  auto flush = [&]() {
+    // the lane index passes through an empty asm so that the addresses are formed here
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
 #pragma unroll
-      for (int q = 0; q < 4; ++q) { acc[i][j][q] = 0.f; acc64[i][j][q] = 0.0; }
+    for (int i = 0; i < RTN; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double* d = &slot[(i * 16 + (ln >> 4) * 4 + q) * 32 + j * 16 + (ln & 15)];
+          const double v = (double)acc[i][j][q];
+          *d = first ? v : *d + v;
+          acc[i][j][q] = 0.f;
+        }
+    first = false;
+  };
   const v4u_t* Gs = (const v4u_t*)a.Gs;
-  const v4u_t* W = (const v4u_t*)a.W;
-  const int ntt = a.M >> 4;   // a multiple of 8: every wave takes ntt / 4 tiles per group
+  const int ntt = M >> 4;   // a multiple of 8: every wave takes ntt / DFT_WAVES tiles per group
   const int g_beg = blockIdx.x * a.groups_per_block;
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
   auto copy_group = [&](int g) {
     for (int j = 0; j < nbu; ++j) {
       const int S = a.Sj[j], f0 = 2 * a.kb[j];
       const v4u_t* src = Gs + a.offGs[j] + (size_t)g * S * 128 + lane;
-      for (int s2 = (wave - f0) & 3; s2 < 2 * S; s2 += 4)
+      for (int s2 = (wave - f0) & (DFT_WAVES - 1); s2 < 2 * S; s2 += DFT_WAVES)
         __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
                                          16, 0, 0);
     }
@@ -628,9 +654,12 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
   __syncthreads();
   int since = 0;
   for (int g = g_beg; g < g_end; ++g) {
-    for (int tt = wave; tt < ntt; tt += 4) {
-      const v4u_t* wt = W + (size_t)tt * a.Smax * 128 + lane;   // twiddle fragments of this t-tile
-      float keep[DFT_MAX_FIELDS][2];
+    for (int tt = wave; tt < ntt; tt += DFT_WAVES) {
+      // twiddle B-fragment of step s for this lane: words c = 0..3 are the table entries at
+      // m_c = q_c t mod M, q_c = 16 s + 4 (lane / 16) + c, t = 16 tt + lane % 16
+      const int t = 16 * tt + r16;
+      const int m00 = (4 * (lane >> 4) * t) % M, st16 = (16 * t) % M;
+      f32x4 dk[DFT_MAX_FIELDS];                                   // every field's 16 x 16 tile
 #pragma unroll
       for (int c = 0; c < DFT_MAX_FIELDS / 4; ++c) {
         if (4 * c < nbu) {
@@ -645,86 +674,61 @@ __global__ __launch_bounds__(256) void k3_dft(Dft3Args a) {
           f32x4 d[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) d[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-          // fragments of step s (zero fragment where a field has fewer steps), one step ahead
-          bf16x8 gh[2][4], gl[2][4], wh[2], wl[2];
-          auto fetch = [&](int s, int buf) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
-              const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
-              gh[buf][u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
-              gl[buf][u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
-            }
-            wh[buf] = __builtin_bit_cast(bf16x8, wt[s * 128]);
-            wl[buf] = __builtin_bit_cast(bf16x8, wt[s * 128 + 64]);
-          };
-          fetch(0, 0);
+          int m0 = m00;
 #pragma unroll
           for (int s = 0; s < DFT_MAX_STEPS; ++s) {
             if (s < nst) {
-              if (s + 1 < DFT_MAX_STEPS && s + 1 < nst) fetch(s + 1, (s + 1) & 1);
-              const int b = s & 1;
+              bf16x8 gh[4], gl[4];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[b][u], wh[b], d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) {
+                const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
+                const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
+                gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
+                gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
+              }
+              uint2 w4[4];
+              int m = m0;
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[b][u], wl[b], d[u], 0, 0, 0);
+              for (int cq = 0; cq < 4; ++cq) {
+                w4[cq] = tw[m];
+                m += t;
+                if (m >= M) m -= M;
+              }
+              m0 += st16;
+              if (m0 >= M) m0 -= M;
+              const bf16x8 wh = __builtin_bit_cast(bf16x8, v4u_t{w4[0].x, w4[1].x, w4[2].x, w4[3].x});
+              const bf16x8 wl = __builtin_bit_cast(bf16x8, v4u_t{w4[0].y, w4[1].y, w4[2].y, w4[3].y});
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[b][u], wh[b], d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh, d[u], 0, 0, 0);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl, d[u], 0, 0, 0);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh, d[u], 0, 0, 0);
             }
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = 4 * c + u;
-            *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(d[u][0], d[u][1]);
-            keep[j][0] = d[u][2];
-            keep[j][1] = d[u][3];
-          }
+          for (int u = 0; u < 4; ++u) dk[4 * c + u] = d[u];
         }
       }
-      if (tt + 4 >= ntt) {
+      if (tt + DFT_WAVES >= ntt) {
         // the group's last synthesis on every wave: the fragments of the next group may land
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
       }
-      dft_contract<RTN>(sF, oa, ob, oc, acc);
 #pragma unroll
-      for (int j = 0; j < DFT_MAX_FIELDS; ++j)
-        if (j < nbu) *(float2*)&sF[(size_t)j * DFT_LD + 2 * lane] = make_float2(keep[j][0], keep[j][1]);
-      dft_contract<RTN>(sF, oa, ob, oc, acc);
-      since += 256;
-      if (since >= 512) {
-        since = 0;
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int i = 0; i < RTN; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { acc64[i][j][q] += (double)acc[i][j][q]; acc[i][j][q] = 0.f; }
+        for (int j = 0; j < DFT_MAX_FIELDS; ++j)
+          if (j < nbu) sF[(size_t)j * DFT_LDQ + lane] = dk[j][q];
+        dft_contract<RTN>(sF, oa, ob, oc, acc);
       }
+      since += 256;
+      if (since >= 512) { since = 0; flush(); }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  // fixed-order reduction of the four waves into the block's partial sums
-  double* red = (double*)smem_raw;   // reuse the fragment stage
-  for (int e = tid; e < 112 * 32; e += 256) red[e] = 0.0;
-  __syncthreads();
-  for (int wv = 0; wv < 4; ++wv) {
-    if (wave == wv) {
-#pragma unroll
-      for (int i = 0; i < RTN; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int p = i * 16 + (lane >> 4) * 4 + q, c = j * 16 + r16;
-            red[p * 32 + c] += acc64[i][j][q] + (double)acc[i][j][q];
-          }
-    }
-    __syncthreads();
-  }
-  double* out = a.partial + (size_t)blockIdx.x * 112 * 32;
-  for (int e = tid; e < 112 * 32; e += 256) out[e] = red[e];
+  flush();
 }
 
 // Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
@@ -811,7 +815,7 @@ void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
 template <int RTN>
 static void launch_dft3_rt(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s) {
   (void)hipFuncSetAttribute((const void*)k3_dft<RTN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k3_dft<RTN>, dim3(nblocks), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k3_dft<RTN>, dim3(nblocks), dim3(DFT_WAVES * 64), lds, s, a);
 }
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s) {
   switch ((a.npairs + 15) / 16) {
