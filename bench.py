@@ -30,11 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {"k3_fused<split-bf16>": None}
+TRAFFIC_BYTES = {"k3_dft": None}
 
 
 def log(*a):
@@ -283,22 +282,21 @@ def main():
                 "split_over_fp32": t32 / t_split,
                 "max_abs_diff_split_vs_fp32_over_max_B": float(np.max(np.abs(Bs[ok] - B32[ok])) / np.max(np.abs(B32[ok])))}
         log(f"[bench] fp32: {t32 * 1e3:.3f} ms/step, contraction {tim32[1]:.3f} ms")
-    # Dominant kernel of the split step: the fused eta-C2R + contraction (k3_fused).  It is bound
-    # by vector ALU / LDS instruction issue, not by HBM, so it is priced in algorithmic FP32
-    # flops per contracted voxel (M n^2 voxels on the M-point delay grid):
-    #   20 shells x 2.5 log2(M) (real inverse FFT along eta)
-    #   + one multiply per (b1, b2) pair of a valid triangle + one multiply-add per valid triangle
+    # Dominant kernel of the split step: k3_dft, the eta synthesis of every shell field as MFMA
+    # GEMMs against twiddle fragments, fused with the pair x field contraction on MFMA.  It is
+    # priced against the dense bf16 MFMA peak with its algorithmic split-BF16 work per contracted
+    # voxel (reported by the library): 3 bf16 products x 2 flops x 2 (H_j + 1) real modes per
+    # field for the synthesis, 3 x 2 x P x F for the contraction (P product rows, F fields), on
+    # the M n^2 voxels of the M-point delay grid.
     M = int(tim_split[3]) or w.nc
-    valid = tri[Nt > 0]
-    n_pairs = len({(int(a), int(b)) for a, b, _ in valid})
-    flops_per_vox = 20 * 2.5 * np.log2(M) + n_pairs + 2.0 * n_valid
-    vox_c = M * w.n * w.n
+    flops_per_vox = tim_split[4]
+    vox_c = int(tim_split[5]) or M * w.n * w.n
     con_ms = tim_split[1]
     fld_ms = tim_split[2]
     ach = flops_per_vox * vox_c / (con_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k3_fused<split-bf16> (eta C2R + contraction)", "achieved": ach,
-            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
-            "traffic": TRAFFIC_BYTES.get("k3_fused<split-bf16>"), "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
+    roof = {"bound": "mfma", "kernel": "k3_dft (eta synthesis + contraction, split-BF16 MFMA)", "achieved": ach,
+            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+            "traffic": TRAFFIC_BYTES.get("k3_dft"), "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
             "delay_grid_M": M, "avg_ms": con_ms,
             "fields_kernels_ms": fld_ms}
     mabs = None

@@ -289,7 +289,12 @@ int bs_var_features(const bs_bins* bins, const int64_t* T3D_host, double pk_inde
  * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP
  * events on the context's stream: out_ms_host[0] = whole call, [1] = the dominant contraction kernel,
  * [2] = fields/FFT kernels, [3] = the delay-axis grid length M the last 3D
- * contraction ran on (0 before any 3D call).  Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
+ * contraction ran on (0 before any 3D call), [4] = algorithmic split-BF16 MFMA flops per
+ * contracted voxel of the last 3D split-BF16 contraction when it ran the MFMA synthesis kernel
+ * (12 sum_j (H_j + 1) for the eta synthesis of the Hermitian half spectra, H_j the largest |eta|
+ * of field j, plus 6 P F for the pair x field contraction, P product rows and F fields; 0 otherwise),
+ * [5] = voxels contracted by that launch (M n^2).  n selects how many values are written (at most 6).
+ * Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
 int bs_set_timing(bs_ctx* ctx, int32_t enable);
 int bs_last_timing(const bs_ctx* ctx, double* out_ms_host, int32_t n);
 /* Largest |x - rint(x)| over the FP64 triangle counts x of the last estimate (or of the cached

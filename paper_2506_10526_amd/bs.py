@@ -240,8 +240,8 @@ def bs_set_timing(ctx: int, enable: bool) -> None:
 
 
 def bs_last_timing(ctx: int):
-    out = (ctypes.c_double * 4)()
-    _check(ctx, lib().bs_last_timing(ctx, out, 4))
+    out = (ctypes.c_double * 6)()
+    _check(ctx, lib().bs_last_timing(ctx, out, 6))
     return list(out)
 
 

@@ -148,12 +148,12 @@ extern "C" int bs_last_timing(const bs_ctx* cc, double* out, int32_t n) {
   // events: 0 start, 1 end, 2/3 contraction, 4/5 fields
   float ms = 0.f;
   if (hipEventSynchronize(c->ev[1]) != hipSuccess) return BS_EHIP;
-  double v[4] = {0, 0, 0, (double)c->last_grid_M};
+  double v[6] = {0, 0, 0, (double)c->last_grid_M, c->last_flops_vox, c->last_vox};
   if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) v[0] = ms;
   if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) v[1] = ms;
   if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) v[2] = ms;
   (void)hipGetLastError();
-  for (int i = 0; i < n && i < 4; ++i) out[i] = v[i];
+  for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
   return BS_OK;
 }
 

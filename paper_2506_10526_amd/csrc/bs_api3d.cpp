@@ -501,6 +501,14 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   rc = est3_enqueue(c, b, vis, w, e, norm, B, N_tri, N_eff);
   if (rc) return rc;
   c->last_grid_M = e.M;
+  c->last_flops_vox = 0.0;
+  c->last_vox = 0.0;
+  if (e.dft) {
+    double modes = 0.0;
+    for (int h : e.pd.hj) modes += h + 1;
+    c->last_flops_vox = 12.0 * modes + 6.0 * e.npairs * (double)e.blocks.size();
+    c->last_vox = (double)e.M * b->P.n * b->P.n;
+  }
   if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }
   return BS_OK;
 }

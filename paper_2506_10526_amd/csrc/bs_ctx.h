@@ -40,6 +40,7 @@ struct bs_ctx {
   bool have_timing = false;
   double last_count_dev = 0.0;
   int last_grid_M = 0;   // delay-axis grid of the last 3D contraction
+  double last_flops_vox = 0.0, last_vox = 0.0;   // algorithmic MFMA flops per voxel, voxels (MFMA synthesis path)
   std::map<std::string, int> tuned;       // autotuned launch parameters, by shape key
 };
 
