@@ -476,6 +476,12 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
   long long blocks_batch = tiles_per_tri * tb;
   int kchunks = 1;
   while (blocks_batch * kchunks < 2048 && Ppix / (kchunks * 2) >= 1024 && (Ppix / (kchunks * 2)) % 32 == 0) kchunks *= 2;
+  // BS_MABS_KCHUNKS (tests): a fixed pixel-chunk count, so that small GEMMs run the long chunks of
+  // large ones (used only if it splits the pixels into multiples of 32)
+  if (const char* ek = getenv("BS_MABS_KCHUNKS")) {
+    const int k = atoi(ek);
+    if (k >= 1 && Ppix % k == 0 && (Ppix / k) % 32 == 0) kchunks = k;
+  }
   int kchunk = Ppix / kchunks;
   // the batch must hold kchunks partial copies
   tb = (int)std::max<size_t>(1, std::min<size_t>(ntri, budget / std::max<size_t>(per_tri * kchunks, 1)));

@@ -430,7 +430,12 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       if (!da.W) return ctx_fail(c, BS_ENOMEM, "eta twiddle fragments");
       da.pairs = e.d_pairs; da.npairs = e.npairs;
       da.ngroups = (int)ngroups;
-      e.dblocks = (int)std::min<long long>(ngroups, 256);
+      // BS_3D_DFT_BLOCKS / BS_3D_DFT_FLUSH (tests): fewer blocks and shorter flush intervals put
+      // several line groups and flushes on every wave of a small cube
+      const char* eb = getenv("BS_3D_DFT_BLOCKS");
+      const char* ef = getenv("BS_3D_DFT_FLUSH");
+      da.flush_vox = ef ? std::max(256, atoi(ef)) : 4096;
+      e.dblocks = (int)std::min<long long>(ngroups, eb ? std::max(1, atoi(eb)) : 256);
       da.groups_per_block = (int)((ngroups + e.dblocks - 1) / e.dblocks);
       e.dblocks = (int)((ngroups + da.groups_per_block - 1) / da.groups_per_block);
       da.partial = e.partial;

@@ -205,6 +205,7 @@ struct Dft3Args {
   const int* pairs; int npairs;
   int ngroups;                 // line groups n * n / 16
   int groups_per_block;
+  int flush_vox;               // voxels per wave between FP64 flushes (4096: 128 FP32 MFMA accumulations)
   double* partial;             // [gridDim.x * DFT_WAVES][112][32]: one slot per wave
 };
 constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LDQ = 68;   // row stride: 16 rows hit distinct banks

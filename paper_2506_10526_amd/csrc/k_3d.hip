@@ -512,10 +512,9 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // contraction, whose pair rows and padding (a zero row) are resolved once per lane.  The copy of
 // the next group's fragments is issued once every wave has finished its last synthesis of the
 // current group and lands while that tile is contracted.  Each wave adds its FP32 sums into its
-// own FP64 slot of `partial` every DFT_FLUSH voxels.
+// own FP64 slot of `partial` every a.flush_vox voxels.
 typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
-constexpr int DFT_FLUSH = 4096;   // voxels per wave between FP64 flushes (128 FP32 MFMA accumulations)
 
 // Contraction of 64 voxels held in rows sF[j * DFT_LDQ + v] (v < 64) into acc: RTN pair row tiles
 // (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc).  Steps
@@ -724,7 +723,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
         dft_contract<RTN>(sF, oa, ob, oc, acc);
       }
       since += 256;
-      if (since >= DFT_FLUSH) { since = 0; flush(); }
+      if (since >= a.flush_vox) { since = 0; flush(); }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();

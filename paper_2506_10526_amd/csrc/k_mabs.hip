@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_mabs_gemm(MabsGemmArgs a) {
 // column block and neighbouring A rows run on the same XCD (blocks are dealt to the eight XCDs
 // round-robin).
 // ---------------------------------------------------------------------------
-constexpr int S_TM = 128, S_TN = 256, S_TK = 32, SFLUSH = 4096;
+constexpr int S_TM = 128, S_TN = 256, S_TK = 32, SFLUSH = 8192;
 // uint16 offsets inside one stage buffer
 constexpr int S_AH = 0, S_AL = S_TM * S_TK, S_BH = 2 * S_TM * S_TK, S_BL = S_BH + S_TN * S_TK;
 constexpr int S_BUF = S_BL + S_TN * S_TK;

@@ -227,3 +227,25 @@ def test_full_row_tiles(ctx):
         bs.bs_free_bins(h)
     assert np.array_equal(Ng, Nref)
     compare_B(Bg, Bref, Nref, scale, TOL[bs.BS_SPLIT_BF16], "full row tiles")
+
+
+@pytest.mark.parametrize("prec", [bs.BS_SPLIT_BF16, bs.BS_FP32])
+def test_multi_flush(ctx, prec, monkeypatch):
+    """128^2 pixels in one pixel chunk (BS_MABS_KCHUNKS=1): every split-BF16 block adds two FP32 runs
+    of 8192 pixels into its FP64 sums (the read-modify-write of the flush), and the FP32 kernel 64
+    runs of 256; checked against the oracle for two nu1 rows."""
+    monkeypatch.setenv("BS_MABS_KCHUNKS", "1")
+    n, nc = 128, 8
+    w = synth.small_workload(n, nc)
+    edges = np.geomspace(1.0, synth.default_umax(n) + 1.0, 5)
+    V = synth.make_cube(w, seed=41)
+    b = ob.make_bins(ob.RING_U, n, nc, edges)
+    nu1 = [1, 6]
+    Bref, Nref, scale = oracle_full(b, V, None, nu1=nu1)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, n, nc, edges)
+    try:
+        Bg, Ng = run_gpu(ctx, h, V, prec, ncand, len(nu1), nc, nu1=nu1)
+    finally:
+        bs.bs_free_bins(h)
+    assert np.array_equal(Ng, Nref)
+    compare_B(Bg, Bref, Nref, scale, TOL[prec], f"multi flush prec={prec}")
