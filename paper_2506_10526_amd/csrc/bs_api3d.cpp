@@ -410,7 +410,8 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     // fragment stage (+ one zero fragment) and four waves of field rows (+ one zero row each)
     const size_t dlds = (size_t)(2 * kb.back() + 1) * 1024 + (size_t)M * 8 + (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
-            dlds <= 160 * 1024 && e.pd.NLu == 16 && (M / 16) % DFT_WAVES == 0 && !getenv("BS_3D_FFT");
+            dlds <= 160 * 1024 && (e.pd.NLu == 16 || e.pd.NLu == 8) && (M / 16) % DFT_WAVES == 0 &&
+            !getenv("BS_3D_FFT");
     if (e.dft) {
       const long long ngroups = nlines / 16;
       std::vector<long long> offGs;

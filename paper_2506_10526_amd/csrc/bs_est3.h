@@ -18,7 +18,7 @@ struct Plan3 {
   long long totT = 0, totG = 0;
   int H = 0;
   std::vector<Work3> wv, wu, we;
-  int NLv = 8, NLu = 16, NLe = 16, NLd = 8;
+  int NLv = 8, NLu = 8, NLe = 16, NLd = 8;
 };
 
 // Device-side state of the field pipeline of one plan: workspaces and work lists.  Prepared once

@@ -131,13 +131,20 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
   if constexpr (std::is_same<T, float>::value) {
     if (a.gs) {
-      // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column
+      // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column:
+      // the lanes whose modes 16 s + 4 (lane / 16) .. +3 lie in this item's planes e0 .. e0 + NL - 1
+      // (NL = 16: all lanes; NL = 8: two of the four lane groups, or all four in a step's last item)
       const int S = (hp1 + 15) >> 4, s = e0 >> 4, nxub = n >> 4;
+      // lane groups of this item and the first one; an item that starts a step and holds all of
+      // its remaining planes also writes the zero padding of the step's other lane groups
+      const bool whole = (e0 & 15) == 0 && hp1 - e0 <= a.NL;
+      const int gpl = whole ? 4 : a.NL >> 2, g0 = whole ? 0 : (e0 & 15) >> 2;
       uint4* out = (uint4*)a.gs + a.off_gs[w.j];
       const float sc = (float)a.scale;
-      for (int e = threadIdx.x; e < nxub * 64; e += blockDim.x) {
-        const int xub = e >> 6, lane = e & 63;
-        const int xu = xub * 16 + (lane & 15), q0 = 4 * (lane >> 4);
+      for (int e = threadIdx.x; e < nxub * 16 * gpl; e += blockDim.x) {
+        const int xub = e / (16 * gpl), lr = e - xub * 16 * gpl;
+        const int lane = g0 * 16 + lr;
+        const int xu = xub * 16 + (lane & 15), q0 = 4 * (lane >> 4) - (e0 & 15);
         uint32_t hw[4], lw[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
