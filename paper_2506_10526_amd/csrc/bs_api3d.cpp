@@ -423,9 +423,9 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       e.fd.gscale = fa.scale;
       Dft3Args& da = e.da;
       da = Dft3Args{};
-      da.Gs = e.fd.Gs; da.offGs = e.fd.d_offGs;
-      da.Sj = upload(c, tag + "_Sj", Sj, rc); if (rc) return rc;
-      da.kb = upload(c, tag + "_kb", kb, rc); if (rc) return rc;
+      da.Gs = e.fd.Gs;
+      for (int j = 0; j < fa.nbu; ++j) { da.offGs[j] = offGs[j]; da.Sj[j] = Sj[j]; }
+      for (int j = 0; j <= fa.nbu; ++j) da.kb[j] = kb[j];
       da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;
       da.W = ctx_dft_twiddle(c, M);
       if (!da.W) return ctx_fail(c, BS_ENOMEM, "eta twiddle fragments");

@@ -194,12 +194,15 @@ constexpr int FUSED_DIRECT_H = 6;
 // (a_0 = 1 with Im dropped, a_q = 2).  W holds, for m = 0..M-1, the words (cos | -sin << 16) of the
 // bf16 hi parts and of the lo parts of e^{2 pi i m / M}: the B-fragment word c of lane l for step s
 // and t = 16 tt + l % 16 is entry (16 s + 4 (l / 16) + c) t mod M.
+constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LDQ = 68;   // row stride: 16 rows hit distinct banks
+// The per-field tables travel by value in the kernel arguments: the kernel reads them as uniform
+// scalars, so a table read never waits for the fragment copies in flight.
 struct Dft3Args {
-  const void* Gs;              // uint4 fragments
-  const long long* offGs;      // per block (16-byte units)
-  const int* Sj;               // per block: K-steps ceil((H_j + 1) / 16)
-  const int* kb;               // per block: prefix of Sj
-  int nbu;                     // fields (<= DFT_MAX_FIELDS)
+  const void* Gs;                           // uint4 fragments
+  long long offGs[DFT_MAX_FIELDS];          // per field (16-byte units)
+  int Sj[DFT_MAX_FIELDS];                   // per field: K-steps ceil((H_j + 1) / 16)
+  int kb[DFT_MAX_FIELDS + 1];               // prefix of Sj
+  int nbu;                                  // fields (<= DFT_MAX_FIELDS)
   int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
   const void* W;               // [M] uint2 twiddle words
   const int* pairs; int npairs;
@@ -208,7 +211,6 @@ struct Dft3Args {
   int flush_vox;               // voxels per wave between FP64 flushes (4096: 128 FP32 MFMA accumulations)
   double* partial;             // [gridDim.x * DFT_WAVES][112][32]: one slot per wave
 };
-constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LDQ = 68;   // row stride: 16 rows hit distinct banks
 constexpr int DFT_WAVES = 8;   // waves per block, two per SIMD (a power of two dividing M / 16)
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s);
 
