@@ -68,38 +68,17 @@ X* upload(bs_ctx* c, const std::string& name, const std::vector<X>& v, int& rc) 
   return d;
 }
 
-// Twiddle words of the eta synthesis x(t) = sum_q a_q (Re G_q cos(2 pi q t / M) - Im G_q sin(2 pi q t / M)):
-// entry m holds (cos | -sin << 16) of the bf16 hi parts and, second, of the lo parts of
-// e^{2 pi i m / M} (hi = rne(x), lo = rne(x - hi)).  Cached per M.
-uint16_t host_bf16(float x) {
-  uint32_t u;
-  std::memcpy(&u, &x, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite values)
-  return (uint16_t)(u >> 16);
-}
-float host_bf16_float(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float x;
-  std::memcpy(&x, &u, 4);
-  return x;
-}
+// Twiddle table of the eta synthesis x(t) = sum_q a_q (Re G_q cos(2 pi q t / M) - Im G_q sin(2 pi q t / M)):
+// entry m holds (cos, sin) of 2 pi m / M in FP32.  Cached per M.
 const void* ctx_dft_twiddle(bs_ctx* c, int M) {
   auto it = c->dftw.find(M);
   if (it != c->dftw.end()) return it->second;
-  std::vector<uint32_t> h(2 * (size_t)M);
+  std::vector<float> h(2 * (size_t)M);
   const long double tp = 2.0L * 3.14159265358979323846264338327950288L;
   for (int m = 0; m < M; ++m) {
     const long double ang = tp * (long double)m / (long double)M;
-    const float v[2] = {(float)cosl(ang), (float)-sinl(ang)};
-    uint32_t hi = 0, lo = 0;
-    for (int e = 0; e < 2; ++e) {
-      const uint16_t vh = host_bf16(v[e]);
-      const uint16_t vl = host_bf16(v[e] - host_bf16_float(vh));
-      hi |= (uint32_t)vh << (16 * e);
-      lo |= (uint32_t)vl << (16 * e);
-    }
-    h[2 * m] = hi;
-    h[2 * m + 1] = lo;
+    h[2 * m] = (float)cosl(ang);
+    h[2 * m + 1] = (float)sinl(ang);
   }
   void* d = nullptr;
   if (hipMalloc(&d, h.size() * 4) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
@@ -407,8 +386,10 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     std::vector<int> Sj, kb{0};
     int Smax = 0;
     for (int h : e.pd.hj) { Sj.push_back((h + 16) / 16); kb.push_back(kb.back() + Sj.back()); Smax = std::max(Smax, Sj.back()); }
-    // fragment stage (+ one zero fragment) and four waves of field rows (+ one zero row each)
-    const size_t dlds = (size_t)(2 * kb.back() + 1) * 1024 + (size_t)M * 8 + (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
+    // fragment stage (+ a zero hi / lo pair), twiddles, synthesis schedule and every wave's field
+    // rows (+ one zero row each)
+    const size_t dlds = (size_t)(2 * kb.back() + 2) * 1024 + (size_t)M * 8 + (size_t)DFT_MAX_STEPS * DFT_SCHED * 4 +
+                        (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
             dlds <= 160 * 1024 && (e.pd.NLu == 16 || e.pd.NLu == 8) && (M / 16) % DFT_WAVES == 0 &&
             !getenv("BS_3D_FFT");

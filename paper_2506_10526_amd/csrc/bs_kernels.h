@@ -204,13 +204,14 @@ struct Dft3Args {
   int kb[DFT_MAX_FIELDS + 1];               // prefix of Sj
   int nbu;                                  // fields (<= DFT_MAX_FIELDS)
   int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
-  const void* W;               // [M] uint2 twiddle words
+  const void* W;               // [M] float2 (cos, sin) of 2 pi m / M
   const int* pairs; int npairs;
   int ngroups;                 // line groups n * n / 16
   int groups_per_block;
   int flush_vox;               // voxels per wave between FP64 flushes (4096: 128 FP32 MFMA accumulations)
   double* partial;             // [gridDim.x * DFT_WAVES][112][32]: one slot per wave
 };
+constexpr int DFT_SCHED = 28;  // schedule row: DFT_MAX_FIELDS fragment indices, chunk mask, padding to 16 bytes
 constexpr int DFT_WAVES = 8;   // waves per block, two per SIMD (a power of two dividing M / 16)
 void launch_dft3(const Dft3Args& a, int nblocks, size_t lds, hipStream_t s);
 

@@ -20,6 +20,12 @@ __device__ __forceinline__ int sidx(int i, int n) { return i < (n + 1) / 2 ? i :
 __device__ __forceinline__ uint32_t dft_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float dft_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
 __device__ __forceinline__ int wrap(int q, int n) { return q < 0 ? q + n : q; }
+// two floats as packed bf16 (round to nearest even): x in the low half, y in the high half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t dft_pk(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x, y}, bf16x2_t));
+}
 
 // --------------------------------------------------------------- delay transform
 // Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) e^{-2 pi i eta nu / nc}, with the v = 0 column
@@ -597,10 +603,26 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   const int nbu = a.nbu, nfr = 2 * a.kb[nbu];
   const int M = a.M;
   v4u_t* stage = (v4u_t*)smem_raw;                                      // [nfr + 1][64], last = zeros
-  uint2* tw = (uint2*)(stage + (size_t)(nfr + 1) * 64);                 // [M] twiddle words
-  float* sF = (float*)(tw + M) + (size_t)wave * ROWS * DFT_LDQ;         // this wave's rows
+  float2* twf = (float2*)(stage + (size_t)(nfr + 2) * 64);              // [M] (cos, sin) of 2 pi m / M
+  // synthesis schedule: sched[s][j] = hi fragment of field j at step s (lo follows it), or the zero
+  // pair nfr, nfr + 1 once the field has no modes left; sched[s][DFT_MAX_FIELDS] = bit c set when
+  // fields 4c .. 4c + 3 still have modes at step s
+  int* sched = (int*)(twf + M);
+  float* sF = (float*)(sched + DFT_MAX_STEPS * DFT_SCHED) + (size_t)wave * ROWS * DFT_LDQ;   // this wave's rows
   stage[(size_t)nfr * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
-  for (int e = tid; e < M; e += DFT_WAVES * 64) tw[e] = ((const uint2*)a.W)[e];
+  stage[(size_t)(nfr + 1) * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
+  for (int e = tid; e < M; e += DFT_WAVES * 64) twf[e] = ((const float2*)a.W)[e];
+  for (int e = tid; e < DFT_MAX_STEPS * DFT_SCHED; e += DFT_WAVES * 64) {
+    const int st = e / DFT_SCHED, j = e - st * DFT_SCHED;
+    int v = 0;
+    if (j < DFT_MAX_FIELDS) {
+      v = j < nbu && st < a.Sj[j] ? 2 * (a.kb[j] + st) : nfr;
+    } else if (j == DFT_MAX_FIELDS) {
+      for (int f = 0; f < nbu; ++f)
+        if (st < a.Sj[f]) v |= 1 << (f >> 2);
+    }
+    sched[e] = v;
+  }
   for (int e = lane; e < DFT_LDQ; e += 64) sF[DFT_MAX_FIELDS * DFT_LDQ + e] = 0.f;
   // per-lane contraction rows: pair (a, b) of row rt * 16 + r16 and field c = ct * 16 + r16
   int oa[RTN], ob[RTN], oc[2];
@@ -662,59 +684,64 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   int since = 0;
   for (int g = g_beg; g < g_end; ++g) {
     for (int tt = wave; tt < ntt; tt += DFT_WAVES) {
-      // twiddle B-fragment of step s for this lane: words c = 0..3 are the table entries at
-      // m_c = q_c t mod M, q_c = 16 s + 4 (lane / 16) + c, t = 16 tt + lane % 16
+      // twiddle B-fragment of step s for this lane: modes q_c = 16 s + 4 (lane / 16) + c (c = 0..3) at
+      // t = 16 tt + lane % 16, i.e. e^{2 pi i q_c t / M}; step 0 comes from the table and every later
+      // step is the previous one times e^{2 pi i 16 t / M} (FP32 rotations, at most seven)
       const int t = 16 * tt + r16;
-      const int m00 = (4 * (lane >> 4) * t) % M, st16 = (16 * t) % M;
+      float2 wv[4];
+      {
+        int m = (4 * (lane >> 4) * t) % M;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          wv[c] = twf[m];
+          m += t;
+          if (m >= M) m -= M;
+        }
+      }
+      const float2 rot = twf[(16 * t) % M];
       f32x4 dk[DFT_MAX_FIELDS];                                   // every field's 16 x 16 tile
 #pragma unroll
-      for (int c = 0; c < DFT_MAX_FIELDS / 4; ++c) {
-        if (4 * c < nbu) {
-          int f0[4], S[4], nst = 0;
+      for (int j = 0; j < DFT_MAX_FIELDS; ++j) dk[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = 4 * c + u;
-            f0[u] = j < nbu ? 2 * a.kb[j] : nfr;
-            S[u] = j < nbu ? a.Sj[j] : 0;
-            nst = max(nst, S[u]);
+      for (int s = 0; s < DFT_MAX_STEPS; ++s) {
+        const int cm = __builtin_amdgcn_readfirstlane(sched[s * DFT_SCHED + DFT_MAX_FIELDS]);
+        if (cm != 0) {
+          if (s > 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const float2 w = wv[c];
+              wv[c] = make_float2(w.x * rot.x - w.y * rot.y, w.x * rot.y + w.y * rot.x);
+            }
           }
-          f32x4 d[4];
+          // B rows (cos, -sin) per mode, split into bf16 hi and lo parts
+          uint32_t hw[4], lw[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) d[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-          int m0 = m00;
+          for (int c = 0; c < 4; ++c) {
+            const float cs = wv[c].x, sn = -wv[c].y;
+            hw[c] = dft_pk(cs, sn);
+            lw[c] = dft_pk(cs - __builtin_bit_cast(float, hw[c] << 16), sn - __builtin_bit_cast(float, hw[c] & 0xffff0000u));
+          }
+          const bf16x8 wh = __builtin_bit_cast(bf16x8, v4u_t{hw[0], hw[1], hw[2], hw[3]});
+          const bf16x8 wl = __builtin_bit_cast(bf16x8, v4u_t{lw[0], lw[1], lw[2], lw[3]});
 #pragma unroll
-          for (int s = 0; s < DFT_MAX_STEPS; ++s) {
-            if (s < nst) {
+          for (int c = 0; c < DFT_MAX_FIELDS / 4; ++c) {
+            if ((cm >> c) & 1) {
+              const int4 fo = *(const int4*)&sched[s * DFT_SCHED + 4 * c];
+              const int f[4] = {fo.x, fo.y, fo.z, fo.w};
               bf16x8 gh[4], gl[4];
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
-                const int fi = s < S[u] ? f0[u] + 2 * s : nfr;
-                const int fl = s < S[u] ? f0[u] + 2 * s + 1 : nfr;
-                gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fi * 64 + lane]);
-                gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)fl * 64 + lane]);
+                gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)f[u] * 64 + lane]);
+                gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)(f[u] + 1) * 64 + lane]);
               }
-              uint2 w4[4];
-              int m = m0;
 #pragma unroll
-              for (int cq = 0; cq < 4; ++cq) {
-                w4[cq] = tw[m];
-                m += t;
-                if (m >= M) m -= M;
-              }
-              m0 += st16;
-              if (m0 >= M) m0 -= M;
-              const bf16x8 wh = __builtin_bit_cast(bf16x8, v4u_t{w4[0].x, w4[1].x, w4[2].x, w4[3].x});
-              const bf16x8 wl = __builtin_bit_cast(bf16x8, v4u_t{w4[0].y, w4[1].y, w4[2].y, w4[3].y});
+              for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh, dk[4 * c + u], 0, 0, 0);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh, d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl, dk[4 * c + u], 0, 0, 0);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl, d[u], 0, 0, 0);
-#pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh, d[u], 0, 0, 0);
+              for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh, dk[4 * c + u], 0, 0, 0);
             }
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) dk[4 * c + u] = d[u];
         }
       }
       if (tt + DFT_WAVES >= ntt) {
