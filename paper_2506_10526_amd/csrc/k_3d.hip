@@ -23,6 +23,7 @@ __device__ __forceinline__ int wrap(int q, int n) { return q < 0 ? q + n : q; }
 // two floats as packed bf16 (round to nearest even): x in the low half, y in the high half
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t dft_pk(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x, y}, bf16x2_t));
 }
@@ -226,17 +227,18 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int C3_RT = 7, C3_CT = 2, C3_SLAB = 128, C3_LDS = C3_SLAB + 4;
 
-__device__ __forceinline__ uint16_t bfbits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
-__device__ __forceinline__ float bffloat(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
+// hi = rne_bf16(v), lo = rne_bf16(v - hi) for eight floats, two conversions per instruction
 __device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
+  uint32_t hw[4], lw[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    uint16_t hb = bfbits(v[q]);
-    uint16_t lb = bfbits(v[q] - bffloat(hb));
-    h[q] = __builtin_bit_cast(__bf16, hb);
-    l[q] = __builtin_bit_cast(__bf16, lb);
+  for (int q = 0; q < 4; ++q) {
+    hw[q] = dft_pk(v[2 * q], v[2 * q + 1]);
+    const float h0 = __builtin_bit_cast(float, hw[q] << 16), h1 = __builtin_bit_cast(float, hw[q] & 0xffff0000u);
+    lw[q] = dft_pk(v[2 * q] - h0, v[2 * q + 1] - h1);
   }
+  h = __builtin_bit_cast(bf16x8, v4u_t{hw[0], hw[1], hw[2], hw[3]});
+  l = __builtin_bit_cast(bf16x8, v4u_t{lw[0], lw[1], lw[2], lw[3]});
 }
 
 template <int MODE>
@@ -526,7 +528,6 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // the next group's fragments is issued once every wave has finished its last synthesis of the
 // current group and lands while that tile is contracted.  Each wave adds its FP32 sums into its
 // own FP64 slot of `partial` every a.flush_vox voxels.
-typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Contraction of 64 voxels held in rows sF[j * DFT_LDQ + v] (v < 64) into acc: RTN pair row tiles
