@@ -134,6 +134,12 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 __device__ __forceinline__ float bf16_float(uint16_t b) {
   return __builtin_bit_cast(float, (uint32_t)b << 16);
 }
+// two floats as packed bf16 (round to nearest even), x in the low half: one conversion instruction
+typedef __bf16 bf16x2_m __attribute__((ext_vector_type(2)));
+typedef float f32x2_m __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pk(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_m{x, y}, bf16x2_m));
+}
 
 __global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ F, uint16_t* __restrict__ hi,
                                                       uint16_t* __restrict__ lo, long long n) {
@@ -455,15 +461,9 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
     const float4 x = p1[g], y = p2[g];
     const float v0 = u ? x.z * y.z : x.x * y.x;
     const float v1 = u ? x.w * y.w : x.y * y.y;
-    uint32_t hp = 0, lp = 0;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const float vv = rok ? (e ? v1 : v0) : 0.f;
-      const uint32_t hb = bf16_bits(vv);
-      const uint32_t lb = bf16_bits(vv - bf16_float((uint16_t)hb));
-      hp |= hb << (16 * e);
-      lp |= lb << (16 * e);
-    }
+    const float w0 = rok ? v0 : 0.f, w1 = rok ? v1 : 0.f;
+    const uint32_t hp = bf16_pk(w0, w1);
+    const uint32_t lp = bf16_pk(w0 - __builtin_bit_cast(float, hp << 16), w1 - __builtin_bit_cast(float, hp & 0xffff0000u));
     hw[g >> 1][(g & 1) * 2 + (u >> 1)] = hp;
     lw[g >> 1][(g & 1) * 2 + (u >> 1)] = lp;
   };
