@@ -65,6 +65,15 @@ FftPlan make_fft_plan(int L) {
   return p;
 }
 
+bool fft_ip_fits(const FftPlan& p, int nl, int threads, int bmax) {
+  for (int s = 0; s < p.nr; ++s) {
+    const int R = p.rad[s];
+    const int bm = R == 8 ? std::max(1, bmax / 2) : bmax;
+    if ((long long)nl * (p.L / R) > (long long)bm * threads) return false;
+  }
+  return true;
+}
+
 const void* ctx_twiddle(bs_ctx* c, int L, bool fp64) {
   auto& mp = fp64 ? c->tw64 : c->tw32;
   auto it = mp.find(L);

@@ -129,11 +129,15 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   const size_t cz = fd.fp64 ? 16 : 8;
   Shell3Geom g = fd.g;
   g.uvm = w ? w->uv_mask : nullptr;
+  // the delay, v and u passes transform in place (one LDS buffer, twice the resident blocks)
+  // whenever their FFT plans fit; BS_3D_FFT_TWO_BUFFERS (tests) keeps the two-buffer form
+  const bool two = getenv("BS_3D_FFT_TWO_BUFFERS") != nullptr;
   if (!fd.indicator) {
     Delay3Args d{};
     d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = fd.D; d.tw = fd.tw_nc;
     d.plan = make_fft_plan(nc); d.NL = p.NLd;
-    size_t lds = 2 * (size_t)p.NLd * (nc + 1) * cz;
+    d.ip = two ? 0 : fft_ip_fits(d.plan, p.NLd, 256, 2) ? 2 : fft_ip_fits(d.plan, p.NLd, 256, 4) ? 4 : 0;
+    size_t lds = (d.ip ? 1 : 2) * (size_t)p.NLd * (nc + 1) * cz;
     if (fd.fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
     LAUNCHCHK(c, "delay transform");
   }
@@ -142,14 +146,16 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   // v pass
   a.work = fd.d_wv; a.off_in = nullptr; a.off_out = fd.d_offT; a.in = fd.D; a.out = fd.Tm; a.tw = fd.tw_n;
   a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = fd.indicator ? 1 : 0;
-  launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, 2 * (size_t)p.NLv * (n + 1) * cz);
+  a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLv, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLv, 256, 4) ? 4 : 0;
+  launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, (a.ip ? 1 : 2) * (size_t)p.NLv * (n + 1) * cz);
   LAUNCHCHK(c, "v pass");
   // u pass
   a.work = fd.d_wu; a.off_in = fd.d_offT; a.off_out = fd.d_offG; a.in = fd.Tm; a.out = fd.Gm; a.NL = p.NLu;
   a.gs = fd.Gs; a.off_gs = fd.d_offGs; a.scale = fd.gscale;
-  launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, 2 * (size_t)p.NLu * (n + 1) * cz);
+  a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLu, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLu, 256, 4) ? 4 : 0;
+  launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, (a.ip ? 1 : 2) * (size_t)p.NLu * (n + 1) * cz);
   LAUNCHCHK(c, "u pass");
-  a.gs = nullptr; a.off_gs = nullptr;
+  a.gs = nullptr; a.off_gs = nullptr; a.ip = 0;
   if (!F) return BS_OK;
   // eta pass (C2R), output length nc
   const int M = nc;

@@ -55,6 +55,9 @@ int ctx_fail(bs_ctx* c, int code, const std::string& msg);
 void* ctx_ws(bs_ctx* c, const char* name, size_t bytes);       // grow-only; NULL on failure
 const void* ctx_twiddle(bs_ctx* c, int L, bool fp64);          // NULL on failure
 FftPlan make_fft_plan(int L);
+// true when every pass of `p` over nl lines fits the in-place LDS FFT with `threads` threads and
+// at most bmax butterflies per thread (bmax / 2 in radix-8 passes)
+bool fft_ip_fits(const FftPlan& p, int nl, int threads, int bmax);
 bool fft_len_ok(int L);
 struct MabsFieldArgs;
 int ring_fields_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, bool fp64, bool count_mode,

@@ -114,6 +114,7 @@ struct Delay3Args {
   const void* tw;           // exp(-2 pi i m / nc)
   FftPlan plan;             // length nc
   int NL;                   // lines (consecutive qv) per block
+  int ip;                   // 2 or 4: in-place FFT with that many butterflies per thread (one LDS buffer); 0: two buffers
 };
 
 // One work item = (shell block j, eta, start index) for the v and u passes, and
@@ -134,6 +135,7 @@ struct Pass3Args {
   const void* tw;              // exp(-2 pi i m / L) for the pass length L
   FftPlan plan;
   int NL;
+  int ip;                      // v / u pass: 2 or 4 = in-place FFT with that many butterflies per thread; 0 = two buffers
   int indicator;               // v pass: 1 = unit indicator of shell and support, 0 = data
   int M;                       // eta pass: output length along eta
   double scale;                // eta pass: overall 1 / (M n^2); u pass with gs: the same, folded into gs

@@ -155,6 +155,73 @@ __device__ __forceinline__ void stockham_any(int R, const Cx<T>* src, Cx<T>* dst
   else stockham_pass<SIGN, 2, T, PIN, POUT>(src, dst, L, Ns, nl, ld, tw, tws);
 }
 
+// In-place Stockham pass: every thread first gathers, twiddles and transforms all of its
+// butterflies (at most BM of them, held in registers), then, after a barrier, writes them back
+// over the same buffer.  Needs nl * L / R <= BM * blockDim.x.
+template <int BMAX, int R>
+constexpr int fft_ip_bm() { return R == 8 ? (BMAX > 1 ? BMAX / 2 : 1) : BMAX; }   // radix 8: half the butterflies
+template <int SIGN, int R, int BM, typename T>
+__device__ __forceinline__ void stockham_pass_ip(Cx<T>* buf, int L, int Ns, int nl, int ld,
+                                                 const Cx<T>* __restrict__ tw, int tws) {
+  const int nbf = L / R;
+  const int total = nl * nbf;
+  const int tstep = (L / (Ns * R)) * tws;
+  const float rnbf = 1.0f / (float)nbf, rns = 1.0f / (float)Ns;
+  Cx<T> v[BM][R];
+  int o[BM];
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    const int t = threadIdx.x + b * blockDim.x;
+    o[b] = -1;
+    if (t < total) {
+      int line, j, jq, k;
+      fdivmod(t, nbf, rnbf, line, j);
+      fdivmod(j, Ns, rns, jq, k);
+      const Cx<T>* in = buf + (size_t)line * ld;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = in[j + r * nbf];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw[k * r * tstep];
+          if (SIGN > 0) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      if (R == 2) dft2<SIGN>(v[b]);
+      else if (R == 3) dft3<SIGN>(v[b]);
+      else if (R == 4) dft4<SIGN>(v[b]);
+      else dft8<SIGN>(v[b]);
+      o[b] = line * ld + jq * Ns * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    if (o[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[o[b] + r * Ns] = v[b][r];
+    }
+  }
+}
+
+// In-place transform of nl lines held in `a` (line i at a + i*ld): one buffer instead of two.
+// Every pass must satisfy nl * L / R <= fft_ip_bm<BMAX, R>() * blockDim.x (the host checks
+// this with fft_ip_fits).  Ends with a barrier.
+template <int SIGN, typename T, int BMAX>
+__device__ void lds_fft_ip(Cx<T>* a, const FftPlan& p, int nl, const Cx<T>* __restrict__ tw, int tws, int ld) {
+  int Ns = 1;
+  for (int s = 0; s < p.nr; ++s) {
+    const int R = p.rad[s];
+    if (R == 8) stockham_pass_ip<SIGN, 8, fft_ip_bm<BMAX, 8>(), T>(a, p.L, Ns, nl, ld, tw, tws);
+    else if (R == 4) stockham_pass_ip<SIGN, 4, fft_ip_bm<BMAX, 4>(), T>(a, p.L, Ns, nl, ld, tw, tws);
+    else if (R == 3) stockham_pass_ip<SIGN, 3, fft_ip_bm<BMAX, 3>(), T>(a, p.L, Ns, nl, ld, tw, tws);
+    else stockham_pass_ip<SIGN, 2, fft_ip_bm<BMAX, 2>(), T>(a, p.L, Ns, nl, ld, tw, tws);
+    __syncthreads();
+    Ns *= R;
+  }
+}
+
 // Transform nl lines held in `a` (line i at a + i*ld, ld >= L; ld = L when omitted).
 // `b` is scratch of the same size.  Returns the buffer holding the result (a or b).
 // Ends with a barrier.  PAD: intermediate passes use the padded layout fft_pad() (input and

@@ -20,6 +20,13 @@ __device__ __forceinline__ int sidx(int i, int n) { return i < (n + 1) / 2 ? i :
 __device__ __forceinline__ uint32_t dft_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float dft_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
 __device__ __forceinline__ int wrap(int q, int n) { return q < 0 ? q + n : q; }
+// Workgroups are dispatched to the eight XCDs in turn (id mod 8).  This maps the dispatch id to a
+// logical block so that every XCD runs one contiguous range of logical blocks: neighbours that
+// share cache lines then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int id, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = id & 7, j = id >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
 // two floats as packed bf16 (round to nearest even): x in the low half, y in the high half
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -31,15 +38,19 @@ __device__ __forceinline__ uint32_t dft_pk(float x, float y) {
 // --------------------------------------------------------------- delay transform
 // Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) e^{-2 pi i eta nu / nc}, with the v = 0 column
 // symmetrised per channel.  Block: NL consecutive qv of one qu row, all channels.
-template <typename T>
+template <typename T, int IP>   // IP: in-place FFT butterflies per thread (2 or 4), 0 = two buffers
 __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Shell3Geom& g = a.g;
   const int nc = g.nc, n = g.n, nh = g.nh;
-  const int ub = blockIdx.y;
+  // logical block (ub, v-block), v-blocks of one uv row consecutive on one XCD: the NL-column
+  // reads of neighbouring blocks fill the same cache lines
+  const int nvblk = (g.nvb + a.NL - 1) / a.NL;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int ub = lb / nvblk;
   const int qu = ub - g.vmax;
   const int iu = wrap(qu, n), iun = wrap(-qu, n);
-  const int v0 = blockIdx.x * a.NL;
+  const int v0 = (lb - ub * nvblk) * a.NL;
   const int nl = min(a.NL, g.nvb - v0);
   const int ld = nc + 1;
   Cx<T>* A = (Cx<T>*)smem_raw;
@@ -58,7 +69,9 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
     A[(size_t)l * ld + nu] = x;
   }
   __syncthreads();
-  Cx<T>* r = lds_fft<-1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  Cx<T>* r = A;
+  if constexpr (IP > 0) lds_fft_ip<-1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  else r = lds_fft<-1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
   Cx<T>* out = (Cx<T>*)a.out;
   const int ne = 2 * g.H + 1;
   for (int e = threadIdx.x; e < ne * nl; e += blockDim.x) {
@@ -86,11 +99,12 @@ __device__ __forceinline__ Cx<T> shell_value(const Pass3Args& a, int shell, int 
   return cconj(D[((size_t)(g.H - eta) * g.nub + (-qu + g.vmax)) * g.nvb + (-qv)]);
 }
 
-template <typename T>
+template <typename T, int IP>
 __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Shell3Geom& g = a.g;
-  const Work3 w = a.work[blockIdx.x];
+  // consecutive work items (neighbouring qu blocks, whose output rows share cache lines) on one XCD
+  const Work3 w = a.work[xcd_block(blockIdx.x, gridDim.x)];
   const int shell = a.shell_of_block[w.j];
   const int n = g.n, ld = n + 1;
   const int nl = min(a.NL, g.nub - w.start);
@@ -102,7 +116,9 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
     A[(size_t)l * ld + i] = shell_value<T>(a, shell, w.eta, qu, sidx(i, n));
   }
   __syncthreads();
-  Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  Cx<T>* r = A;
+  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
   // T_j[x_v][eta][qu]: consecutive threads write consecutive qu rows of one x_v
   const int hp1 = a.hj[w.j] + 1;
   Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
@@ -115,7 +131,7 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
 // --------------------------------------------------------------- u pass
 // Work item (j, x_v = w.start, eta0 = w.eta): the delay planes eta0.. of one x_v column.
 // Output G_j[line = x_u n + x_v][eta] keeps each line's delay spectrum contiguous.
-template <typename T>
+template <typename T, int IP>
 __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const Shell3Geom& g = a.g;
@@ -135,7 +151,9 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
     A[(size_t)l * ld + i] = x;
   }
   __syncthreads();
-  Cx<T>* r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  Cx<T>* r = A;
+  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
   if constexpr (std::is_same<T, float>::value) {
     if (a.gs) {
       // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column:
@@ -811,23 +829,41 @@ static void set_lds(const void* f, size_t lds) {
   (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-void launch_delay3_f32(const Delay3Args& a, hipStream_t s, size_t lds) {
-  set_lds<float>((const void*)k3_delay<float>, lds);
-  hipLaunchKernelGGL(k3_delay<float>, dim3((a.g.nvb + a.NL - 1) / a.NL, a.g.nub), dim3(256), lds, s, a);
+template <typename T, int IP>
+static void launch_delay3_t(const Delay3Args& a, hipStream_t s, size_t lds) {
+  set_lds<T>((const void*)k3_delay<T, IP>, lds);
+  hipLaunchKernelGGL((k3_delay<T, IP>), dim3((a.g.nvb + a.NL - 1) / a.NL * a.g.nub), dim3(256), lds, s, a);
 }
-void launch_delay3_f64(const Delay3Args& a, hipStream_t s, size_t lds) {
-  set_lds<double>((const void*)k3_delay<double>, lds);
-  hipLaunchKernelGGL(k3_delay<double>, dim3((a.g.nvb + a.NL - 1) / a.NL, a.g.nub), dim3(256), lds, s, a);
+template <typename T>
+static void launch_delay3_ip(const Delay3Args& a, hipStream_t s, size_t lds) {
+  if (a.ip == 2) launch_delay3_t<T, 2>(a, s, lds);
+  else if (a.ip == 4) launch_delay3_t<T, 4>(a, s, lds);
+  else launch_delay3_t<T, 0>(a, s, lds);
+}
+void launch_delay3_f32(const Delay3Args& a, hipStream_t s, size_t lds) { launch_delay3_ip<float>(a, s, lds); }
+void launch_delay3_f64(const Delay3Args& a, hipStream_t s, size_t lds) { launch_delay3_ip<double>(a, s, lds); }
+template <typename T, int IP>
+static void launch_pass3_t(bool upass, const Pass3Args& a, int nwork, hipStream_t s, size_t lds) {
+  const void* f = upass ? (const void*)k3_upass<T, IP> : (const void*)k3_vpass<T, IP>;
+  set_lds<T>(f, lds);
+  if (upass) hipLaunchKernelGGL((k3_upass<T, IP>), dim3(nwork), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k3_vpass<T, IP>), dim3(nwork), dim3(256), lds, s, a);
+}
+template <typename T>
+static void launch_pass3_ip(bool upass, const Pass3Args& a, int nwork, hipStream_t s, size_t lds) {
+  if (a.ip == 2) launch_pass3_t<T, 2>(upass, a, nwork, s, lds);
+  else if (a.ip == 4) launch_pass3_t<T, 4>(upass, a, nwork, s, lds);
+  else launch_pass3_t<T, 0>(upass, a, nwork, s, lds);
 }
 void launch_vpass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds) {
   if (nwork <= 0) return;
-  if (fp64) { set_lds<double>((const void*)k3_vpass<double>, lds); hipLaunchKernelGGL(k3_vpass<double>, dim3(nwork), dim3(256), lds, s, a); }
-  else { set_lds<float>((const void*)k3_vpass<float>, lds); hipLaunchKernelGGL(k3_vpass<float>, dim3(nwork), dim3(256), lds, s, a); }
+  if (fp64) launch_pass3_ip<double>(false, a, nwork, s, lds);
+  else launch_pass3_ip<float>(false, a, nwork, s, lds);
 }
 void launch_upass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds) {
   if (nwork <= 0) return;
-  if (fp64) { set_lds<double>((const void*)k3_upass<double>, lds); hipLaunchKernelGGL(k3_upass<double>, dim3(nwork), dim3(256), lds, s, a); }
-  else { set_lds<float>((const void*)k3_upass<float>, lds); hipLaunchKernelGGL(k3_upass<float>, dim3(nwork), dim3(256), lds, s, a); }
+  if (fp64) launch_pass3_ip<double>(true, a, nwork, s, lds);
+  else launch_pass3_ip<float>(true, a, nwork, s, lds);
 }
 void launch_etapass3(const Pass3Args& a, int nwork, bool fp64, hipStream_t s, size_t lds) {
   if (nwork <= 0) return;
