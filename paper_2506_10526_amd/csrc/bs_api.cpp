@@ -38,6 +38,8 @@ void* ctx_ws(bs_ctx* c, const char* name, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return b.p;
   if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  b.mirror.clear();
+  ++c->ws_gen;
   if (getenv("BS_FORCE_ENOMEM")) return nullptr;
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }

@@ -56,13 +56,24 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
 
 namespace {
 
+// Host table -> named device workspace.  A table equal to what the workspace already holds is not
+// copied again: a copy from pageable memory would hold the host until the stream reaches it, so
+// repeated calls could no longer be queued ahead of the running kernels.
 template <typename X>
 X* upload(bs_ctx* c, const std::string& name, const std::vector<X>& v, int& rc) {
   X* d = (X*)ctx_ws(c, name.c_str(), std::max<size_t>(v.size() * sizeof(X), 16));
   if (!d) { rc = ctx_fail(c, BS_ENOMEM, "workspace " + name); return nullptr; }
-  if (!v.empty() && hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-    rc = ctx_fail(c, BS_EHIP, "upload " + name);
-    return nullptr;
+  DevBuf& wb = c->ws[name];
+  const size_t nb = v.size() * sizeof(X);
+  const unsigned char* hv = (const unsigned char*)v.data();
+  if (nb > 0 && !(wb.mirror.size() == nb && std::memcmp(wb.mirror.data(), hv, nb) == 0)) {
+    if (hipMemcpyAsync(d, v.data(), nb, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      wb.mirror.clear();
+      rc = ctx_fail(c, BS_EHIP, "upload " + name);
+      return nullptr;
+    }
+    wb.mirror.assign(hv, hv + nb);
+    ++c->ws_gen;
   }
   rc = BS_OK;
   return d;
@@ -486,9 +497,31 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   if (!vis || !B || !N_tri) return ctx_fail(c, BS_EINVAL, "vis, B and N_tri must be non-NULL");
   if (precision < 0 || precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
   if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
-  Est3 e;
-  rc = est3_prepare(c, b, w, precision, "c3", e);
-  if (rc) return rc;
+  // Unweighted calls reuse the last prepared estimate (pair cover, work lists, uploaded tables) as
+  // long as the bins, precision and path switches are the same and no workspace has changed since.
+  // With weights the mask and channel weights are read back on every call.
+  const bool cacheable = !w || (!w->ng && !w->uv_mask && !w->chan_w);
+  std::string key;
+  if (cacheable) {
+    key = std::to_string((uintptr_t)b) + ":" + std::to_string((uintptr_t)b->d_lut) + ":" + std::to_string(b->P.hash) +
+          ":" + std::to_string(precision);
+    for (const char* k : {"BS_3D_FULLGRID", "BS_3D_UNFUSED", "BS_3D_ALLFFT", "BS_3D_FFT", "BS_3D_DFT_BLOCKS",
+                          "BS_3D_DFT_FLUSH", "BS_FORCE_ENOMEM"}) {
+      const char* v = getenv(k);
+      key += std::string(":") + (v ? v : "-");
+    }
+  }
+  std::shared_ptr<Est3> held;
+  if (cacheable && c->est3 && c->est3_key == key && c->est3_gen == c->ws_gen) {
+    held = c->est3;
+  } else {
+    held = std::make_shared<Est3>();
+    rc = est3_prepare(c, b, w, precision, "c3", *held);
+    if (rc) return rc;
+    if (cacheable) { c->est3 = held; c->est3_key = key; c->est3_gen = c->ws_gen; }
+    else c->est3.reset();
+  }
+  Est3& e = *held;
   if (e.ntri == 0) return BS_OK;
   c->last_count_dev = e.count_dev;
   rc = est3_enqueue(c, b, vis, w, e, norm, B, N_tri, N_eff);

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,7 @@
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  std::vector<unsigned char> mirror;   // bytes last uploaded into p from the host (tables only)
 };
 
 struct CountCache {
@@ -25,6 +27,8 @@ struct CountCache {
 
 // Largest distance of an FP64 triangle count from an integer that is accepted before rounding.
 constexpr double kCountTol = 0.25;
+
+struct Est3;
 
 struct bs_ctx {
   int device = 0;
@@ -42,6 +46,11 @@ struct bs_ctx {
   int last_grid_M = 0;   // delay-axis grid of the last 3D contraction
   double last_flops_vox = 0.0, last_vox = 0.0;   // algorithmic MFMA flops per voxel, voxels (MFMA synthesis path)
   std::map<std::string, int> tuned;       // autotuned launch parameters, by shape key
+  uint64_t ws_gen = 0;                    // bumped whenever a workspace is reallocated or re-uploaded
+  // last prepared unweighted 3D estimate, reused while its key and ws_gen still match
+  std::shared_ptr<Est3> est3;
+  std::string est3_key;
+  uint64_t est3_gen = 0;
 };
 
 struct bs_bins {
