@@ -548,16 +548,25 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // own FP64 slot of `partial` every a.flush_vox voxels.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Contraction of 64 voxels held in rows sF[j * DFT_LDQ + v] (v < 64) into acc: RTN pair row tiles
-// (row offsets oa / ob per lane, zero row for padding), two field column tiles (offsets oc).  Steps
-// (32 voxels, pair row tile) are issued as: LDS reads of the next step, products and splits of this
-// step, its six MFMAs; sched_barrier keeps that order (the compiler would otherwise wait for every
-// read right before its use).
+// Contraction of one 16 x 16 synthesis tile (256 voxels, dk[j] for field j) into acc, in four
+// quarters of 64 voxels staged in rows sF[j * DFT_LDQ + v] (v < 64): RTN pair row tiles (row
+// offsets oa / ob per lane, zero row for padding) and two field column tiles (offsets oc).  Steps
+// (32 voxels, pair row tile) are issued as: LDS reads of the next step, products and splits of
+// this step, its six MFMAs; sched_barrier keeps that order (the compiler would otherwise wait for
+// every read right before its use).  The rows of the next quarter are written right after the last
+// reads of the current one: a wave's LDS operations complete in order, so the writes cannot pass
+// those reads, and the pipeline runs through all four quarters without draining.
 template <int RTN>
-__device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const int (&oa)[RTN], const int (&ob)[RTN],
-                                             const int (&oc)[2], f32x4 (&acc)[RTN][2]) {
-  const int kq = (threadIdx.x & 63) >> 4;
+__device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const f32x4 (&dk)[DFT_MAX_FIELDS], int nbu,
+                                                  const int (&oa)[RTN], const int (&ob)[RTN], const int (&oc)[2],
+                                                  f32x4 (&acc)[RTN][2]) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4;
   float4 ra[2][2], rb[2][2], rc[2][2][2];
+  auto write_q = [&](int q) {
+#pragma unroll
+    for (int j = 0; j < DFT_MAX_FIELDS; ++j)
+      if (j < nbu) sF[(size_t)j * DFT_LDQ + lane] = dk[j][q];
+  };
   auto load_ab = [&](int ks, int rt, int buf) {
     const int vb = ks * 32 + kq * 8;
     ra[buf][0] = *(const float4*)&sF[oa[rt] + vb];
@@ -573,41 +582,50 @@ __device__ __forceinline__ void dft_contract(const float* __restrict__ sF, const
       rc[buf][ct][1] = *(const float4*)&sF[oc[ct] + vb + 4];
     }
   };
+  write_q(0);
   load_c(0, 0);
   load_ab(0, 0, 0);
   bf16x8 bh[2], bl[2];
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
+  for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int rt = 0; rt < RTN; ++rt) {
-      const int i = ks * RTN + rt;
-      __builtin_amdgcn_sched_barrier(0);
-      if (rt + 1 < RTN) {
-        load_ab(ks, rt + 1, (i + 1) & 1);
-      } else if (ks + 1 < 2) {
-        load_ab(ks + 1, 0, (i + 1) & 1);
-        load_c(ks + 1, (ks + 1) & 1);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if (rt == 0) {
+    for (int ks = 0; ks < 2; ++ks) {
+      const int kk = 2 * q + ks;   // 32-voxel step of the tile (parity selects the rc buffer)
+#pragma unroll
+      for (int rt = 0; rt < RTN; ++rt) {
+        const int i = kk * RTN + rt;
+        __builtin_amdgcn_sched_barrier(0);
+        if (rt + 1 < RTN) {
+          load_ab(ks, rt + 1, (i + 1) & 1);
+        } else if (ks + 1 < 2) {
+          load_ab(ks + 1, 0, (i + 1) & 1);
+          load_c(ks + 1, (kk + 1) & 1);
+        } else if (q + 1 < 4) {
+          write_q(q + 1);
+          load_ab(0, 0, (i + 1) & 1);
+          load_c(0, (kk + 1) & 1);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (rt == 0) {
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const float4 c0 = rc[kk & 1][ct][0], c1 = rc[kk & 1][ct][1];
+            const float v[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            split8(v, bh[ct], bl[ct]);
+          }
+        }
+        const float4 a0 = ra[i & 1][0], a1 = ra[i & 1][1], b0 = rb[i & 1][0], b1 = rb[i & 1][1];
+        const float v[8] = {a0.x * b0.x, a0.y * b0.y, a0.z * b0.z, a0.w * b0.w,
+                            a1.x * b1.x, a1.y * b1.y, a1.z * b1.z, a1.w * b1.w};
+        bf16x8 ah, al;
+        split8(v, ah, al);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const float4 c0 = rc[ks & 1][ct][0], c1 = rc[ks & 1][ct][1];
-          const float v[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-          split8(v, bh[ct], bl[ct]);
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
         }
-      }
-      const float4 a0 = ra[i & 1][0], a1 = ra[i & 1][1], b0 = rb[i & 1][0], b1 = rb[i & 1][1];
-      const float v[8] = {a0.x * b0.x, a0.y * b0.y, a0.z * b0.z, a0.w * b0.w,
-                          a1.x * b1.x, a1.y * b1.y, a1.z * b1.z, a1.w * b1.w};
-      bf16x8 ah, al;
-      split8(v, ah, al);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
-        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
-        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
       }
     }
   }
@@ -768,13 +786,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int j = 0; j < DFT_MAX_FIELDS; ++j)
-          if (j < nbu) sF[(size_t)j * DFT_LDQ + lane] = dk[j][q];
-        dft_contract<RTN>(sF, oa, ob, oc, acc);
-      }
+      dft_contract_tile<RTN>(sF, dk, nbu, oa, ob, oc, acc);
       since += 256;
       if (since >= a.flush_vox) { since = 0; flush(); }
     }
