@@ -422,7 +422,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       Dft3Args& da = e.da;
       da = Dft3Args{};
       da.Gs = e.fd.Gs;
-      for (int j = 0; j < fa.nbu; ++j) { da.offGs[j] = offGs[j]; da.Sj[j] = Sj[j]; }
+      for (int j = 0; j < fa.nbu; ++j) { da.offGs[j] = offGs[j]; da.Sj[j] = Sj[j]; da.Hj[j] = e.pd.hj[j]; }
       for (int j = 0; j <= fa.nbu; ++j) da.kb[j] = kb[j];
       da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;
       da.W = ctx_dft_twiddle(c, M);

@@ -204,6 +204,7 @@ struct Dft3Args {
   long long offGs[DFT_MAX_FIELDS];          // per field (16-byte units)
   int Sj[DFT_MAX_FIELDS];                   // per field: K-steps ceil((H_j + 1) / 16)
   int kb[DFT_MAX_FIELDS + 1];               // prefix of Sj
+  int Hj[DFT_MAX_FIELDS];                   // per field: largest delay mode H_j
   int nbu;                                  // fields (<= DFT_MAX_FIELDS)
   int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
   const void* W;               // [M] float2 (cos, sin) of 2 pi m / M

@@ -157,13 +157,11 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   if constexpr (std::is_same<T, float>::value) {
     if (a.gs) {
       // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column:
-      // the lanes whose modes 16 s + 4 (lane / 16) .. +3 lie in this item's planes e0 .. e0 + NL - 1
-      // (NL = 16: all lanes; NL = 8: two of the four lane groups, or all four in a step's last item)
+      // lane group g (lanes 16 g .. 16 g + 15) holds modes 16 s + 4 g .. +3.  This item writes its
+      // planes' groups that hold at least one mode (<= H_j); groups wholly past H_j are never
+      // written (the synthesis kernel keeps them zero in LDS and does not copy them).
       const int S = (hp1 + 15) >> 4, s = e0 >> 4, nxub = n >> 4;
-      // lane groups of this item and the first one; an item that starts a step and holds all of
-      // its remaining planes also writes the zero padding of the step's other lane groups
-      const bool whole = (e0 & 15) == 0 && hp1 - e0 <= a.NL;
-      const int gpl = whole ? 4 : a.NL >> 2, g0 = whole ? 0 : (e0 & 15) >> 2;
+      const int g0 = (e0 & 15) >> 2, gpl = min(a.NL >> 2, (hp1 - e0 + 3) >> 2);
       uint4* out = (uint4*)a.gs + a.off_gs[w.j];
       const float sc = (float)a.scale;
       for (int e = threadIdx.x; e < nxub * 16 * gpl; e += blockDim.x) {
@@ -181,10 +179,8 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
             re = z.x * (dc ? sc : 2.f * sc);
             im = dc ? 0.f : z.y * (2.f * sc);
           }
-          const uint32_t rh = dft_bf16(re), ih = dft_bf16(im);
-          const uint32_t rl = dft_bf16(re - dft_f32(rh)), il = dft_bf16(im - dft_f32(ih));
-          hw[c] = rh | (ih << 16);
-          lw[c] = rl | (il << 16);
+          hw[c] = dft_pk(re, im);
+          lw[c] = dft_pk(re - __builtin_bit_cast(float, hw[c] << 16), im - __builtin_bit_cast(float, hw[c] & 0xffff0000u));
         }
         uint4* o = out + ((size_t)(xv * nxub + xub) * S + s) * 128;
         o[lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
@@ -646,8 +642,9 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   // fields 4c .. 4c + 3 still have modes at step s
   int* sched = (int*)(twf + M);
   float* sF = (float*)(sched + DFT_MAX_STEPS * DFT_SCHED) + (size_t)wave * ROWS * DFT_LDQ;   // this wave's rows
-  stage[(size_t)nfr * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
-  stage[(size_t)(nfr + 1) * 64 + lane] = v4u_t{0u, 0u, 0u, 0u};
+  // the whole stage starts at zero: lane groups past a field's last mode are never copied and
+  // stay zero, and fragments nfr, nfr + 1 are the zero pair
+  for (int e = tid; e < (nfr + 2) * 64; e += DFT_WAVES * 64) stage[e] = v4u_t{0u, 0u, 0u, 0u};
   for (int e = tid; e < M; e += DFT_WAVES * 64) twf[e] = ((const float2*)a.W)[e];
   for (int e = tid; e < DFT_MAX_STEPS * DFT_SCHED; e += DFT_WAVES * 64) {
     const int st = e / DFT_SCHED, j = e - st * DFT_SCHED;
@@ -706,15 +703,19 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   const int ntt = M >> 4;   // a multiple of 8: every wave takes ntt / DFT_WAVES tiles per group
   const int g_beg = blockIdx.x * a.groups_per_block;
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
+  // fragment s2 of field j (hi / lo of step s2 / 2): each lane copies its 16 bytes, lanes whose
+  // group holds no mode of the field (16 step + 4 (lane / 16) > H_j) copy nothing
   auto copy_group = [&](int g) {
     for (int j = 0; j < nbu; ++j) {
-      const int S = a.Sj[j], f0 = 2 * a.kb[j];
+      const int S = a.Sj[j], f0 = 2 * a.kb[j], lim = a.Hj[j] - 4 * (lane >> 4);
       const v4u_t* src = Gs + a.offGs[j] + (size_t)g * S * 128 + lane;
       for (int s2 = (wave - f0) & (DFT_WAVES - 1); s2 < 2 * S; s2 += DFT_WAVES)
-        __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
-                                         16, 0, 0);
+        if (16 * (s2 >> 1) <= lim)
+          __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
+                                           16, 0, 0);
     }
   };
+  __syncthreads();   // the zeroed stage is complete before any copy lands in it
   if (g_beg < g_end) copy_group(g_beg);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
