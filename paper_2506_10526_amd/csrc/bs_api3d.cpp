@@ -461,7 +461,7 @@ int est3_enqueue(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights*
     if (e.dft) {
       launch_dft3(e.da, e.dblocks, e.dlds, c->stream);
       LAUNCHCHK(c, "eta synthesis and contraction");
-      nparts = e.dblocks * DFT_WAVES;   // one partial slot per wave
+      nparts = e.dblocks;   // one summed slot per block (the first of its waves' slots)
     } else {
       launch_fused3(e.fa, e.precision == BS_FP32 ? 1 : 2, e.fblocks, e.lds, c->stream);
       LAUNCHCHK(c, "fused contraction");
@@ -480,6 +480,7 @@ int est3_enqueue(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights*
   if (c->timing) (void)hipEventRecord(c->ev[3], c->stream);
   Fin3Args f{};
   f.partial = e.partial; f.nparts = nparts; f.tri_pair = e.d_tp; f.tri_col = e.d_tc; f.ntri = e.ntri;
+  if (e.fused && e.dft) { f.pstride = DFT_WAVES; f.nent = (e.npairs + 15) / 16 * 16 * 32; }
   f.T3D = e.d_counts; f.rho3 = e.rho3; f.nvox = (double)e.nvox; f.norm = norm; f.sfac = e.sfac;
   f.B = B; f.N = N_tri; f.Neff = N_eff;
   launch_fin3(f, e.reduced, c->stream);

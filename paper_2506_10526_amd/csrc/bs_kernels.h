@@ -156,7 +156,9 @@ struct Con3Args {
 };
 
 struct Fin3Args {
-  const double* partial; int nparts;  // reduce over parts
+  const double* partial; int nparts;  // reduce over parts: part p at partial + p * pstride * 112 * 32
+  int pstride;                        // slots between parts (0 means 1)
+  int nent;                           // entries of each [112][32] part that are summed (0 means all)
   const int* tri_pair; const int* tri_col;  // per triangle
   int ntri;
   const int64_t* T3D;          // counts (NULL when computing counts)

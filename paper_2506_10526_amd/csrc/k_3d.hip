@@ -795,25 +795,39 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
     __syncthreads();
   }
   flush();
+  // sum the block's wave slots into the first one, in wave order (rows past the pair tiles stay
+  // zero); the reduction over blocks then reads one slot per block
+  __syncthreads();
+  double* bslot = a.partial + (size_t)blockIdx.x * DFT_WAVES * 112 * 32;
+  for (int e = tid; e < RTN * 16 * 32; e += DFT_WAVES * 64) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < DFT_WAVES; ++w) v += bslot[(size_t)w * 112 * 32 + e];
+    bslot[e] = v;
+  }
 }
 
 // Sum the per-block partial sums: out[e] = sum_p partial[p][e] (fixed order, coalesced).
 // Two fixed-order stages: first every group of RGROUP consecutive parts is summed into the group's
 // first slot (in place), then the group sums are added in group order.
+// Parts are pstride slots apart; only the first nent entries of each are summed (the rows of the
+// pair tiles in use), the rest of `out` is cleared.
 constexpr int RGROUP = 32;
-__global__ void k3_reduce_groups(double* __restrict__ partial, int nparts) {
+__global__ void k3_reduce_groups(double* __restrict__ partial, int nparts, int pstride, int nent) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 112 * 32) return;
+  if (e >= nent) return;
   const int p0 = blockIdx.y * RGROUP, p1 = min(nparts, p0 + RGROUP);
   double s = 0.0;
-  for (int p = p0; p < p1; ++p) s += partial[(size_t)p * 112 * 32 + e];
-  partial[(size_t)p0 * 112 * 32 + e] = s;
+  for (int p = p0; p < p1; ++p) s += partial[(size_t)p * pstride * 112 * 32 + e];
+  partial[(size_t)p0 * pstride * 112 * 32 + e] = s;
 }
-__global__ void k3_reduce_parts(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
+__global__ void k3_reduce_parts(const double* __restrict__ partial, int nparts, int pstride, int nent,
+                                double* __restrict__ out) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 112 * 32) return;
   double s = 0.0;
-  for (int p = 0; p < nparts; p += RGROUP) s += partial[(size_t)p * 112 * 32 + e];
+  if (e < nent)
+    for (int p = 0; p < nparts; p += RGROUP) s += partial[(size_t)p * pstride * 112 * 32 + e];
   out[e] = s;
 }
 
@@ -890,8 +904,11 @@ void launch_contract3(const Con3Args& a, int mode, int nblocks, hipStream_t s) {
 }
 void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s) {
   const int groups = (a.nparts + RGROUP - 1) / RGROUP;
-  hipLaunchKernelGGL(k3_reduce_groups, dim3((112 * 32 + 255) / 256, groups), dim3(256), 0, s, (double*)a.partial, a.nparts);
-  hipLaunchKernelGGL(k3_reduce_parts, dim3((112 * 32 + 255) / 256), dim3(256), 0, s, a.partial, a.nparts, reduced);
+  const int ps = a.pstride > 0 ? a.pstride : 1, ne = a.nent > 0 ? a.nent : 112 * 32;
+  hipLaunchKernelGGL(k3_reduce_groups, dim3((ne + 255) / 256, groups), dim3(256), 0, s, (double*)a.partial, a.nparts,
+                     ps, ne);
+  hipLaunchKernelGGL(k3_reduce_parts, dim3((112 * 32 + 255) / 256), dim3(256), 0, s, a.partial, a.nparts, ps, ne,
+                     reduced);
   Fin3Args b = a;
   b.partial = reduced;
   if (a.ntri > 0) hipLaunchKernelGGL(k3_fin, dim3((a.ntri + 127) / 128), dim3(128), 0, s, b);
