@@ -56,17 +56,38 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
   const Cx<T>* vis = (const Cx<T>*)a.vis;
-  for (int e = threadIdx.x; e < nl * nc; e += blockDim.x) {
-    int nu = e / nl, l = e - nu * nl, v = v0 + l;
-    T cw = a.chw ? T(a.chw[nu]) : T(1);
-    T m = g.uvm ? T(g.uvm[(size_t)iu * nh + v]) : T(1);
-    Cx<T> x = cscale(vis[((size_t)nu * n + iu) * nh + v], cw * m);
-    if (v == 0) {
-      T mn = g.uvm ? T(g.uvm[(size_t)iun * nh]) : T(1);
-      Cx<T> y = cscale(vis[((size_t)nu * n + iun) * nh], cw * mn);
-      x = cscale(cadd(x, cconj(y)), T(0.5));
+  // eight elements per thread in flight before their LDS stores
+  const float rnl = 1.0f / (float)nl;
+  for (int e0 = threadIdx.x; e0 < nl * nc; e0 += 8 * blockDim.x) {
+    Cx<T> x[8], y[8];
+    int nuu[8], lu[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * blockDim.x;
+      int nu = 0, l = 0;
+      if (e < nl * nc) fdivmod(e, nl, rnl, nu, l);
+      nuu[u] = e < nl * nc ? nu : -1;
+      lu[u] = l;
+      const int v = v0 + l;
+      x[u] = y[u] = cmk(T(0), T(0));
+      if (e < nl * nc) {
+        x[u] = vis[((size_t)nu * n + iu) * nh + v];
+        if (v == 0) y[u] = vis[((size_t)nu * n + iun) * nh];
+      }
     }
-    A[(size_t)l * ld + nu] = x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int nu = nuu[u], l = lu[u], v = v0 + l;
+      if (nu < 0) continue;
+      const T cw = a.chw ? T(a.chw[nu]) : T(1);
+      const T m = g.uvm ? T(g.uvm[(size_t)iu * nh + v]) : T(1);
+      Cx<T> xv = cscale(x[u], cw * m);
+      if (v == 0) {
+        const T mn = g.uvm ? T(g.uvm[(size_t)iun * nh]) : T(1);
+        xv = cscale(cadd(xv, cconj(cscale(y[u], cw * mn))), T(0.5));
+      }
+      A[(size_t)l * ld + nu] = xv;
+    }
   }
   __syncthreads();
   Cx<T>* r = A;
@@ -84,15 +105,23 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
 
 // --------------------------------------------------------------- v pass
 // Input value of shell j at (eta >= 0, qu, qv): data Vt or the unit indicator.
-template <typename T>
-__device__ __forceinline__ Cx<T> shell_value(const Pass3Args& a, int shell, int eta, int qu, int qv) {
+// Membership of (eta >= 0, qu, qv) in shell j (shell table and uv support), then its input value:
+// data Vt or the unit indicator.
+__device__ __forceinline__ bool shell_member(const Pass3Args& a, int shell, int eta, int qu, int qv) {
   const Shell3Geom& g = a.g;
-  if (qv > g.vmax || qv < -g.vmax) return cmk(T(0), T(0));
-  int s = qu * qu + qv * qv;
-  if (s < 1 || s > g.smax) return cmk(T(0), T(0));
-  if (g.lut[(size_t)eta * g.S1 + s] != shell) return cmk(T(0), T(0));
-  int hu = qv >= 0 ? qu : -qu, hv = qv >= 0 ? qv : -qv;  // stored half-plane cell
-  if (g.uvm && !g.uvm[(size_t)wrap(hu, g.n) * g.nh + hv]) return cmk(T(0), T(0));
+  if (qv > g.vmax || qv < -g.vmax) return false;
+  const int s = qu * qu + qv * qv;
+  if (s < 1 || s > g.smax) return false;
+  bool in = g.lut[(size_t)eta * g.S1 + s] == shell;
+  if (g.uvm) {
+    const int hu = qv >= 0 ? qu : -qu, hv = qv >= 0 ? qv : -qv;  // stored half-plane cell
+    in = in && g.uvm[(size_t)wrap(hu, g.n) * g.nh + hv];
+  }
+  return in;
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> shell_data(const Pass3Args& a, int eta, int qu, int qv) {
+  const Shell3Geom& g = a.g;
   if (a.indicator) return cmk(T(1), T(0));
   const Cx<T>* D = (const Cx<T>*)a.in;
   if (qv >= 0) return D[((size_t)(eta + g.H) * g.nub + (qu + g.vmax)) * g.nvb + qv];
@@ -110,10 +139,21 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   const int nl = min(a.NL, g.nub - w.start);
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
-  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int l = e / n, i = e - l * n;
-    int qu = w.start + l - g.vmax;
-    A[(size_t)l * ld + i] = shell_value<T>(a, shell, w.eta, qu, sidx(i, n));
+  // column i (qv) of the block's qu rows, eight rows at a time: the shell-table and mask reads of
+  // all eight first, then the data reads of the members, then the LDS stores
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int qv = sidx(i, n);
+    for (int l0 = 0; l0 < nl; l0 += 8) {
+      bool mem[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mem[u] = l0 + u < nl && shell_member(a, shell, w.eta, w.start + l0 + u - g.vmax, qv);
+      Cx<T> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = mem[u] ? shell_data<T>(a, w.eta, w.start + l0 + u - g.vmax, qv) : cmk(T(0), T(0));
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (l0 + u < nl) A[(size_t)(l0 + u) * ld + i] = v[u];
+    }
   }
   __syncthreads();
   Cx<T>* r = A;
@@ -143,12 +183,19 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
   const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + ((size_t)xv * hp1 + e0) * g.nub;
-  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int l = e / n, i = e - l * n;
-    int qu = sidx(i, n);
-    Cx<T> x = cmk(T(0), T(0));
-    if (qu >= -g.vmax && qu <= g.vmax) x = in[(size_t)l * g.nub + qu + g.vmax];
-    A[(size_t)l * ld + i] = x;
+  // column i of every plane: eight loads in flight per thread before their LDS stores
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int qu = sidx(i, n);
+    const bool inw = qu >= -g.vmax && qu <= g.vmax;
+    const Cx<T>* src = in + (inw ? qu + g.vmax : 0);
+    for (int l0 = 0; l0 < nl; l0 += 8) {
+      Cx<T> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = inw && l0 + u < nl ? src[(size_t)(l0 + u) * g.nub] : cmk(T(0), T(0));
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (l0 + u < nl) A[(size_t)(l0 + u) * ld + i] = v[u];
+    }
   }
   __syncthreads();
   Cx<T>* r = A;
