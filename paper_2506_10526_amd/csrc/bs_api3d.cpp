@@ -158,13 +158,13 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   a.work = fd.d_wv; a.off_in = nullptr; a.off_out = fd.d_offT; a.in = fd.D; a.out = fd.Tm; a.tw = fd.tw_n;
   a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = fd.indicator ? 1 : 0;
   a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLv, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLv, 256, 4) ? 4 : 0;
-  launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, (a.ip ? 1 : 2) * (size_t)p.NLv * (n + 1) * cz);
+  launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, ((a.ip ? 1 : 2) * (size_t)p.NLv * (n + 1) + n) * cz);
   LAUNCHCHK(c, "v pass");
   // u pass
   a.work = fd.d_wu; a.off_in = fd.d_offT; a.off_out = fd.d_offG; a.in = fd.Tm; a.out = fd.Gm; a.NL = p.NLu;
   a.gs = fd.Gs; a.off_gs = fd.d_offGs; a.scale = fd.gscale;
   a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLu, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLu, 256, 4) ? 4 : 0;
-  launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, (a.ip ? 1 : 2) * (size_t)p.NLu * (n + 1) * cz);
+  launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, ((a.ip ? 1 : 2) * (size_t)p.NLu * (n + 1) + n) * cz);
   LAUNCHCHK(c, "u pass");
   a.gs = nullptr; a.off_gs = nullptr; a.ip = 0;
   if (!F) return BS_OK;

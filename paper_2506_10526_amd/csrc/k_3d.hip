@@ -139,6 +139,9 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   const int nl = min(a.NL, g.nub - w.start);
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
+  // the FFT's twiddle table (n entries) in LDS after the line buffers, loaded with the lines
+  Cx<T>* twl = A + (size_t)a.NL * ld * (IP > 0 ? 1 : 2);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = ((const Cx<T>*)a.tw)[e];
   // column i (qv) of the block's qu rows, eight rows at a time: the shell-table and mask reads of
   // all eight first, then the data reads of the members, then the LDS stores
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -157,8 +160,8 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   }
   __syncthreads();
   Cx<T>* r = A;
-  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
-  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, twl, 1, ld);
+  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, twl, 1, ld);
   // T_j[x_v][eta][qu]: consecutive threads write consecutive qu rows of one x_v
   const int hp1 = a.hj[w.j] + 1;
   Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
@@ -182,6 +185,9 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   const int nl = min(a.NL, hp1 - e0);
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
+  // the FFT's twiddle table (n entries) in LDS after the line buffers, loaded with the lines
+  Cx<T>* twl = A + (size_t)a.NL * ld * (IP > 0 ? 1 : 2);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = ((const Cx<T>*)a.tw)[e];
   const Cx<T>* in = (const Cx<T>*)a.in + a.off_in[w.j] + ((size_t)xv * hp1 + e0) * g.nub;
   // column i of every plane: eight loads in flight per thread before their LDS stores
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -199,8 +205,8 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
   }
   __syncthreads();
   Cx<T>* r = A;
-  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
-  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  if constexpr (IP > 0) lds_fft_ip<+1, T, IP>(A, a.plan, nl, twl, 1, ld);
+  else r = lds_fft<+1, T>(A, Bf, a.plan, nl, twl, 1, ld);
   if constexpr (std::is_same<T, float>::value) {
     if (a.gs) {
       // bf16 hi/lo A-fragments of K-step s = e0 / 16 for the n / 16 line groups of this x_v column:
