@@ -148,7 +148,7 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
     d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = fd.D; d.tw = fd.tw_nc;
     d.plan = make_fft_plan(nc); d.NL = p.NLd;
     d.ip = two ? 0 : fft_ip_fits(d.plan, p.NLd, 256, 2) ? 2 : fft_ip_fits(d.plan, p.NLd, 256, 4) ? 4 : 0;
-    size_t lds = (d.ip ? 1 : 2) * (size_t)p.NLd * (nc + 1) * cz;
+    size_t lds = ((d.ip ? 1 : 2) * (size_t)p.NLd * (nc + 1) + nc) * cz;
     if (fd.fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
     LAUNCHCHK(c, "delay transform");
   }

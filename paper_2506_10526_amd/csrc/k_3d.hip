@@ -55,6 +55,9 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
   const int ld = nc + 1;
   Cx<T>* A = (Cx<T>*)smem_raw;
   Cx<T>* Bf = A + (size_t)a.NL * ld;
+  // the FFT's twiddle table (nc entries) in LDS after the line buffers, loaded with the lines
+  Cx<T>* twl = A + (size_t)a.NL * ld * (IP > 0 ? 1 : 2);
+  for (int e = threadIdx.x; e < nc; e += blockDim.x) twl[e] = ((const Cx<T>*)a.tw)[e];
   const Cx<T>* vis = (const Cx<T>*)a.vis;
   // eight elements per thread in flight before their LDS stores
   const float rnl = 1.0f / (float)nl;
@@ -91,8 +94,8 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
   }
   __syncthreads();
   Cx<T>* r = A;
-  if constexpr (IP > 0) lds_fft_ip<-1, T, IP>(A, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
-  else r = lds_fft<-1, T>(A, Bf, a.plan, nl, (const Cx<T>*)a.tw, 1, ld);
+  if constexpr (IP > 0) lds_fft_ip<-1, T, IP>(A, a.plan, nl, twl, 1, ld);
+  else r = lds_fft<-1, T>(A, Bf, a.plan, nl, twl, 1, ld);
   Cx<T>* out = (Cx<T>*)a.out;
   const int ne = 2 * g.H + 1;
   for (int e = threadIdx.x; e < ne * nl; e += blockDim.x) {
