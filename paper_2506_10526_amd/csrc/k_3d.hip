@@ -728,16 +728,16 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
     const int c = ct * 16 + r16;
     oc[ct] = (c < nbu ? c : DFT_MAX_FIELDS) * DFT_LDQ;
   }
-  // this wave's FP64 slot: rows past the pair tiles are zero; the owned entries are written on the
-  // first flush and accumulated afterwards (always by the owning lane)
+  // this wave's FP64 slot, zeroed here; every flush adds the FP32 sums into it with FP64 atomic adds
+  // that return nothing, so a flush never waits for memory (each entry is updated only by its
+  // owning lane, in program order: the sums stay deterministic)
   double* slot = a.partial + ((size_t)blockIdx.x * DFT_WAVES + wave) * 112 * 32;
-  for (int e = RTN * 16 * 32 + lane; e < 112 * 32; e += 64) slot[e] = 0.0;
+  for (int e = lane; e < RTN * 16 * 32; e += 64) slot[e] = 0.0;   // only the pair-tile rows are read
   f32x4 acc[RTN][2];
 #pragma unroll
   for (int i = 0; i < RTN; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bool first = true;
   auto flush = [&]() {
     // the lane index passes through an empty asm so that the addresses are formed here
     int ln = lane;
@@ -749,11 +749,9 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double* d = &slot[(i * 16 + (ln >> 4) * 4 + q) * 32 + j * 16 + (ln & 15)];
-          const double v = (double)acc[i][j][q];
-          *d = first ? v : *d + v;
+          unsafeAtomicAdd(d, (double)acc[i][j][q]);
           acc[i][j][q] = 0.f;
         }
-    first = false;
   };
   const v4u_t* Gs = (const v4u_t*)a.Gs;
   const int ntt = M >> 4;   // a multiple of 8: every wave takes ntt / DFT_WAVES tiles per group
@@ -858,7 +856,8 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   for (int e = tid; e < RTN * 16 * 32; e += DFT_WAVES * 64) {
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < DFT_WAVES; ++w) v += bslot[(size_t)w * 112 * 32 + e];
+    for (int w = 0; w < DFT_WAVES; ++w)   // read at device scope: the adds were made at L2
+      v += __hip_atomic_load(&bslot[(size_t)w * 112 * 32 + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bslot[e] = v;
   }
 }
