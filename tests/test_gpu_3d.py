@@ -174,3 +174,47 @@ def test_3d_rejects_cell_weights(ctx):
         assert e.value.code == bs.BS_EUNSUPPORTED
     finally:
         bs.bs_free_bins(h)
+
+
+@pytest.mark.parametrize("prec", [bs.BS_FP32, bs.BS_SPLIT_BF16])
+def test_3d_plan_reuse_across_bins(prec):
+    """Unweighted estimates reuse their prepared plan while bins, precision and workspaces stay the
+    same.  Alternating two bin sets (and a weighted call in between) on one context must give, for
+    every call, the bits a fresh context gives for that call alone."""
+    n, nc = 32, 128
+    wl = synth.small_workload(n, nc)
+    V = synth.make_cube(wl, seed=29)
+    ea, kwa, _ = cubic_case(n, nc, 6, 40.0)
+    eb, kwb, _ = cubic_case(n, nc, 5, 10.0)
+
+    def fresh(edges, kw, **wk):
+        c = Ctx()
+        try:
+            h, ncand = bs.bs_make_bins(c.h, bs.BS_SHELL_K, n, nc, edges, **kw)
+            try:
+                return run3(c.h, h, V, prec, ncand, **wk)
+            finally:
+                bs.bs_free_bins(h)
+        finally:
+            c.close()
+
+    ref_a, ref_b = fresh(ea, kwa), fresh(eb, kwb)
+    uvm = synth.disk_mask(n)
+    ref_aw = fresh(ea, kwa, uv_mask=cuda(uvm))
+    c = Ctx()
+    try:
+        ha, na = bs.bs_make_bins(c.h, bs.BS_SHELL_K, n, nc, ea, **kwa)
+        hb, nb = bs.bs_make_bins(c.h, bs.BS_SHELL_K, n, nc, eb, **kwb)
+        try:
+            seq = [("a", ha, na, {}), ("a", ha, na, {}), ("b", hb, nb, {}), ("a", ha, na, {}),
+                   ("aw", ha, na, {"uv_mask": cuda(uvm)}), ("a", ha, na, {}), ("b", hb, nb, {})]
+            refs = {"a": ref_a, "b": ref_b, "aw": ref_aw}
+            for name, h, ncand, wk in seq:
+                got = run3(c.h, h, V, prec, ncand, **wk)
+                for g, r in zip(got, refs[name]):
+                    assert np.array_equal(np.nan_to_num(g, nan=-1.0), np.nan_to_num(r, nan=-1.0)), name
+        finally:
+            bs.bs_free_bins(ha)
+            bs.bs_free_bins(hb)
+    finally:
+        c.close()
