@@ -38,6 +38,7 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
   p.NLe = fp64 ? 8 : 16;
   if (P.nc >= 1024) p.NLe = fp64 ? 4 : 8;
   p.NLd = (P.nc > 512) ? 4 : (fp64 ? 8 : 16);   // long delay axes: small blocks, several per CU
+  bool iv_ok = P.kind == BS_SHELL_K && P.smax < 65536;
   for (size_t j = 0; j < blocks.size(); ++j) {
     int h = std::max(0, P.eta_hi[blocks[j]]);
     p.hj.push_back(h);
@@ -46,12 +47,23 @@ void build_plan3(const bsplan::Plan& P, const std::vector<int>& blocks, bool fp6
     p.offG.push_back(p.totG);
     p.totT += (long long)(h + 1) * nub * n;
     p.totG += (long long)(h + 1) * n2;
-    for (int e = 0; e <= h; ++e)
-      for (int q0 = 0; q0 < nub; q0 += p.NLv) p.wv.push_back({(int)j, e, q0, 0});
+    for (int e = 0; e <= h; ++e) {
+      // the shell's cells at |eta| = e as one range [lo, hi] of s, if they are one
+      int lo = -1, hi = -2;
+      for (int sv = 1; sv <= P.smax; ++sv)
+        if (P.lut[(size_t)e * (P.smax + 1) + sv] == blocks[j]) { if (lo < 0) lo = sv; hi = sv; }
+      for (int sv = std::max(lo, 1); sv <= hi && iv_ok; ++sv)
+        iv_ok = P.lut[(size_t)e * (P.smax + 1) + sv] == blocks[j];
+      if (lo < 0) { lo = 1; hi = 0; }   // empty
+      iv_ok = iv_ok && hi < 65536;
+      const int pad = iv_ok ? (lo | (hi << 16)) : 0;
+      for (int q0 = 0; q0 < nub; q0 += p.NLv) p.wv.push_back({(int)j, e, q0, pad});
+    }
     for (int xv = 0; xv < n; ++xv)
       for (int e0 = 0; e0 <= h; e0 += p.NLu) p.wu.push_back({(int)j, e0, xv, 0});
     for (long long l0 = 0; l0 < n2; l0 += p.NLe) p.we.push_back({(int)j, 0, (int)l0, 0});
   }
+  p.shell_iv = iv_ok;
 }
 
 namespace {
@@ -157,6 +169,7 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   // v pass
   a.work = fd.d_wv; a.off_in = nullptr; a.off_out = fd.d_offT; a.in = fd.D; a.out = fd.Tm; a.tw = fd.tw_n;
   a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = fd.indicator ? 1 : 0;
+  a.shell_iv = p.shell_iv && !getenv("BS_3D_SHELL_TABLE") ? 1 : 0;
   a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLv, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLv, 256, 4) ? 4 : 0;
   launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, ((a.ip ? 1 : 2) * (size_t)p.NLv * (n + 1) + n) * cz);
   LAUNCHCHK(c, "v pass");
@@ -166,7 +179,7 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLu, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLu, 256, 4) ? 4 : 0;
   launch_upass3(a, (int)p.wu.size(), fd.fp64, c->stream, ((a.ip ? 1 : 2) * (size_t)p.NLu * (n + 1) + n) * cz);
   LAUNCHCHK(c, "u pass");
-  a.gs = nullptr; a.off_gs = nullptr; a.ip = 0;
+  a.gs = nullptr; a.off_gs = nullptr; a.ip = 0; a.shell_iv = 0;
   if (!F) return BS_OK;
   // eta pass (C2R), output length nc
   const int M = nc;

@@ -19,6 +19,9 @@ struct Plan3 {
   int H = 0;
   std::vector<Work3> wv, wu, we;
   int NLv = 8, NLu = 8, NLe = 16, NLd = 8;
+  // true when, for every v-pass item, the cells of its shell at its |eta| are one range of
+  // s = qu^2 + qv^2, held in the item's pad as lo | hi << 16 (the v pass then needs no table reads)
+  bool shell_iv = false;
 };
 
 // Device-side state of the field pipeline of one plan: workspaces and work lists.  Prepared once

@@ -137,6 +137,7 @@ struct Pass3Args {
   int NL;
   int ip;                      // v / u pass: 2 or 4 = in-place FFT with that many butterflies per thread; 0 = two buffers
   int indicator;               // v pass: 1 = unit indicator of shell and support, 0 = data
+  int shell_iv;                // v pass: 1 = shell membership from the item's s range (Work3::pad)
   int M;                       // eta pass: output length along eta
   double scale;                // eta pass: overall 1 / (M n^2); u pass with gs: the same, folded into gs
   long long fstride;           // eta pass: elements per output field (M n^2)

@@ -110,12 +110,13 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
 // Input value of shell j at (eta >= 0, qu, qv): data Vt or the unit indicator.
 // Membership of (eta >= 0, qu, qv) in shell j (shell table and uv support), then its input value:
 // data Vt or the unit indicator.
-__device__ __forceinline__ bool shell_member(const Pass3Args& a, int shell, int eta, int qu, int qv) {
+// With a.shell_iv the shell's cells at this |eta| are the range [s_lo, s_hi] of s (no table read).
+__device__ __forceinline__ bool shell_member(const Pass3Args& a, int shell, int eta, int qu, int qv, int s_lo, int s_hi) {
   const Shell3Geom& g = a.g;
   if (qv > g.vmax || qv < -g.vmax) return false;
   const int s = qu * qu + qv * qv;
   if (s < 1 || s > g.smax) return false;
-  bool in = g.lut[(size_t)eta * g.S1 + s] == shell;
+  bool in = a.shell_iv ? s >= s_lo && s <= s_hi : g.lut[(size_t)eta * g.S1 + s] == shell;
   if (g.uvm) {
     const int hu = qv >= 0 ? qu : -qu, hv = qv >= 0 ? qv : -qv;  // stored half-plane cell
     in = in && g.uvm[(size_t)wrap(hu, g.n) * g.nh + hv];
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   // the FFT's twiddle table (n entries) in LDS after the line buffers, loaded with the lines
   Cx<T>* twl = A + (size_t)a.NL * ld * (IP > 0 ? 1 : 2);
   for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = ((const Cx<T>*)a.tw)[e];
+  const int s_lo = w.pad & 0xffff, s_hi = (int)((unsigned)w.pad >> 16);
   // column i (qv) of the block's qu rows, eight rows at a time: the shell-table and mask reads of
   // all eight first, then the data reads of the members, then the LDS stores
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -152,7 +154,8 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
     for (int l0 = 0; l0 < nl; l0 += 8) {
       bool mem[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) mem[u] = l0 + u < nl && shell_member(a, shell, w.eta, w.start + l0 + u - g.vmax, qv);
+      for (int u = 0; u < 8; ++u)
+        mem[u] = l0 + u < nl && shell_member(a, shell, w.eta, w.start + l0 + u - g.vmax, qv, s_lo, s_hi);
       Cx<T> v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = mem[u] ? shell_data<T>(a, w.eta, w.start + l0 + u - g.vmax, qv) : cmk(T(0), T(0));

@@ -53,7 +53,8 @@ def run3(ctx, h, V, prec, ncand, **wk):
 @pytest.mark.parametrize("prec", PREC)
 @pytest.mark.parametrize("case", ["cubic16x8", "cubic32x24_flags", "cubic32x128_fused", "cubic32x128_unfused",
                                   "cubic32x256_coarse", "cubic32x256_fullgrid", "cubic32x128_wide",
-                                  "cubic32x128_wide_fft", "cubic32x128_wide_groups", "cubic32x128_wide_twobuf"])
+                                  "cubic32x128_wide_fft", "cubic32x128_wide_groups", "cubic32x128_wide_twobuf",
+                                  "cubic32x128_wide_table"])
 def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
     """Small cubes: radix-2/3 delay axes, flags, and (nc = 128) the fused eta-C2R + contraction
     kernels (split-BF16: synthesis on MFMA, or the FFT form with BS_3D_FFT=1) next to the path that
@@ -64,6 +65,9 @@ def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
         monkeypatch.setenv("BS_3D_FULLGRID", "1")
     if case.endswith("_fft"):
         monkeypatch.setenv("BS_3D_FFT", "1")
+    if case.endswith("_table"):
+        # v pass reading the shell table per cell instead of each item's range of s
+        monkeypatch.setenv("BS_3D_SHELL_TABLE", "1")
     if case.endswith("_twobuf"):
         # delay, v and u passes with the two-buffer LDS FFT instead of the in-place one
         monkeypatch.setenv("BS_3D_FFT_TWO_BUFFERS", "1")
