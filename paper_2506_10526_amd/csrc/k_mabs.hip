@@ -530,9 +530,13 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
         for (int e = 0; e < 16; ++e) {
           const int row = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (ln >> 5) * 4 + (e & 3);
           if (interior || (row < nrows && col < a.nc)) {
+            // first flush: a plain store; later ones: FP64 atomic adds that return nothing, so
+            // the copies in flight are not waited for (each entry belongs to one lane: the
+            // order of the adds and the result are fixed)
             double* d = &S[(size_t)row * a.nc + col];
-            double v = (double)acc[i][j][e];
-            *d = first_flush ? v : *d + v;
+            const double v = (double)acc[i][j][e];
+            if (first_flush) *d = v;
+            else unsafeAtomicAdd(d, v);
           }
           acc[i][j][e] = 0.f;
         }
