@@ -731,11 +731,11 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
     const int c = ct * 16 + r16;
     oc[ct] = (c < nbu ? c : DFT_MAX_FIELDS) * DFT_LDQ;
   }
-  // this wave's FP64 slot, zeroed here; every flush adds the FP32 sums into it with FP64 atomic adds
-  // that return nothing, so a flush never waits for memory (each entry is updated only by its
-  // owning lane, in program order: the sums stay deterministic)
+  // this wave's FP64 slot (pair-tile rows only): the first flush stores the FP32 sums, later ones
+  // add them with FP64 atomic adds that return nothing, so a flush never waits for memory (each
+  // entry is updated only by its owning lane, in program order: the sums stay deterministic)
   double* slot = a.partial + ((size_t)blockIdx.x * DFT_WAVES + wave) * 112 * 32;
-  for (int e = lane; e < RTN * 16 * 32; e += 64) slot[e] = 0.0;   // only the pair-tile rows are read
+  bool first = true;
   f32x4 acc[RTN][2];
 #pragma unroll
   for (int i = 0; i < RTN; ++i)
@@ -752,9 +752,11 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double* d = &slot[(i * 16 + (ln >> 4) * 4 + q) * 32 + j * 16 + (ln & 15)];
-          unsafeAtomicAdd(d, (double)acc[i][j][q]);
+          if (first) *d = (double)acc[i][j][q];
+          else unsafeAtomicAdd(d, (double)acc[i][j][q]);
           acc[i][j][q] = 0.f;
         }
+    first = false;
   };
   const v4u_t* Gs = (const v4u_t*)a.Gs;
   const int ntt = M >> 4;   // a multiple of 8: every wave takes ntt / DFT_WAVES tiles per group
