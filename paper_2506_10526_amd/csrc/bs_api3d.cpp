@@ -446,7 +446,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       // several line groups and flushes on every wave of a small cube
       const char* eb = getenv("BS_3D_DFT_BLOCKS");
       const char* ef = getenv("BS_3D_DFT_FLUSH");
-      da.flush_vox = ef ? std::max(256, atoi(ef)) : 4096;
+      da.flush_vox = ef ? std::max(256, atoi(ef)) : 8192;
       e.dblocks = (int)std::min<long long>(ngroups, eb ? std::max(1, atoi(eb)) : 256);
       da.groups_per_block = (int)((ngroups + e.dblocks - 1) / e.dblocks);
       e.dblocks = (int)((ngroups + da.groups_per_block - 1) / da.groups_per_block);

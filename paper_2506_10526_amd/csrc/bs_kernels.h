@@ -214,7 +214,7 @@ struct Dft3Args {
   const int* pairs; int npairs;
   int ngroups;                 // line groups n * n / 16
   int groups_per_block;
-  int flush_vox;               // voxels per wave between FP64 flushes (4096: 128 FP32 MFMA accumulations)
+  int flush_vox;               // voxels per wave between FP64 flushes (8192: 256 FP32 MFMA accumulations)
   double* partial;             // [gridDim.x * DFT_WAVES][112][32]: one slot per wave
 };
 constexpr int DFT_SCHED = 28;  // schedule row: DFT_MAX_FIELDS fragment indices, chunk mask, padding to 16 bytes
