@@ -22,6 +22,7 @@ struct GenArgs {
   FftPlan pn, pnc;               // lengths n and nc
   int NL;                        // row pairs per block (row passes)
   int NLx, NLz;                  // lines per block of the x and z passes
+  int ipx, ipz;                  // their in-place FFT bound (butterflies per thread; 0: two buffers)
 };
 
 // sqrt(A) into stat[0] (sum of P over the full grid, reduced in a fixed order).

@@ -59,8 +59,17 @@ GenArgs gen_args(bs_ctx* c, const bs_field_desc* d, int& rc) {
   a.pnc = make_fft_plan(d->nc);
   a.NL = d->n <= 256 ? 16 : (d->n <= 512 ? 8 : 4);
   a.NLx = a.NL;
-  a.NLz = 16;
-  while (a.NLz > 1 && 2 * (size_t)a.NLz * (d->nc + 1) * 8 + (size_t)a.NLz * 8 > 100 * 1024) a.NLz /= 2;
+  auto ip_of = [](const FftPlan& p, int nl) { return fft_ip_fits(p, nl, 256, 2) ? 2 : fft_ip_fits(p, nl, 256, 4) ? 4 : 0; };
+  a.ipx = ip_of(a.pn, a.NLx);
+  // z pass: the most lines that transform in place within 32 KB of LDS (several blocks per CU),
+  // else two buffers within 100 KB
+  a.ipz = 0;
+  for (int nl = 16; nl >= 1 && !a.ipz; nl /= 2)
+    if ((size_t)nl * (d->nc + 1) * 8 + (size_t)nl * 8 <= 32 * 1024 && ip_of(a.pnc, nl)) { a.NLz = nl; a.ipz = ip_of(a.pnc, nl); }
+  if (!a.ipz) {
+    a.NLz = 16;
+    while (a.NLz > 1 && 2 * (size_t)a.NLz * (d->nc + 1) * 8 + (size_t)a.NLz * 8 > 100 * 1024) a.NLz /= 2;
+  }
   return a;
 }
 

@@ -228,13 +228,14 @@ __global__ __launch_bounds__(256) void k_gen_mean(GenArgs a, int nparts) {
 // so consecutive lines are consecutive addresses.
 // OP 0: forward; 1: inverse; 2: forward, times sqrt(A P), inverse (z axis, outer = 1);
 // 3: forward, times w(o) (x axis, o = z).
-template <int OP>
+// IP > 0: in-place FFT with at most IP butterflies per thread (one line buffer), else two buffers.
+template <int OP, int IP>
 __global__ __launch_bounds__(256) void k_gen_axis(GenArgs a, int L, int outer, int inner, int NL) {
   extern __shared__ unsigned char smem[];
   const int ld = L + 1;
   C* bufA = (C*)smem;
   C* bufB = bufA + (size_t)NL * ld;
-  long long* base = (long long*)(bufB + (size_t)NL * ld);
+  long long* base = (long long*)(bufA + (size_t)NL * ld * (IP > 0 ? 1 : 2));
   const long long nlines = (long long)outer * inner;
   const long long g0 = (long long)blockIdx.x * NL;
   const int nl = (int)((nlines - g0) < NL ? (nlines - g0) : NL);
@@ -244,15 +245,28 @@ __global__ __launch_bounds__(256) void k_gen_axis(GenArgs a, int L, int outer, i
     base[threadIdx.x] = o * (long long)L * inner + b;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < L * NL; t += 256) {
-    const int l = t / NL, bl = t - l * NL;
-    if (bl < nl) bufA[(size_t)bl * ld + l] = a.W[base[bl] + (long long)l * inner];
+  // eight loads in flight per thread before their LDS stores
+  for (int t0 = threadIdx.x; t0 < L * NL; t0 += 8 * 256) {
+    C v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * 256, l = t / NL, bl = t - l * NL;
+      if (t < L * NL && bl < nl) v[u] = a.W[base[bl] + (long long)l * inner];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * 256, l = t / NL, bl = t - l * NL;
+      if (t < L * NL && bl < nl) bufA[(size_t)bl * ld + l] = v[u];
+    }
   }
   __syncthreads();
   const C* tw = (const C*)(L == a.n ? a.tw_n : a.tw_nc);
   const FftPlan& pl = (L == a.n) ? a.pn : a.pnc;
-  C* R;
-  if (OP == 1) {
+  C* R = bufA;
+  if constexpr (IP > 0) {
+    if (OP == 1) lds_fft_ip<1, float, IP>(bufA, pl, nl, tw, 1, ld);
+    else lds_fft_ip<-1, float, IP>(bufA, pl, nl, tw, 1, ld);
+  } else if (OP == 1) {
     R = lds_fft<1, float>(bufA, bufB, pl, nl, tw, 1, ld);
   } else {
     R = lds_fft<-1, float>(bufA, bufB, pl, nl, tw, 1, ld);
@@ -271,8 +285,12 @@ __global__ __launch_bounds__(256) void k_gen_axis(GenArgs a, int L, int outer, i
       R[(size_t)bl * ld + l] = cscale(R[(size_t)bl * ld + l], s);
     }
     __syncthreads();
-    C* other = (R == bufA) ? bufB : bufA;
-    R = lds_fft<1, float>(R, other, pl, nl, tw, 1, ld);
+    if constexpr (IP > 0) {
+      lds_fft_ip<1, float, IP>(R, pl, nl, tw, 1, ld);
+    } else {
+      C* other = (R == bufA) ? bufB : bufA;
+      R = lds_fft<1, float>(R, other, pl, nl, tw, 1, ld);
+    }
   }
   for (int t = threadIdx.x; t < L * NL; t += 256) {
     const int l = t / NL, bl = t - l * NL;
@@ -334,6 +352,13 @@ void launch_gen_set_state(unsigned long long* state, unsigned long long seed, un
   hipLaunchKernelGGL(k_gen_set_state, dim3(1), dim3(64), 0, s, state, seed, real);
 }
 
+template <int OP>
+static void launch_axis(const GenArgs& a, int ip, int nb, size_t lds, hipStream_t s, int L, int outer, int inner, int NL) {
+  if (ip == 2) { set_lds(k_gen_axis<OP, 2>, lds); hipLaunchKernelGGL((k_gen_axis<OP, 2>), dim3(nb), dim3(256), lds, s, a, L, outer, inner, NL); }
+  else if (ip == 4) { set_lds(k_gen_axis<OP, 4>, lds); hipLaunchKernelGGL((k_gen_axis<OP, 4>), dim3(nb), dim3(256), lds, s, a, L, outer, inner, NL); }
+  else { set_lds(k_gen_axis<OP, 0>, lds); hipLaunchKernelGGL((k_gen_axis<OP, 0>), dim3(nb), dim3(256), lds, s, a, L, outer, inner, NL); }
+}
+
 int gen_row_blocks(const GenArgs& a) {
   const long long npairs = (long long)a.nc * a.n / 2;
   return (int)((npairs + a.NL - 1) / a.NL);
@@ -344,25 +369,21 @@ void launch_gen_cube(const GenArgs& a, hipStream_t s) {
   const int rb = gen_row_blocks(a);
   // axis passes: x (L = n, outer = nc, inner = nh), z (L = nc, outer = 1, inner = n nh)
   const int NLx = a.NLx, NLz = a.NLz;
-  const size_t lds_x = 2 * (size_t)NLx * (a.n + 1) * sizeof(C) + (size_t)NLx * 8;
-  const size_t lds_z = 2 * (size_t)NLz * (a.nc + 1) * sizeof(C) + (size_t)NLz * 8;
+  const size_t lds_x = (a.ipx ? 1 : 2) * (size_t)NLx * (a.n + 1) * sizeof(C) + (size_t)NLx * 8;
+  const size_t lds_z = (a.ipz ? 1 : 2) * (size_t)NLz * (a.nc + 1) * sizeof(C) + (size_t)NLz * 8;
   const long long lx = (long long)a.nc * a.nh, lz = (long long)a.n * a.nh;
   const int bx = (int)((lx + NLx - 1) / NLx), bz = (int)((lz + NLz - 1) / NLz);
   set_lds(k_gen_rows_fwd<0>, lds_rows);
   set_lds(k_gen_rows_fwd<1>, lds_rows);
   set_lds(k_gen_rows_c2r, lds_rows);
-  set_lds(k_gen_axis<0>, lds_x);
-  set_lds(k_gen_axis<1>, lds_x);
-  set_lds(k_gen_axis<2>, lds_z);
-  set_lds(k_gen_axis<3>, lds_x);
   hipLaunchKernelGGL(k_gen_rows_fwd<0>, dim3(rb), dim3(256), lds_rows, s, a);
-  hipLaunchKernelGGL(k_gen_axis<0>, dim3(bx), dim3(256), lds_x, s, a, a.n, a.nc, a.nh, NLx);
-  hipLaunchKernelGGL(k_gen_axis<2>, dim3(bz), dim3(256), lds_z, s, a, a.nc, 1, a.n * a.nh, NLz);
-  hipLaunchKernelGGL(k_gen_axis<1>, dim3(bx), dim3(256), lds_x, s, a, a.n, a.nc, a.nh, NLx);
+  launch_axis<0>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
+  launch_axis<2>(a, a.ipz, bz, lds_z, s, a.nc, 1, a.n * a.nh, NLz);
+  launch_axis<1>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
   hipLaunchKernelGGL(k_gen_rows_c2r, dim3(rb), dim3(256), lds_rows, s, a);
   hipLaunchKernelGGL(k_gen_mean, dim3(1), dim3(256), 0, s, a, rb);
   hipLaunchKernelGGL(k_gen_rows_fwd<1>, dim3(rb), dim3(256), lds_rows, s, a);
-  hipLaunchKernelGGL(k_gen_axis<3>, dim3(bx), dim3(256), lds_x, s, a, a.n, a.nc, a.nh, NLx);
+  launch_axis<3>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
 }
 
 void launch_mc_accumulate(const double* B, int ntri, long long* cnt, double* mean, double* m2,
