@@ -113,7 +113,7 @@ __global__ void k_gen_amp(GenArgs a) {
 
 // ---------------------------------------------------------------- rows along y
 // Block: NL row pairs (rows 2p, 2p+1, p = blockIdx.x NL + l).  MODE 0: white noise; 1: delta(g).
-template <int MODE>
+template <int MODE, int IP>   // IP: in-place FFT bound (butterflies per thread), 0 = two buffers
 __global__ __launch_bounds__(256) void k_gen_rows_fwd(GenArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.n, nh = a.nh, ld = n + 1, NL = a.NL;
@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) void k_gen_rows_fwd(GenArgs a) {
     }
   }
   __syncthreads();
-  C* R = lds_fft<-1, float>(bufA, bufB, a.pn, nl, (const C*)a.tw_n, 1, ld);
+  C* R = bufA;
+  if constexpr (IP > 0) lds_fft_ip<-1, float, IP>(bufA, a.pn, nl, (const C*)a.tw_n, 1, ld);
+  else R = lds_fft<-1, float>(bufA, bufB, a.pn, nl, (const C*)a.tw_n, 1, ld);
   // split Z = X0 + i X1 into the two real rows' half spectra
   for (int t = threadIdx.x; t < nl * nh; t += 256) {
     const int l = t / nh, k = t - l * nh;
@@ -164,6 +166,7 @@ __global__ __launch_bounds__(256) void k_gen_rows_fwd(GenArgs a) {
 }
 
 // Inverse along y of two half spectra at once; writes g and per-block partial sums of g^2.
+template <int IP>
 __global__ __launch_bounds__(256) void k_gen_rows_c2r(GenArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.n, nh = a.nh, ld = n + 1, NL = a.NL;
@@ -185,7 +188,9 @@ __global__ __launch_bounds__(256) void k_gen_rows_c2r(GenArgs a) {
     bufA[(size_t)l * ld + k] = z;
   }
   __syncthreads();
-  C* R = lds_fft<1, float>(bufA, bufB, a.pn, nl, (const C*)a.tw_n, 1, ld);
+  C* R = bufA;
+  if constexpr (IP > 0) lds_fft_ip<1, float, IP>(bufA, a.pn, nl, (const C*)a.tw_n, 1, ld);
+  else R = lds_fft<1, float>(bufA, bufB, a.pn, nl, (const C*)a.tw_n, 1, ld);
   const float sc = (float)(1.0 / ((double)a.nc * n * n));
   double s2 = 0.0;
   for (int t = threadIdx.x; t < nl * n; t += 256) {
@@ -364,8 +369,22 @@ int gen_row_blocks(const GenArgs& a) {
   return (int)((npairs + a.NL - 1) / a.NL);
 }
 
+template <int IP>
+static void launch_rows(const GenArgs& a, int which, int rb, size_t lds, hipStream_t s) {
+  if (which == 0) { set_lds(k_gen_rows_fwd<0, IP>, lds); hipLaunchKernelGGL((k_gen_rows_fwd<0, IP>), dim3(rb), dim3(256), lds, s, a); }
+  else if (which == 1) { set_lds(k_gen_rows_fwd<1, IP>, lds); hipLaunchKernelGGL((k_gen_rows_fwd<1, IP>), dim3(rb), dim3(256), lds, s, a); }
+  else { set_lds(k_gen_rows_c2r<IP>, lds); hipLaunchKernelGGL((k_gen_rows_c2r<IP>), dim3(rb), dim3(256), lds, s, a); }
+}
+// which: 0 = forward rows from white noise, 1 = forward rows of delta, 2 = inverse rows (C2R)
+static void launch_rows_ip(const GenArgs& a, int which, int rb, size_t lds, hipStream_t s) {
+  if (a.ipx == 2) launch_rows<2>(a, which, rb, lds, s);
+  else if (a.ipx == 4) launch_rows<4>(a, which, rb, lds, s);
+  else launch_rows<0>(a, which, rb, lds, s);
+}
+
 void launch_gen_cube(const GenArgs& a, hipStream_t s) {
-  const size_t lds_rows = 2 * (size_t)a.NL * (a.n + 1) * sizeof(C);
+  // the rows use the plan and line count of the x passes (a.NL == a.NLx), hence a.ipx
+  const size_t lds_rows = (a.ipx ? 1 : 2) * (size_t)a.NL * (a.n + 1) * sizeof(C);
   const int rb = gen_row_blocks(a);
   // axis passes: x (L = n, outer = nc, inner = nh), z (L = nc, outer = 1, inner = n nh)
   const int NLx = a.NLx, NLz = a.NLz;
@@ -373,16 +392,13 @@ void launch_gen_cube(const GenArgs& a, hipStream_t s) {
   const size_t lds_z = (a.ipz ? 1 : 2) * (size_t)NLz * (a.nc + 1) * sizeof(C) + (size_t)NLz * 8;
   const long long lx = (long long)a.nc * a.nh, lz = (long long)a.n * a.nh;
   const int bx = (int)((lx + NLx - 1) / NLx), bz = (int)((lz + NLz - 1) / NLz);
-  set_lds(k_gen_rows_fwd<0>, lds_rows);
-  set_lds(k_gen_rows_fwd<1>, lds_rows);
-  set_lds(k_gen_rows_c2r, lds_rows);
-  hipLaunchKernelGGL(k_gen_rows_fwd<0>, dim3(rb), dim3(256), lds_rows, s, a);
+  launch_rows_ip(a, 0, rb, lds_rows, s);
   launch_axis<0>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
   launch_axis<2>(a, a.ipz, bz, lds_z, s, a.nc, 1, a.n * a.nh, NLz);
   launch_axis<1>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
-  hipLaunchKernelGGL(k_gen_rows_c2r, dim3(rb), dim3(256), lds_rows, s, a);
+  launch_rows_ip(a, 2, rb, lds_rows, s);
   hipLaunchKernelGGL(k_gen_mean, dim3(1), dim3(256), 0, s, a, rb);
-  hipLaunchKernelGGL(k_gen_rows_fwd<1>, dim3(rb), dim3(256), lds_rows, s, a);
+  launch_rows_ip(a, 1, rb, lds_rows, s);
   launch_axis<3>(a, a.ipx, bx, lds_x, s, a.n, a.nc, a.nh, NLx);
 }
 
