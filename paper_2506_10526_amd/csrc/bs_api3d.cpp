@@ -303,6 +303,38 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
   }
   e.npairs = (int)(pairs.size() / 2);
   if (e.npairs > kMaxPairs) return ctx_fail(c, BS_EUNSUPPORTED, "more than 112 shell pairs in use");
+  // Column choice and row order.  A triangle goes to one of its chosen pairs whose third shell is
+  // below 16 (the first field column tile) when it has one; the pairs that still serve a triangle
+  // with a third shell of 16 or more come first, so the MFMA contraction needs the second column
+  // tile only for the leading ceil(n_high / 16) pair row tiles.
+  {
+    std::map<std::pair<int, int>, int> pidx;
+    for (int i = 0; i < e.npairs; ++i) pidx[pkey(pairs[2 * i], pairs[2 * i + 1])] = i;
+    for (int t = 0; t < ntri; ++t) {
+      int best = -1, bcol = -1;
+      for (int q = 0; q < 3; ++q) {
+        auto it = pidx.find(pkey(tb[t][q], tb[t][(q + 1) % 3]));
+        if (it == pidx.end()) continue;
+        const int col = tb[t][(q + 2) % 3];
+        if (best < 0 || (bcol >= 16 && col < 16)) { best = it->second; bcol = col; }
+      }
+      tpair[t] = best;
+      tcol[t] = bcol;
+    }
+    std::vector<char> high(e.npairs, 0);
+    for (int t = 0; t < ntri; ++t) high[tpair[t]] |= tcol[t] >= 16;
+    std::vector<int> order;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < e.npairs; ++i)
+        if ((bool)high[i] == (pass == 0)) order.push_back(i);
+    std::vector<int> where(e.npairs), np2;
+    for (int i = 0; i < e.npairs; ++i) { where[order[i]] = i; np2.push_back(pairs[2 * order[i]]); np2.push_back(pairs[2 * order[i] + 1]); }
+    for (int t = 0; t < ntri; ++t) tpair[t] = where[tpair[t]];
+    pairs.swap(np2);
+    int nhigh = 0;
+    for (char h : high) nhigh += h;
+    e.ct1_tiles = (nhigh + 15) / 16;
+  }
   e.nvox = (long long)P.nc * P.n * P.n;
   e.d_pairs = upload(c, tag + "_pairs", pairs, rc); if (rc) return rc;
   e.d_tp = upload(c, tag + "_tpair", tpair, rc); if (rc) return rc;
@@ -440,7 +472,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;
       da.W = ctx_dft_twiddle(c, M);
       if (!da.W) return ctx_fail(c, BS_ENOMEM, "eta twiddle fragments");
-      da.pairs = e.d_pairs; da.npairs = e.npairs;
+      da.pairs = e.d_pairs; da.npairs = e.npairs; da.ct1_tiles = e.ct1_tiles;
       da.ngroups = (int)ngroups;
       // BS_3D_DFT_BLOCKS / BS_3D_DFT_FLUSH (tests): fewer blocks and shorter flush intervals put
       // several line groups and flushes on every wave of a small cube

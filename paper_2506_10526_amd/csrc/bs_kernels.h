@@ -212,6 +212,7 @@ struct Dft3Args {
   int n, M, Smax;              // uv size (multiple of 16), delay grid, max Sj
   const void* W;               // [M] float2 (cos, sin) of 2 pi m / M
   const int* pairs; int npairs;
+  int ct1_tiles;               // pair row tiles (the leading ones) contracted against fields 16..31 too
   int ngroups;                 // line groups n * n / 16
   int groups_per_block;
   int flush_vox;               // voxels per wave between FP64 flushes (8192: 256 FP32 MFMA accumulations)

@@ -614,7 +614,7 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 template <int RTN>
 __device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const f32x4 (&dk)[DFT_MAX_FIELDS], int nbu,
                                                   const int (&oa)[RTN], const int (&ob)[RTN], const int (&oc)[2],
-                                                  f32x4 (&acc)[RTN][2]) {
+                                                  int ct1_tiles, f32x4 (&acc)[RTN][2]) {
   const int lane = threadIdx.x & 63, kq = lane >> 4;
   float4 ra[2][2], rb[2][2], rc[2][2][2];
   auto write_q = [&](int q) {
@@ -675,11 +675,14 @@ __device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const 
         bf16x8 ah, al;
         split8(v, ah, al);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rt][ct], 0, 0, 0);
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rt][ct], 0, 0, 0);
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rt][ct], 0, 0, 0);
+        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[0], acc[rt][0], 0, 0, 0);
+        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[0], acc[rt][0], 0, 0, 0);
+        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], acc[rt][0], 0, 0, 0);
+        // fields 16..31 only for the pair row tiles that serve such a column
+        if (rt < ct1_tiles) {
+          acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[1], acc[rt][1], 0, 0, 0);
+          acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[1], acc[rt][1], 0, 0, 0);
+          acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], acc[rt][1], 0, 0, 0);
         }
       }
     }
@@ -846,7 +849,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
       }
-      dft_contract_tile<RTN>(sF, dk, nbu, oa, ob, oc, acc);
+      dft_contract_tile<RTN>(sF, dk, nbu, oa, ob, oc, a.ct1_tiles, acc);
       since += 256;
       if (since >= a.flush_vox) { since = 0; flush(); }
     }

@@ -54,7 +54,7 @@ def run3(ctx, h, V, prec, ncand, **wk):
 @pytest.mark.parametrize("case", ["cubic16x8", "cubic32x24_flags", "cubic32x128_fused", "cubic32x128_unfused",
                                   "cubic32x256_coarse", "cubic32x256_fullgrid", "cubic32x128_wide",
                                   "cubic32x128_wide_fft", "cubic32x128_wide_groups", "cubic32x128_wide_twobuf",
-                                  "cubic32x128_wide_table"])
+                                  "cubic32x128_wide_table", "cubic32x128_many"])
 def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
     """Small cubes: radix-2/3 delay axes, flags, and (nc = 128) the fused eta-C2R + contraction
     kernels (split-BF16: synthesis on MFMA, or the FFT form with BS_3D_FFT=1) next to the path that
@@ -79,6 +79,12 @@ def test_3d_matches_oracle(ctx, prec, case, monkeypatch):
     if case.startswith("cubic32x128_wide"):
         # delay modes up to |eta| = 40: three 16-mode steps of the MFMA synthesis for the outer shells
         n, nc, nb, kmax = 32, 128, 6, 40.0
+        wl = synth.small_workload(n, nc)
+        cw = None
+    elif case == "cubic32x128_many":
+        # 18 shells: fields 16 and 17 are contraction columns of the second column tile, which the
+        # MFMA kernel contracts only for the leading pair row tiles
+        n, nc, nb, kmax = 32, 128, 18, 40.0
         wl = synth.small_workload(n, nc)
         cw = None
     elif case.startswith("cubic32x256"):
