@@ -292,7 +292,8 @@ int bs_var_features(const bs_bins* bins, const int64_t* T3D_host, double pk_inde
  * contraction ran on (0 before any 3D call), [4] = algorithmic split-BF16 MFMA flops per
  * contracted voxel of the last 3D split-BF16 contraction when it ran the MFMA synthesis kernel
  * (12 sum_j (H_j + 1) for the eta synthesis of the Hermitian half spectra, H_j the largest |eta|
- * of field j, plus 6 P F for the pair x field contraction, P product rows and F fields; 0 otherwise),
+ * of field j, plus 6 (P min(F, 16) + P_hi max(F - 16, 0)) for the pair x field contraction, P product
+ * rows, F fields and P_hi the rows that serve a triangle whose third field is 16 or later; 0 otherwise),
  * [5] = voxels contracted by that launch (M n^2).  n selects how many values are written (at most 6).
  * Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
 int bs_set_timing(bs_ctx* ctx, int32_t enable);

@@ -333,6 +333,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     pairs.swap(np2);
     int nhigh = 0;
     for (char h : high) nhigh += h;
+    e.nhigh = nhigh;
     e.ct1_tiles = (nhigh + 15) / 16;
   }
   e.nvox = (long long)P.nc * P.n * P.n;
@@ -578,7 +579,10 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   if (e.dft) {
     double modes = 0.0;
     for (int h : e.pd.hj) modes += h + 1;
-    c->last_flops_vox = 12.0 * modes + 6.0 * e.npairs * (double)e.blocks.size();
+    // synthesis: 3 bf16 products x 2 flops x 2 real modes per Hermitian mode; contraction: every
+    // pair against the first 16 fields, the pairs serving a third shell of 16+ against all fields
+    const double F = (double)e.blocks.size();
+    c->last_flops_vox = 12.0 * modes + 6.0 * (e.npairs * std::min(F, 16.0) + e.nhigh * std::max(F - 16.0, 0.0));
     c->last_vox = (double)e.M * b->P.n * b->P.n;
   }
   if (c->timing) { (void)hipEventRecord(c->ev[1], c->stream); c->have_timing = true; }

@@ -52,6 +52,7 @@ struct Est3 {
   bool fp64 = false;
   int ntri = 0, npairs = 0;
   int ct1_tiles = 0;   // leading pair row tiles that serve a triangle with third shell >= 16
+  int nhigh = 0;       // pairs that serve such a triangle
   std::vector<int> blocks;
   int *d_pairs = nullptr, *d_tp = nullptr, *d_tc = nullptr;
   long long nvox = 0, nblk = 0, chunk = 0;
