@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {"k3_dft": (269.0 + 172.0) * 1e6}   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
+TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6}   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
 
 
 def log(*a):
