@@ -694,7 +694,8 @@ template <int RTN>
 __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int ROWS = DFT_MAX_FIELDS + 1;   // fields + one zero row
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15;
+  // the wave index is uniform: readfirstlane lets the tile and copy loops run on scalar control
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), r16 = lane & 15;
   const int nbu = a.nbu, nfr = 2 * a.kb[nbu];
   const int M = a.M;
   v4u_t* stage = (v4u_t*)smem_raw;                                      // [nfr + 1][64], last = zeros
