@@ -14,7 +14,9 @@ MABS (Gill & Bharadwaj 2025, Sec. 3.2):
   X1 X2 X3 / N_pix over closed grid triangles (Sec. 3.2, the paragraph after
   Eq. estimator_t).  `norm` stands for 1/A.
   Ergodic collapse to (dnu1, dnu2) = (nu1 - nu3, nu2 - nu3) averages the
-  per-triplet estimates (Sec. 3.2, the paragraph before Eq. dft).
+  per-triplet estimates (Sec. 3.2, the paragraph before Eq. dft), and Eq. (dft)
+  takes the collapsed MABS to the cylindrical 3D BS by a 2D DFT over the
+  separations (mabs_dft).
 
 3D bispectrum: the delay transform along frequency is applied to the weighted
 cube, the 3D grid is split into |k| shells, each shell is inverse-FFT'd to a
@@ -214,6 +216,31 @@ def collapse_mabs(B: np.ndarray, N: np.ndarray, circular: bool = False):
                 if cnt:
                     Bbar[t, i1, i2] = acc / cnt
     return Bbar, Nnu, Ntot
+
+
+def mabs_dft(Bbar: np.ndarray, scale: float = 1.0, circular: bool = False) -> np.ndarray:
+    """Eq. (dft): 2D DFT of the collapsed MABS over the separations (n, m) channels.
+
+    out[t][a][b] = scale * sum_{n,m=-h..h} exp(-2 pi i (n a + m b) / nc) Bbar_t(n, m),
+    h = nc // 2, both ends of the range included as the equation writes them; a, b in
+    [0, nc) index k_par = 2 pi a / (r' B_bw) (a >= nc/2 are the negative frequencies).
+    scale stands for (r^2 r' dnu_c)^2.  Bbar is a collapse from collapse_mabs:
+    non-circular [nt][2nc-1][2nc-1] (separation d at d + nc - 1) or circular
+    [nt][nc][nc] (d at d mod nc, so d = -h and d = +h read the same entry).
+    Separations with no sampled triplet (NaN) contribute nothing.
+    """
+    Bbar = np.asarray(Bbar, dtype=np.float64)
+    size = Bbar.shape[1]
+    nc = size if circular else (size + 1) // 2
+    h = nc // 2
+    d = np.arange(-h, h + 1)
+    idx = d % nc if circular else d + nc - 1
+    A = Bbar[:, idx][:, :, idx]
+    A = np.where(np.isnan(A), 0.0, A)
+    a = np.arange(nc)
+    # phase (a d mod nc) / nc taken exactly in integers before the exponential
+    E = np.exp(-2j * np.pi * (np.outer(a, d) % nc) / nc)
+    return scale * np.matmul(np.matmul(E, A), E.T)
 
 
 # ---------------------------------------------------------------------------

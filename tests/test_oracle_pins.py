@@ -413,3 +413,95 @@ def test_generator_power_matches_theory_normalisation():
     ratio = est[sel] / P[sel]
     assert abs(ratio.mean() - 1.0) < 0.01
     assert np.all(est[~sel] < 1e-20)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (dft): collapsed MABS -> cylindrical 3D BS by a 2D DFT over (dnu1, dnu2)
+# ---------------------------------------------------------------------------
+def _end_sum(nc, a):
+    """sum_{n=-h..h} exp(-2 pi i n a / nc), h = nc // 2, from the geometric series: a full
+    period sums to zero, so for even nc only the extra n = +h term (-1)^a survives."""
+    if a % nc == 0:
+        return 2 * (nc // 2) + 1
+    return (-1) ** a if nc % 2 == 0 else 0
+
+
+@pytest.mark.parametrize("nc", [2, 6, 8, 9])
+def test_mabs_dft_constant_and_delta_closed_forms(nc):
+    h, size, c, scale = nc // 2, 2 * nc - 1, 1.75, 3.0
+    out = oe.mabs_dft(np.full((1, size, size), c), scale)
+    for a in range(nc):
+        for b in range(nc):
+            want = scale * c * _end_sum(nc, a) * _end_sum(nc, b)
+            assert abs(out[0, a, b] - want) <= 1e-12 * (nc + 1) ** 2
+    # a delta at separations (n0, m0) gives one plane wave; n0 != m0 catches a transposed operand
+    for n0, m0 in [(1, -1), (h, -h), (-h, 0), (h - 1 if h > 1 else 0, h)]:
+        B = np.zeros((2, size, size))
+        B[1, n0 + nc - 1, m0 + nc - 1] = 1.0
+        out = oe.mabs_dft(B, scale)
+        aa, bb = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
+        want = scale * np.exp(-2j * np.pi * (n0 * aa + m0 * bb) / nc)
+        assert np.max(np.abs(out[1] - want)) <= 1e-13 and np.max(np.abs(out[0])) == 0.0
+    # separations beyond |d| = h lie outside the sum; unsampled (NaN) separations add nothing
+    if nc >= 4:
+        B = np.zeros((1, size, size))
+        B[0, h + 1 + nc - 1, nc - 1] = 5.0
+        B[0, nc - 1, -h - 1 + nc - 1] = np.nan
+        assert np.max(np.abs(oe.mabs_dft(B))) == 0.0
+
+
+@pytest.mark.parametrize("nc", [4, 9, 12])
+def test_mabs_dft_hermitian_and_library_fft(nc):
+    rng = np.random.default_rng(nc)
+    h, size = nc // 2, 2 * nc - 1
+    B = rng.standard_normal((2, size, size))
+    out = oe.mabs_dft(B, 0.5)
+    neg = (-np.arange(nc)) % nc
+    # real input: B(-a, -b) = conj B(a, b) (the (dnu1, dnu2) -> (-, -) symmetry of the cylindrical BS)
+    assert np.max(np.abs(out[:, neg][:, :, neg] - np.conj(out))) <= 1e-12 * np.max(np.abs(out))
+    # with the end separations +-h zeroed (even nc) or always (odd nc: -h..h is one period),
+    # the sum is NumPy's 2D FFT of the window laid out by residue n mod nc
+    if nc % 2 == 0:
+        for e in (-h, h):
+            B[:, e + nc - 1, :] = 0.0
+            B[:, :, e + nc - 1] = 0.0
+    F = np.zeros((2, nc, nc))
+    for n in range(-h, h + 1):
+        for m in range(-h, h + 1):
+            F[:, n % nc, m % nc] += B[:, n + nc - 1, m + nc - 1]
+    ref = 0.5 * np.fft.fft2(F)
+    assert np.max(np.abs(oe.mabs_dft(B, 0.5) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_mabs_dft_of_circular_collapse_is_the_cylindrical_3d_sum():
+    """Periodic cube, odd nc (-h..h is one period): Eq. (dft) applied to the circular collapse
+    of the MABS equals norm * N_pix * nc * S_D^3D / N_tri, where S_D^3D sums over voxels the
+    product of complex 3D inverse transforms of the cube restricted to R_i x {a_i}, a3 = -a1-a2
+    (the cylindrical triangle the pair (a1, a2) names); N_tri is the same for every channel
+    triplet without flags."""
+    n, nc, norm = 16, 9, 0.5
+    rb = ob.make_bins(ob.RING_U, n, nc, np.array([1.0, 2.5, 4.0, 5.5]))
+    V = synth.make_cube(synth.small_workload(n, nc), 23)
+    B, N, _, _ = oe.estimate_mabs(rb, V, norm=norm)
+    Bbar, Nnu, _ = oe.collapse_mabs(B, N, circular=True)
+    out = oe.mabs_dft(Bbar, circular=True)
+    vt_full = obr.full_volume(oe.delay_transform(V), n)
+    ring_full = np.real(obr.full_plane(rb.lut.astype(np.complex128), n)).astype(np.int64)
+    npix = n * n
+    checked = 0
+    for t, (r1, r2, r3) in enumerate(rb.triangles):
+        if N[t].max() == 0:
+            continue
+        assert N[t].min() == N[t].max() and np.all(Nnu[t] == nc)
+        for a1 in range(0, nc, 2):
+            for a2 in range(nc):
+                a3 = (-a1 - a2) % nc
+                fields = []
+                for r, a in ((r1, a1), (r2, a2), (r3, a3)):
+                    mask = (ring_full == r)[None, :, :] & (np.arange(nc) == a)[:, None, None]
+                    fields.append(np.fft.ifftn(np.where(mask, vt_full, 0)))
+                rhs = norm * npix * nc * np.sum(fields[0] * fields[1] * fields[2]) / N[t, 0, 0, 0]
+                lhs = out[t, a1, a2]
+                assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs)) + 1e-15
+                checked += abs(rhs) > 0
+    assert checked > 40
