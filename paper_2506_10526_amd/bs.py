@@ -20,7 +20,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
-    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_estimate_3d",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
     L.bs_estimate_mabs.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), ctypes.POINTER(bs_mabs_sel), i32, dbl,
                                    vp, vp, vp]
     L.bs_estimate_3d.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, dbl, vp, vp, vp]
+    L.bs_mabs_dft.argtypes = [vp, i32, i32, i32, vp, dbl, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
@@ -233,6 +234,18 @@ def bs_estimate_3d(ctx: int, bins: int, vis, precision: int, B, N_tri, N_eff=Non
     w = _weights(ng, uv_mask, chan_w)
     _check(ctx, lib().bs_estimate_3d(ctx, bins, _ptr(vis), ctypes.byref(w), precision, float(norm),
                                      _ptr(B), _ptr(N_tri), _ptr(N_eff)))
+
+
+def bs_mabs_dft(ctx: int, nc: int, Bbar, out, scale: float = 1.0, circular: bool = False) -> None:
+    """Eq. (dft) on a collapsed MABS: Bbar float64 [n_tri][2nc-1][2nc-1] (or [n_tri][nc][nc] when
+    circular), out complex128 [n_tri][nc][nc], both on the device."""
+    size = nc if circular else 2 * nc - 1
+    nt = int(Bbar.shape[0])
+    if (tuple(Bbar.shape) != (nt, size, size) or tuple(out.shape) != (nt, nc, nc)
+            or not Bbar.is_contiguous() or not out.is_contiguous()):
+        raise ValueError("bs_mabs_dft: Bbar must be contiguous [n_tri][%d][%d] and out contiguous [n_tri][%d][%d]"
+                         % (size, size, nc, nc))
+    _check(ctx, lib().bs_mabs_dft(ctx, int(nc), nt, 1 if circular else 0, _ptr(Bbar), float(scale), _ptr(out)))
 
 
 def bs_set_timing(ctx: int, enable: bool) -> None:

@@ -215,3 +215,20 @@ def make_cube(w: Workload, seed: int, dtype=np.complex128) -> np.ndarray:
 def small_workload(n: int, nc: int, kind: str = "cubic", **kw) -> Workload:
     """A tiny cube for brute-force and Monte Carlo tests."""
     return Workload(f"tiny{n}x{nc}", n=n, nc=nc, kind=kind, **kw)
+
+
+def collapsed_mabs(nt: int, nc: int, seed: int, circular: bool = False, gap_frac: float = 0.01) -> np.ndarray:
+    """Seeded stand-in for an ergodically collapsed MABS over channel separations (d1, d2):
+    float64 [nt][S][S] with S = 2nc - 1 (d at d + nc - 1) or S = nc when circular (d at d mod nc).
+
+    Values are standard normal.  NaN marks separations with no channel triplet: in the
+    non-circular layout every (d1, d2) with |d2 - d1| >= nc, plus a random gap_frac of the rest
+    in both layouts (separations that flagged channels leave unsampled)."""
+    rng = np.random.default_rng(seed)
+    size = nc if circular else 2 * nc - 1
+    B = rng.standard_normal((nt, size, size))
+    if not circular:
+        d = np.arange(size) - (nc - 1)
+        B[:, np.abs(d[None, :] - d[:, None]) >= nc] = np.nan
+    B[rng.random((nt, size, size)) < gap_frac] = np.nan
+    return B
