@@ -10,9 +10,10 @@ normalisation (triangle counts depend only on the geometry and are cached after 
 first call).  The metric counts one product per valid triangle per voxel.
 
 Also reported on the same cube: the plain FP32 path of the same step, and the MABS
-contraction on MFMA for 133 ring triples x 8 nu1 rows (768 x 768 x 65536 GEMMs).
+contraction on MFMA for 133 ring triples x 8 nu1 rows (768 x 768 x 65536 GEMMs); the 2D DFT of
+Eq. (dft) on a collapsed MABS of 133 triples; Monte Carlo, batch and surrogate blocks.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mabs]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mabs] [--no-mabs-dft]
 """
 from __future__ import annotations
 
@@ -33,7 +34,8 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6}   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
+TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
+                 "mdft": (1821.5 + 629.2 + 630.1 + 1255.2) * 1e6}   # profiles/mdft_fp64_133x1535x1535_nc768.md
 
 
 def log(*a):
@@ -49,6 +51,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-mabs", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-mabs-dft", action="store_true")
     p.add_argument("--no-mc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-surrogate", action="store_true")
@@ -121,6 +124,66 @@ def cpu_baseline(w, V, edges, gpu_B, tri_all):
                    f"= {t_full:.0f} s, counts excluded as on the GPU"),
         "max_rel_err_vs_gpu_on_sample": float(np.nanmax(err)) if len(sel) else None,
         "sample_valid_triangles": n_valid,
+    }
+
+
+def mabs_dft_block(bs, ctx, w, torch, nt=133):
+    """Eq. (dft) on a collapsed MABS of the cube's shape: nt = 133 ring triples (as in the MABS
+    block), nc = 768, the non-circular collapse [133][1535][1535] in HBM (seeded standard normal
+    values, NaN where no channel triplet exists, |d2 - d1| >= nc), scaled by (r^2 r' dnu_c)^2.
+    HBM-bound: the algorithmic bytes per launch are the window read once ((nc + 1)^2 float64 per
+    triangle) and the output written once (nc^2 complex128 per triangle); the half spectra the two
+    passes exchange (nc (nc/2 + 1) complex128 per triangle, written and read once) are counted
+    apart.  The oracle's time for the same transform on two triangles is reported beside it."""
+    from oracle import estimator as oe
+    nc = w.nc
+    size = 2 * nc - 1
+    h = nc // 2
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    Bd = torch.randn((nt, size, size), dtype=torch.float64, device="cuda", generator=g)
+    d = torch.arange(size, device="cuda") - (nc - 1)
+    Bd[:, (d[None, :] - d[:, None]).abs() >= nc] = float("nan")
+    out = torch.empty((nt, nc, nc), dtype=torch.complex128, device="cuda")
+    scale = (w.r_mpc ** 2 * w.rprime * w.dnu) ** 2
+    f = lambda: bs.bs_mabs_dft(ctx, nc, Bd, out, scale=scale)
+    f()
+    torch.cuda.synchronize()
+    pn, pm, tot = [], [], []
+    for _ in range(5):
+        f()
+        tm = bs.bs_last_timing(ctx)
+        tot.append(tm[0])
+        pm.append(tm[1])
+        pn.append(tm[2])
+    t_wall = time_steps(f, 5, 0, torch)
+    ms_n, ms_m, ms = float(np.median(pn)), float(np.median(pm)), float(np.median(tot))
+    win = nt * (2 * h + 1) ** 2 * 8
+    outb = nt * nc * nc * 16
+    half = nt * nc * (nc // 2 + 1) * 16
+    alg = win + outb
+    ach = alg / ((ms_n + ms_m) * 1e-3) / 1e9
+    # the oracle on two triangles, checked against the GPU output
+    t0 = time.perf_counter()
+    errs = []
+    for t in (0, nt - 1):
+        ref = oe.mabs_dft(Bd[t:t + 1].cpu().numpy(), scale)
+        got = out[t:t + 1].cpu().numpy()
+        errs.append(float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    t_cpu = (time.perf_counter() - t0) / 2
+    return {
+        "value": nt / t_wall, "unit": "triangles/s", "ms_per_call": t_wall * 1e3, "kernels_ms": ms,
+        "pass_n_ms": ms_n, "pass_m_ms": ms_m,
+        "pass_n_GBps_moved": (win + half) / (ms_n * 1e-3) / 1e9,
+        "pass_m_GBps_moved": (half + outb) / (ms_m * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_mdft_n + k_mdft_m (Eq. dft, FP64)", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": alg, "half_spectrum_bytes_exchanged": 2 * half,
+                     "traffic": TRAFFIC_BYTES.get("mdft")},
+        "max_rel_err_vs_oracle_2_triangles": max(errs),
+        "cpu_oracle": {"value": 1.0 / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                       "sample": "2 of 133 triangles, float64 NumPy, the literal sum as two matrix products"},
+        "workload": f"{nt} triangles x collapsed MABS [{size}][{size}] (nc = {nc}) -> [{nc}][{nc}] complex128",
     }
 
 
@@ -328,6 +391,12 @@ def main():
         mabs = res
         bs.bs_free_bins(rb)
         del Bm, Nm
+    mdft = None
+    if not args.no_mabs_dft:
+        log("[bench] Eq. (dft): collapsed MABS of 133 triples -> cylindrical 3D BS")
+        mdft = mabs_dft_block(bs, ctx, w, torch)
+        log(f"[bench] mabs_dft: {mdft['ms_per_call']:.3f} ms/call (pass n {mdft['pass_n_ms']:.3f}, pass m "
+            f"{mdft['pass_m_ms']:.3f}), {mdft['roofline']['achieved']:.0f} GB/s algorithmic")
     mc = None
     if not args.no_mc:
         log("[bench] Monte Carlo: 64 flagged realizations from one graph")
@@ -370,6 +439,7 @@ def main():
         "kernel_ms": {"step_events": tim_split[0], "contraction": tim_split[1], "fields": tim_split[2]},
         "fp32": fp32,
         "mabs": mabs,
+        "mabs_dft": mdft,
         "mc": mc,
         "batch": batch,
         "surrogate": sur,

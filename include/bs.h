@@ -167,7 +167,8 @@ int bs_estimate_mabs(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs
  *   Only |n|, |m| <= h are read.  NaN (no sampled triplet, N_nu == 0) contributes zero.
  * out (device): complex128 [n_tri][nc][nc], interleaved (re, im); the caller owns both buffers.
  * Runs on the context's stream as two FP64 FFT passes; scratch: n_tri nc (nc/2 + 1) 16 bytes of
- * context workspace.  bs_last_timing then reports [0] the call, [1] the column pass, [2] the row pass.
+ * context workspace.  bs_last_timing then reports [0] the call, [1] the pass along m (which writes
+ * the output), [2] the pass along n (which reads Bbar).
  * Errors: BS_EINVAL (nc not 2^a 3^b in [2, 4096], n_tri outside [0, 65535], NULL pointers with
  * n_tri > 0), BS_ENOMEM, BS_EHIP.  n_tri == 0 returns BS_OK without touching the GPU buffers. */
 int bs_mabs_dft(bs_ctx* ctx, int32_t nc, int32_t n_tri, int32_t circular, const double* Bbar, double scale,

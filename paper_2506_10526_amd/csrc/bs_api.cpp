@@ -371,52 +371,52 @@ extern "C" int bs_mabs_dft(bs_ctx* c, int32_t nc, int32_t n_tri, int32_t circula
   a.circ = circular ? 1 : 0;
   a.nt = n_tri;
   a.scale = scale;
-  a.X = ctx_ws(c, "mdft_half", (size_t)n_tri * nc * a.H * 16);
-  if (!a.X) return ctx_fail(c, BS_ENOMEM, "bs_mabs_dft workspace");
   constexpr size_t kLdsMax = 160 * 1024;
   auto knob = [](const char* name, int def) {
     const char* e = getenv(name);
     return e ? atoi(e) : def;
   };
-  // Row pass: folded row pairs per block (at most BS_MDFT_ROWS, default 2) whose in-place FFT fits
-  // 4 butterflies per thread.  Column pass: columns per block (at most BS_MDFT_COLS, default 8),
-  // lines padded to a stride of 8 mod 16 elements so that the transposing load spreads over the banks.
-  // A block of 256 threads is tried first where asked for; 512 threads fit every length up to 4096.
-  // Each pass takes the fewest butterflies per thread (2 or 4) that its FFT fits.
-  const int rwant = std::max(1, std::min(4, knob("BS_MDFT_ROWS", 2)));
-  const int cwant = std::max(1, std::min(8, knob("BS_MDFT_COLS", 8)));
-  const int ld = nc + (24 - nc % 16) % 16;
-  int rnl = 0, cnl = 0, rthreads = 0, cthreads = 0, rbm = 0, cbm = 0;
-  for (int th : {knob("BS_MDFT_ROWS_THREADS", 256) > 256 ? 512 : 256, 512})
-    for (int nl : {4, 2, 1})
-      for (int bm : {2, 4})
-        if (!rnl && nl <= rwant && fft_ip_fits(a.plan, nl, th, bm) && (size_t)(nl + 1) * nc * 16 <= kLdsMax) {
-          rnl = nl;
-          rthreads = th;
-          rbm = bm;
-        }
-  for (int th : {knob("BS_MDFT_COLS_THREADS", 512) > 256 ? 512 : 256, 512})
+  // Pass n: column pairs per group (at most BS_MDFT_NCOLS, default 4), line stride 4 mod 16
+  // elements so that the transposing store spreads over the LDS banks.  Pass m: rows per
+  // group (at most BS_MDFT_MROWS, default 2).  A block of 256 threads is tried first where asked
+  // for (512 threads fit every length up to 4096); each pass takes the fewest butterflies per
+  // thread (2 or 4) that its in-place FFT fits.
+  const int nwant = std::max(1, std::min(8, knob("BS_MDFT_NCOLS", 4)));
+  const int mwant = std::max(1, std::min(4, knob("BS_MDFT_MROWS", 2)));
+  const int ld = nc + (20 - nc % 16) % 16;
+  int nnl = 0, mnl = 0, nthreads = 0, mthreads = 0, nbm = 0, mbm = 0;
+  for (int th : {knob("BS_MDFT_NCOLS_THREADS", 512) > 256 ? 512 : 256, 512})
     for (int nl : {8, 4, 2, 1})
       for (int bm : {2, 4})
-        if (!cnl && nl <= cwant && fft_ip_fits(a.plan, nl, th, bm) && (size_t)(nc + nl * ld) * 16 <= kLdsMax) {
-          cnl = nl;
-          cthreads = th;
-          cbm = bm;
+        if (!nnl && nl <= nwant && fft_ip_fits(a.plan, nl, th, bm) && (size_t)(nc + nl * ld) * 16 <= kLdsMax) {
+          nnl = nl;
+          nthreads = th;
+          nbm = bm;
         }
-  a.grid = std::max(1, knob("BS_MDFT_GRID", 2048));
-  if (!rnl || !cnl) return ctx_fail(c, BS_EUNSUPPORTED, "bs_mabs_dft: no in-place FFT layout for this nc");
+  for (int th : {knob("BS_MDFT_MROWS_THREADS", 256) > 256 ? 512 : 256, 512})
+    for (int nl : {4, 2, 1})
+      for (int bm : {2, 4})
+        if (!mnl && nl <= mwant && fft_ip_fits(a.plan, nl, th, bm) && (size_t)(nl + 1) * nc * 16 <= kLdsMax) {
+          mnl = nl;
+          mthreads = th;
+          mbm = bm;
+        }
+  if (!nnl || !mnl) return ctx_fail(c, BS_EUNSUPPORTED, "bs_mabs_dft: no in-place FFT layout for this nc");
+  a.grid = std::max(1, knob("BS_MDFT_GRID", 4096));
+  a.X = ctx_ws(c, "mdft_half", (size_t)n_tri * nc * a.H * 16);
+  if (!a.X) return ctx_fail(c, BS_ENOMEM, "bs_mabs_dft workspace");
   if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
-  a.nl = rnl;
-  a.threads = rthreads;
-  a.bm = rbm;
-  launch_mdft_rows(a, (size_t)(rnl + 1) * nc * 16, c->stream);
-  if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
-  a.nl = cnl;
-  a.lgnl = cnl == 8 ? 3 : cnl == 4 ? 2 : cnl == 2 ? 1 : 0;
+  a.nl = nnl;
+  a.lgnl = nnl == 8 ? 3 : nnl == 4 ? 2 : nnl == 2 ? 1 : 0;
   a.ld = ld;
-  a.threads = cthreads;
-  a.bm = cbm;
-  launch_mdft_cols(a, (size_t)(nc + cnl * ld) * 16, c->stream);
+  a.threads = nthreads;
+  a.bm = nbm;
+  launch_mdft_n(a, (size_t)(nc + nnl * ld) * 16, c->stream);
+  if (c->timing) { (void)hipEventRecord(c->ev[5], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  a.nl = mnl;
+  a.threads = mthreads;
+  a.bm = mbm;
+  launch_mdft_m(a, (size_t)(mnl + 1) * nc * 16, c->stream);
   if (c->timing) {
     (void)hipEventRecord(c->ev[3], c->stream);
     (void)hipEventRecord(c->ev[1], c->stream);

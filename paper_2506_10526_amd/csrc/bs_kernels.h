@@ -227,22 +227,22 @@ void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s);
 void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s);
 
 // ---- Eq. (dft): collapsed MABS -> cylindrical 3D BS ----
-// Row pass: separations folded by residue (n mod L, m mod L), unsampled (NaN) entries as zero,
-// two folded rows packed into one complex FFT along m and split into their half spectra.
-// Column pass: FFT along n of CB columns at a time, scaled, written with the Hermitian mirror.
+// Pass n: window folded by residue (n mod L, m mod L), unsampled (NaN) entries as zero, two real
+// columns packed into one complex FFT along n and split into their half spectra a < H.
+// Pass m: FFT along m of NL half-spectrum rows, scaled, written with the Hermitian mirror rows.
 struct MdftArgs {
   const double* B;   // [nt][S][S] collapsed MABS
-  void* X;           // workspace, complex double [nt][L][H]
+  void* X;           // workspace, complex double [nt][H][L]
   void* out;         // complex double [nt][L][L]
   const void* tw;    // complex double exp(-2 pi i m / L), m < L
   FftPlan plan;
   int L, H, h, S, circ, nt;
-  int nl, lgnl;      // rows: folded row pairs per block; columns: columns per block (2^lgnl)
-  int ld;            // LDS line stride of the column pass
+  int nl, lgnl;      // pass n: column pairs per group (2^lgnl); pass m: rows per group
+  int ld;            // LDS line stride of pass n
   int threads;       // block size, at most 512
   int bm;            // butterflies per thread of the in-place FFT (2 or 4)
   int grid;          // most blocks launched; each loops over (triangle, line block) groups
   double scale;
 };
-void launch_mdft_rows(const MdftArgs& a, size_t lds, hipStream_t s);
-void launch_mdft_cols(const MdftArgs& a, size_t lds, hipStream_t s);
+void launch_mdft_n(const MdftArgs& a, size_t lds, hipStream_t s);
+void launch_mdft_m(const MdftArgs& a, size_t lds, hipStream_t s);

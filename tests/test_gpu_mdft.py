@@ -64,16 +64,18 @@ def test_mdft_of_the_oracle_collapse_of_a_cube(ctx):
         check(got, oe.mabs_dft(Bbar, 1.5, circular=circular), f"cube circ={circular}")
 
 
-@pytest.mark.parametrize("rows,cols,rth,cth", [(1, 1, 256, 256), (4, 2, 512, 512), (2, 4, 256, 512)])
-def test_mdft_block_shapes(ctx, monkeypatch, rows, cols, rth, cth):
-    """Rows and columns per block and block sizes other than the defaults give the same result."""
-    monkeypatch.setenv("BS_MDFT_ROWS", str(rows))
-    monkeypatch.setenv("BS_MDFT_COLS", str(cols))
-    monkeypatch.setenv("BS_MDFT_ROWS_THREADS", str(rth))
-    monkeypatch.setenv("BS_MDFT_COLS_THREADS", str(cth))
-    nc = 72
-    Bbar = synth.collapsed_mabs(3, nc, 7)
-    check(run(ctx, Bbar, nc), oe.mabs_dft(Bbar), f"rows={rows} cols={cols}")
+@pytest.mark.parametrize("ncols,mrows,nth,mth", [(1, 1, 256, 256), (2, 4, 512, 512), (4, 1, 256, 512),
+                                                  (8, 2, 256, 256)])
+def test_mdft_block_shapes(ctx, monkeypatch, ncols, mrows, nth, mth):
+    """Lines per group and block sizes other than the defaults give the same result."""
+    monkeypatch.setenv("BS_MDFT_NCOLS", str(ncols))
+    monkeypatch.setenv("BS_MDFT_MROWS", str(mrows))
+    monkeypatch.setenv("BS_MDFT_NCOLS_THREADS", str(nth))
+    monkeypatch.setenv("BS_MDFT_MROWS_THREADS", str(mth))
+    monkeypatch.setenv("BS_MDFT_GRID", "37")
+    for nc in (72, 81):
+        Bbar = synth.collapsed_mabs(3, nc, 7)
+        check(run(ctx, Bbar, nc), oe.mabs_dft(Bbar), f"nc={nc} ncols={ncols} mrows={mrows}")
 
 
 def test_mdft_full_size_sampled(ctx):
