@@ -221,19 +221,19 @@ def collapse_mabs(B: np.ndarray, N: np.ndarray, circular: bool = False):
 def mabs_dft(Bbar: np.ndarray, scale: float = 1.0, circular: bool = False) -> np.ndarray:
     """Eq. (dft): 2D DFT of the collapsed MABS over the separations (n, m) channels.
 
-    out[t][a][b] = scale * sum_{n,m=-h..h} exp(-2 pi i (n a + m b) / nc) Bbar_t(n, m),
-    h = nc // 2, both ends of the range included as the equation writes them; a, b in
-    [0, nc) index k_par = 2 pi a / (r' B_bw) (a >= nc/2 are the negative frequencies).
-    scale stands for (r^2 r' dnu_c)^2.  Bbar is a collapse from collapse_mabs:
-    non-circular [nt][2nc-1][2nc-1] (separation d at d + nc - 1) or circular
-    [nt][nc][nc] (d at d mod nc, so d = -h and d = +h read the same entry).
+    out[t][a][b] = scale * sum_{n,m} exp(-2 pi i (n a + m b) / nc) Bbar_t(n, m), with n and m
+    over the half-open range [-nc/2, nc/2), i.e. -h .. nc - 1 - h for h = nc // 2: one period,
+    each separation once (the printed limits would count the end separation +-nc/2 twice).
+    a, b in [0, nc) index k_par = 2 pi a / (r' B_bw) (a >= nc/2 are the negative frequencies).
+    scale stands for (r^2 r' dnu_c)^2.  Bbar is a collapse from collapse_mabs: non-circular
+    [nt][2nc-1][2nc-1] (separation d at d + nc - 1) or circular [nt][nc][nc] (d at d mod nc).
     Separations with no sampled triplet (NaN) contribute nothing.
     """
     Bbar = np.asarray(Bbar, dtype=np.float64)
     size = Bbar.shape[1]
     nc = size if circular else (size + 1) // 2
     h = nc // 2
-    d = np.arange(-h, h + 1)
+    d = np.arange(-h, nc - h)
     idx = d % nc if circular else d + nc - 1
     A = Bbar[:, idx][:, :, idx]
     A = np.where(np.isnan(A), 0.0, A)

@@ -418,36 +418,31 @@ def test_generator_power_matches_theory_normalisation():
 # ---------------------------------------------------------------------------
 # Eq. (dft): collapsed MABS -> cylindrical 3D BS by a 2D DFT over (dnu1, dnu2)
 # ---------------------------------------------------------------------------
-def _end_sum(nc, a):
-    """sum_{n=-h..h} exp(-2 pi i n a / nc), h = nc // 2, from the geometric series: a full
-    period sums to zero, so for even nc only the extra n = +h term (-1)^a survives."""
-    if a % nc == 0:
-        return 2 * (nc // 2) + 1
-    return (-1) ** a if nc % 2 == 0 else 0
-
-
 @pytest.mark.parametrize("nc", [2, 6, 8, 9])
 def test_mabs_dft_constant_and_delta_closed_forms(nc):
     h, size, c, scale = nc // 2, 2 * nc - 1, 1.75, 3.0
+    # a constant over one full period of separations: nc^2 c at a = b = 0, zero elsewhere
+    # (the geometric series of a non-zero frequency over a period vanishes)
     out = oe.mabs_dft(np.full((1, size, size), c), scale)
-    for a in range(nc):
-        for b in range(nc):
-            want = scale * c * _end_sum(nc, a) * _end_sum(nc, b)
-            assert abs(out[0, a, b] - want) <= 1e-12 * (nc + 1) ** 2
+    want = np.zeros((nc, nc), dtype=complex)
+    want[0, 0] = scale * c * nc * nc
+    assert np.max(np.abs(out[0] - want)) <= 1e-12 * nc * nc
     # a delta at separations (n0, m0) gives one plane wave; n0 != m0 catches a transposed operand
-    for n0, m0 in [(1, -1), (h, -h), (-h, 0), (h - 1 if h > 1 else 0, h)]:
+    for n0, m0 in [(1, -1), (-h, 0), (nc - 1 - h, -h), (0, nc - 1 - h)]:
+        if not (-h <= n0 < nc - h and -h <= m0 < nc - h):
+            continue
         B = np.zeros((2, size, size))
         B[1, n0 + nc - 1, m0 + nc - 1] = 1.0
         out = oe.mabs_dft(B, scale)
         aa, bb = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
         want = scale * np.exp(-2j * np.pi * (n0 * aa + m0 * bb) / nc)
         assert np.max(np.abs(out[1] - want)) <= 1e-13 and np.max(np.abs(out[0])) == 0.0
-    # separations beyond |d| = h lie outside the sum; unsampled (NaN) separations add nothing
-    if nc >= 4:
-        B = np.zeros((1, size, size))
-        B[0, h + 1 + nc - 1, nc - 1] = 5.0
-        B[0, nc - 1, -h - 1 + nc - 1] = np.nan
-        assert np.max(np.abs(oe.mabs_dft(B))) == 0.0
+    # separations outside [-nc/2, nc/2) are not summed (for even nc that includes +nc/2);
+    # unsampled (NaN) separations add nothing
+    B = np.zeros((1, size, size))
+    B[0, nc - h + nc - 1, nc - 1] = 5.0
+    B[0, nc - 1, -1 + nc - 1] = np.nan      # separation (0, -1), inside the range
+    assert np.max(np.abs(oe.mabs_dft(B))) == 0.0
 
 
 @pytest.mark.parametrize("nc", [4, 9, 12])
@@ -459,27 +454,22 @@ def test_mabs_dft_hermitian_and_library_fft(nc):
     neg = (-np.arange(nc)) % nc
     # real input: B(-a, -b) = conj B(a, b) (the (dnu1, dnu2) -> (-, -) symmetry of the cylindrical BS)
     assert np.max(np.abs(out[:, neg][:, :, neg] - np.conj(out))) <= 1e-12 * np.max(np.abs(out))
-    # with the end separations +-h zeroed (even nc) or always (odd nc: -h..h is one period),
-    # the sum is NumPy's 2D FFT of the window laid out by residue n mod nc
-    if nc % 2 == 0:
-        for e in (-h, h):
-            B[:, e + nc - 1, :] = 0.0
-            B[:, :, e + nc - 1] = 0.0
+    # one period of separations laid out by residue n mod nc: NumPy's 2D FFT
     F = np.zeros((2, nc, nc))
-    for n in range(-h, h + 1):
-        for m in range(-h, h + 1):
-            F[:, n % nc, m % nc] += B[:, n + nc - 1, m + nc - 1]
+    for n in range(-h, nc - h):
+        for m in range(-h, nc - h):
+            F[:, n % nc, m % nc] = B[:, n + nc - 1, m + nc - 1]
     ref = 0.5 * np.fft.fft2(F)
-    assert np.max(np.abs(oe.mabs_dft(B, 0.5) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-def test_mabs_dft_of_circular_collapse_is_the_cylindrical_3d_sum():
-    """Periodic cube, odd nc (-h..h is one period): Eq. (dft) applied to the circular collapse
-    of the MABS equals norm * N_pix * nc * S_D^3D / N_tri, where S_D^3D sums over voxels the
-    product of complex 3D inverse transforms of the cube restricted to R_i x {a_i}, a3 = -a1-a2
-    (the cylindrical triangle the pair (a1, a2) names); N_tri is the same for every channel
-    triplet without flags."""
-    n, nc, norm = 16, 9, 0.5
+@pytest.mark.parametrize("nc", [8, 9])
+def test_mabs_dft_of_circular_collapse_is_the_cylindrical_3d_sum(nc):
+    """Periodic cube: Eq. (dft) applied to the circular collapse of the MABS equals
+    norm * N_pix * nc * S_D^3D / N_tri, where S_D^3D sums over voxels the product of complex 3D
+    inverse transforms of the cube restricted to R_i x {a_i}, a3 = -a1-a2 (the cylindrical
+    triangle the pair (a1, a2) names); N_tri is the same for every channel triplet without flags."""
+    n, norm = 16, 0.5
     rb = ob.make_bins(ob.RING_U, n, nc, np.array([1.0, 2.5, 4.0, 5.5]))
     V = synth.make_cube(synth.small_workload(n, nc), 23)
     B, N, _, _ = oe.estimate_mabs(rb, V, norm=norm)
