@@ -35,7 +35,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
 TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
-                 "mdft": (1821.5 + 629.2 + 630.1 + 1255.2) * 1e6}   # profiles/mdft_fp64_133x1535x1535_nc768.md
+                 "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6}   # profiles/mdft_fp64_133x1535x1535_nc768.md
 
 
 def log(*a):
@@ -131,14 +131,14 @@ def mabs_dft_block(bs, ctx, w, torch, nt=133):
     """Eq. (dft) on a collapsed MABS of the cube's shape: nt = 133 ring triples (as in the MABS
     block), nc = 768, the non-circular collapse [133][1535][1535] in HBM (seeded standard normal
     values, NaN where no channel triplet exists, |d2 - d1| >= nc), scaled by (r^2 r' dnu_c)^2.
-    HBM-bound: the algorithmic bytes per launch are the window read once ((nc + 1)^2 float64 per
-    triangle) and the output written once (nc^2 complex128 per triangle); the half spectra the two
+    HBM-bound: the algorithmic bytes per launch are the window read once (nc^2 float64 per
+    triangle: one period of separations) and the output written once (nc^2 complex128 per
+    triangle); the half spectra the two
     passes exchange (nc (nc/2 + 1) complex128 per triangle, written and read once) are counted
     apart.  The oracle's time for the same transform on two triangles is reported beside it."""
     from oracle import estimator as oe
     nc = w.nc
     size = 2 * nc - 1
-    h = nc // 2
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
     Bd = torch.randn((nt, size, size), dtype=torch.float64, device="cuda", generator=g)
@@ -158,7 +158,7 @@ def mabs_dft_block(bs, ctx, w, torch, nt=133):
         pn.append(tm[2])
     t_wall = time_steps(f, 5, 0, torch)
     ms_n, ms_m, ms = float(np.median(pn)), float(np.median(pm)), float(np.median(tot))
-    win = nt * (2 * h + 1) ** 2 * 8
+    win = nt * nc * nc * 8
     outb = nt * nc * nc * 16
     half = nt * nc * (nc // 2 + 1) * 16
     alg = win + outb

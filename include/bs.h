@@ -156,15 +156,16 @@ int bs_estimate_mabs(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs
                      double* B, int64_t* N_tri, int32_t* N_nu);
 
 /* ---- collapsed MABS -> cylindrical 3D bispectrum (Sec. 3.2, Eq. dft) ----
- * out[t][a][b] = scale * sum_{n,m = -h..h} exp(-2 pi i (n a + m b) / nc) Bbar_t(n, m),  h = nc / 2,
- * for a, b in [0, nc): a 2D DFT of the ergodically collapsed MABS over the channel separations
- * (dnu1, dnu2) = (n dnu_c, m dnu_c), both ends of the range included as the equation writes them.
+ * out[t][a][b] = scale * sum_{n,m} exp(-2 pi i (n a + m b) / nc) Bbar_t(n, m) for a, b in [0, nc):
+ * a 2D DFT of the ergodically collapsed MABS over the channel separations (dnu1, dnu2) =
+ * (n dnu_c, m dnu_c), with n and m over the half-open range [-nc/2, nc/2), i.e. -h .. nc-1-h for
+ * h = nc / 2 (one period, each separation once; the printed limits would count +-nc/2 twice).
  * a and b index k_par = 2 pi a / (r' B_bw) (a >= nc/2: the negative frequencies a - nc);
  * scale is the caller's (r^2 r' dnu_c)^2 (1 for grid units).
  * Bbar (device float64): the output of bs_estimate_mabs with collapse == 1, [n_tri][2nc-1][2nc-1]
  *   with separation d at index d + nc - 1 (circular == 0), or with collapse == 2, [n_tri][nc][nc]
- *   with d at d mod nc (circular == 1; then d = -h and d = +h read the same entry for even nc).
- *   Only |n|, |m| <= h are read.  NaN (no sampled triplet, N_nu == 0) contributes zero.
+ *   with d at d mod nc (circular == 1).  Only separations in the range are read.  NaN (no sampled
+ *   triplet, N_nu == 0) contributes zero.
  * out (device): complex128 [n_tri][nc][nc], interleaved (re, im); the caller owns both buffers.
  * Runs on the context's stream as two FP64 FFT passes; scratch: n_tri nc (nc/2 + 1) 16 bytes of
  * context workspace.  bs_last_timing then reports [0] the call, [1] the pass along m (which writes

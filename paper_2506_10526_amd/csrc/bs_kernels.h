@@ -227,8 +227,9 @@ void launch_fin3(const Fin3Args& a, double* reduced, hipStream_t s);
 void launch_fused3(const Fused3Args& a, int mode, int nblocks, size_t lds, hipStream_t s);
 
 // ---- Eq. (dft): collapsed MABS -> cylindrical 3D BS ----
-// Pass n: window folded by residue (n mod L, m mod L), unsampled (NaN) entries as zero, two real
-// columns packed into one complex FFT along n and split into their half spectra a < H.
+// Pass n: window of separations [-L/2, L/2)^2 laid out by residue (n mod L, m mod L), unsampled
+// (NaN) entries as zero, two real columns packed into one complex FFT along n and split into their
+// half spectra a < H.
 // Pass m: FFT along m of NL half-spectrum rows, scaled, written with the Hermitian mirror rows.
 struct MdftArgs {
   const double* B;   // [nt][S][S] collapsed MABS

@@ -1,10 +1,10 @@
 // Eq. (dft): the 2D DFT that takes the ergodically collapsed MABS over the channel separations
 // (dnu1, dnu2) = (n, m) channels to the cylindrical 3D bispectrum at (k_par1 a, k_par2 b).
-// The sum runs over n, m in [-h, h], h = L / 2, both ends included; it is a length-L DFT of the
-// window folded by residue (for even L the two ends n = +-h share a residue), so each axis is one
-// FP64 LDS FFT.  The input is real, hence the output is Hermitian: the pass along n keeps the half
-// spectrum a < H = L/2 + 1 and the pass along m writes row L - a as the mirror of row a, so that
-// the output leaves in whole contiguous rows.
+// The sum runs over n, m in the half-open range [-L/2, L/2) (one period: the printed limits
+// would count the end separation twice), i.e. a length-L DFT of the window laid out by residue,
+// so each axis is one FP64 LDS FFT.  The input is real, hence the output is Hermitian: the pass
+// along n keeps the half spectrum a < H = L/2 + 1 and the pass along m writes row L - a as the
+// mirror of row a, so that the output leaves in whole contiguous rows.
 #include <hip/hip_runtime.h>
 
 #include "bs_kernels.h"
@@ -20,28 +20,19 @@ __device__ __forceinline__ int sep_index(const MdftArgs& a, int d) { return a.ci
 
 __device__ __forceinline__ double nan0(double v) { return v == v ? v : 0.0; }
 
-// Folded window entry at residues (r, c): the separations n = r or r - L and m = c or c - L that lie
-// in [-h, h].  Every residue has one such separation; for even L the residue h has two (n = +-h).
-__device__ __forceinline__ double fold_at(const MdftArgs& a, const double* __restrict__ Bt, int r, int c) {
-  const int L = a.L, h = a.h;
-  const long long S = a.S;
-  const int rm = sep_index(a, r <= h ? r : r - L), cm = sep_index(a, c <= h ? c : c - L);
-  double s = nan0(Bt[rm * S + cm]);
-  const bool er = (L & 1) == 0 && r == h, ec = (L & 1) == 0 && c == h;
-  if (er | ec) {   // the second end of the range: rows / columns n = -h
-    const int x = sep_index(a, -h);
-    if (er) s += nan0(Bt[x * S + cm]);
-    if (ec) s += nan0(Bt[rm * S + x]);
-    if (er && ec) s += nan0(Bt[x * S + x]);
-  }
-  return s;
+// Window entry at residues (r, c): separations n = r and m = c below L - h, else r - L and c - L,
+// so that n, m run over [-h, L - 1 - h], one period with each separation once.
+__device__ __forceinline__ double window_at(const MdftArgs& a, const double* __restrict__ Bt, int r, int c) {
+  const int lim = a.L - 1 - a.h;
+  const int rm = sep_index(a, r <= lim ? r : r - a.L), cm = sep_index(a, c <= lim ? c : c - a.L);
+  return nan0(Bt[(long long)rm * a.S + cm]);
 }
 
 // Both passes loop over work groups (triangle, block of lines) so that each block copies the
 // twiddle table into LDS once.  Blocks take groups in a strided order: the groups in flight at any
 // time are neighbours, which keeps the HBM accesses of the whole grid on a narrow band of pages.
 //
-// Pass n: W = 2 CB folded window columns c0 .. c0 + W - 1 per group, columns 2q and 2q + 1 packed
+// Pass n: W = 2 CB window columns (residues) c0 .. c0 + W - 1 per group, columns 2q and 2q + 1 packed
 // into complex line q (z = x0 + i x1), transformed along n; the half spectra a < H of both columns
 // go to Y[t][a][c] (runs of W contiguous entries per a).
 template <int BM>
@@ -67,7 +58,7 @@ __global__ __launch_bounds__(MDFT_THREADS) void k_mdft_n(MdftArgs a) {
       for (int u = 0; u < MDFT_NB; ++u) {
         const int i = base + u * blockDim.x;
         const int c = c0 + (i & (W - 1));
-        v[u] = i < total && c < L ? fold_at(a, Bt, i >> lg, c) : 0.0;
+        v[u] = i < total && c < L ? window_at(a, Bt, i >> lg, c) : 0.0;
       }
     };
     auto store = [&](int base, const double* v) {
