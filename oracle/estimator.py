@@ -243,6 +243,67 @@ def mabs_dft(Bbar: np.ndarray, scale: float = 1.0, circular: bool = False) -> np
     return scale * np.matmul(np.matmul(E, A), E.T)
 
 
+# Shape bins of the monopole: 5 linear bins over [0.5, 1] in mu and in t (Sec. 5)
+SHAPE_EDGES = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+
+
+def triangle_shape(kperp: np.ndarray, kpar1: np.ndarray, kpar2: np.ndarray):
+    """Size and shape (k1, mu, t) of cylindrical triangles (Eq. shape).
+
+    Sides k_i = sqrt(kperp_i^2 + kpar_i^2) with kpar3 = -(kpar1 + kpar2) (the three wave vectors
+    close), relabelled so that k1 >= k2 >= k3; t = k2 / k1 and mu = -k1.k2 / (k1 k2) where closure
+    gives k1.k2 = (k3^2 - k1^2 - k2^2) / 2, i.e. mu = (k1^2 + k2^2 - k3^2) / (2 k1 k2).  mu and t
+    are clamped to [0.5, 1] (their range for a closed triangle; ring-averaged kperp need not close
+    exactly).  kperp: [..., 3]; kpar1, kpar2 broadcast against kperp[..., 0].
+    """
+    kpar3 = -(kpar1 + kpar2)
+    s = np.stack([kperp[..., 0] * kperp[..., 0] + kpar1 * kpar1,
+                  kperp[..., 1] * kperp[..., 1] + kpar2 * kpar2,
+                  kperp[..., 2] * kperp[..., 2] + kpar3 * kpar3], axis=-1)
+    s = -np.sort(-s, axis=-1)
+    k1, k2 = np.sqrt(s[..., 0]), np.sqrt(s[..., 1])
+    mu = ((s[..., 0] + s[..., 1]) - s[..., 2]) / (2.0 * (k1 * k2))
+    t = k2 / k1
+    return k1, np.clip(mu, 0.5, 1.0), np.clip(t, 0.5, 1.0)
+
+
+def shape_bin(x: np.ndarray) -> np.ndarray:
+    """Bin of mu or t in [0.5, 1]: half-open [e_j, e_j+1), the last bin closed at 1."""
+    return np.minimum(np.searchsorted(np.asarray(SHAPE_EDGES), x, side="right") - 1, 4)
+
+
+def bs_monopole(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edges: np.ndarray):
+    """Monopole B(k1, mu, t) of cylindrical 3D BS estimates (Sec. 2.2 Eq. shape, Sec. 5).
+
+    Bcyl: [nt][nc][nc] complex, the output of Eq. (dft) for nt ring triples, index a of the
+    first separation and b of the second (k_par = kpar_unit * a', a' = a for 2a < nc, else a - nc);
+    kperp: [nt][3] the k_perp of the three rings.  Without redshift-space distortion the BS does
+    not depend on the orientation, so the monopole of a (k1, mu, t) bin is the mean of Re B over
+    every cylindrical cell whose triangle falls in it: k1 bins half-open on k1_edges (cells
+    outside are dropped), 5 x 5 shape bins (shape_bin).  Returns (mean [nk][5][5], NaN where
+    empty, and the cell count [nk][5][5]).
+    """
+    Bcyl = np.asarray(Bcyl)
+    nt, nc = Bcyl.shape[0], Bcyl.shape[1]
+    k1_edges = np.asarray(k1_edges, dtype=np.float64)
+    nk = len(k1_edges) - 1
+    a = np.arange(nc)
+    kp = kpar_unit * np.where(2 * a < nc, a, a - nc).astype(np.float64)
+    sums = np.zeros(nk * 25)
+    counts = np.zeros(nk * 25, dtype=np.int64)
+    for t in range(nt):
+        kpt = np.broadcast_to(np.asarray(kperp[t], dtype=np.float64), (nc, nc, 3))
+        k1, mu, tt = triangle_shape(kpt, kp[:, None], kp[None, :])
+        j = np.searchsorted(k1_edges, k1, side="right") - 1
+        ok = (j >= 0) & (j < nk)
+        idx = (j * 25 + shape_bin(mu) * 5 + shape_bin(tt))[ok]
+        sums += np.bincount(idx, weights=np.real(Bcyl[t])[ok], minlength=nk * 25)
+        counts += np.bincount(idx, minlength=nk * 25)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = np.where(counts > 0, sums / np.maximum(counts, 1), np.nan)
+    return mean.reshape(nk, 5, 5), counts.reshape(nk, 5, 5)
+
+
 # ---------------------------------------------------------------------------
 # 3D bispectrum
 # ---------------------------------------------------------------------------

@@ -495,3 +495,75 @@ def test_mabs_dft_of_circular_collapse_is_the_cylindrical_3d_sum(nc):
                 assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs)) + 1e-15
                 checked += abs(rhs) > 0
     assert checked > 40
+
+
+# ---------------------------------------------------------------------------
+# monopole B(k1, mu, t): triangle shape (Eq. shape) and binning (Sec. 5)
+# ---------------------------------------------------------------------------
+def _explicit_shape(v1, v2, kp1, kp2):
+    """mu and t from explicit 3D wave vectors and the dot product, as Eq. shape defines them."""
+    vs = [np.array([v1[0], v1[1], kp1]), np.array([v2[0], v2[1], kp2]), np.array([-v1[0] - v2[0], -v1[1] - v2[1], -kp1 - kp2])]
+    vs.sort(key=lambda v: -np.linalg.norm(v))
+    k1, k2 = np.linalg.norm(vs[0]), np.linalg.norm(vs[1])
+    return k1, -np.dot(vs[0], vs[1]) / (k1 * k2), k2 / k1
+
+
+def test_triangle_shape_matches_explicit_vectors():
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        v1, v2 = rng.normal(size=2), rng.normal(size=2)
+        kp1, kp2 = rng.normal(size=2) * rng.choice([0.0, 0.3, 2.0])
+        kperp = np.array([np.hypot(*v1), np.hypot(*v2), np.hypot(*(v1 + v2))])
+        k1, mu, t = oe.triangle_shape(kperp[None], np.array([kp1]), np.array([kp2]))
+        k1e, mue, te = _explicit_shape(v1, v2, kp1, kp2)
+        assert abs(k1[0] - k1e) <= 1e-12 * k1e and abs(t[0] - te) <= 1e-12
+        assert abs(mu[0] - min(max(mue, 0.5), 1.0)) <= 1e-9
+        # every closed triangle with k1 >= k2 >= k3 lies in 0.5 <= mu, t <= 1 with 2 mu t >= 1
+        assert 0.5 - 1e-12 <= mue <= 1 + 1e-12 and 0.5 - 1e-12 <= te <= 1 and 2 * mue * te >= 1 - 1e-9
+
+
+def test_triangle_shape_special_triangles():
+    # equilateral (three equal rings, k_par = 0): mu = 1/2, t = 1 -> shape bins (0, 4)
+    k1, mu, t = oe.triangle_shape(np.array([[0.1, 0.1, 0.1]]), np.array([0.0]), np.array([0.0]))
+    assert abs(mu[0] - 0.5) <= 1e-15 and t[0] == 1.0
+    assert oe.shape_bin(mu)[0] == 0 and oe.shape_bin(t)[0] == 4
+    # squeezed: k3 -> 0 with k1 = k2 gives mu -> 1, t = 1; stretched: k2 = k3 = k1 / 2 gives mu = 1, t = 1/2
+    k1, mu, t = oe.triangle_shape(np.array([[1.0, 1.0, 1e-4]]), np.array([0.0]), np.array([0.0]))
+    assert mu[0] > 0.999999 and t[0] == 1.0
+    k1, mu, t = oe.triangle_shape(np.array([[1.0, 0.5, 0.5]]), np.array([0.0]), np.array([0.0]))
+    assert abs(mu[0] - 1.0) <= 1e-15 and t[0] == 0.5 and oe.shape_bin(t)[0] == 0
+    # isosceles with a line-of-sight component: rings (a, a, c) with k_par1 = -k_par2 swaps nothing
+    k1, mu, t = oe.triangle_shape(np.array([[0.3, 0.3, 0.2]]), np.array([0.4]), np.array([-0.4]))
+    assert t[0] == 1.0 and abs(k1[0] - 0.5) <= 1e-15
+
+
+def test_bs_monopole_brute_force_and_constant():
+    """Cell by cell with explicit vectors on a tiny cylindrical BS; a constant BS has that
+    constant as its monopole in every filled bin."""
+    rng = np.random.default_rng(9)
+    nt, nc, unit = 3, 6, 0.05
+    vec = [(rng.normal(size=2) * 0.2, rng.normal(size=2) * 0.2) for _ in range(nt)]
+    kperp = np.array([[np.hypot(*v1), np.hypot(*v2), np.hypot(*(v1 + v2))] for v1, v2 in vec])
+    B = rng.normal(size=(nt, nc, nc)) + 1j * rng.normal(size=(nt, nc, nc))
+    edges = np.geomspace(0.05, 0.6, 5)
+    mean, cnt = oe.bs_monopole(B, kperp, unit, edges)
+    sums = np.zeros((4, 5, 5))
+    cref = np.zeros((4, 5, 5), dtype=np.int64)
+    for t, (v1, v2) in enumerate(vec):
+        for a in range(nc):
+            for b in range(nc):
+                kp1 = unit * (a if 2 * a < nc else a - nc)
+                kp2 = unit * (b if 2 * b < nc else b - nc)
+                k1, mu, tt = _explicit_shape(v1, v2, kp1, kp2)
+                j = int(np.searchsorted(edges, k1, side="right")) - 1
+                if not 0 <= j < 4:
+                    continue
+                im = min(int(np.searchsorted(oe.SHAPE_EDGES, min(max(mu, 0.5), 1.0), side="right")) - 1, 4)
+                it = min(int(np.searchsorted(oe.SHAPE_EDGES, tt, side="right")) - 1, 4)
+                sums[j, im, it] += B[t, a, b].real
+                cref[j, im, it] += 1
+    assert np.array_equal(cnt, cref) and cnt.sum() > 40
+    ok = cref > 0
+    assert np.allclose(mean[ok], sums[ok] / cref[ok], rtol=1e-12, atol=0) and np.all(np.isnan(mean[~ok]))
+    mc, cc = oe.bs_monopole(np.full((nt, nc, nc), 2.5 + 1.0j), kperp, unit, edges)
+    assert np.array_equal(cc, cnt) and np.all(mc[cc > 0] == 2.5)
