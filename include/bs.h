@@ -175,6 +175,26 @@ int bs_estimate_mabs(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs
 int bs_mabs_dft(bs_ctx* ctx, int32_t nc, int32_t n_tri, int32_t circular, const double* Bbar, double scale,
                 void* out);
 
+/* ---- monopole B(k1, mu, t) of the cylindrical 3D bispectrum (Sec. 2.2 Eq. shape, Sec. 5) ----
+ * Every cell (t, a, b) of a cylindrical BS (the output of bs_mabs_dft) is a triangle with sides
+ * k_i = sqrt(kperp_i^2 + kpar_i^2): kperp_host[t][0..2] (the three rings' k_perp, > 0),
+ * kpar_1 = kpar_unit a', kpar_2 = kpar_unit b' (a' = a for 2a < nc, else a - nc; kpar_unit =
+ * 2 pi / (r' B_bw)) and kpar_3 = -(kpar_1 + kpar_2).  Ordered k1 >= k2 >= k3 its shape is
+ * t = k2 / k1 and mu = (k1^2 + k2^2 - k3^2) / (2 k1 k2) (Eq. shape with closure), both clamped to
+ * [0.5, 1].  Bins: k1 half-open on k1_edges_host[0..n_k1] (increasing; cells outside are dropped),
+ * mu and t in 5 linear bins over [0.5, 1] (half-open, the last closed).  Without redshift-space
+ * distortion the BS does not depend on orientation, so the monopole of a bin is the mean of Re B
+ * over the cells in it.
+ * Bcyl (device): complex128 [n_tri][nc][nc].  Outputs (device): mean float64 [n_k1][5][5] (NaN
+ * where empty), count int64 [n_k1][5][5] (cells per bin).  The bin of every cell is decided in
+ * FP64 with each operation rounded separately, as a plain IEEE evaluation of the formula above.
+ * Synchronises the context's stream before returning.  bs_last_timing reports [0] the call,
+ * [1] the binning kernel, [2] the reduction.
+ * Errors: BS_EINVAL (n_k1 outside [1, 64], edges not increasing, kperp not positive, kpar_unit
+ * not positive, n_tri nc >= 2^31, NULL pointers), BS_ENOMEM, BS_EHIP. */
+int bs_monopole(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
+                const void* Bcyl, int32_t n_k1, const double* k1_edges_host, double* mean, int64_t* count);
+
 /* ---- 3D bispectrum (delay transform along frequency, |k| shells; Sec. 2.2, Eq. dft) ----
  * Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) exp(-2 pi i eta nu / nc); F_j = inverse 3D FT of Vt on shell j;
  * for each candidate triangle (a,b,c): S_D = sum_x F_a F_b F_c over the nc*n*n voxels,

@@ -20,7 +20,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
-    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_estimate_3d",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
                                    vp, vp, vp]
     L.bs_estimate_3d.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, dbl, vp, vp, vp]
     L.bs_mabs_dft.argtypes = [vp, i32, i32, i32, vp, dbl, vp]
+    L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
@@ -246,6 +247,22 @@ def bs_mabs_dft(ctx: int, nc: int, Bbar, out, scale: float = 1.0, circular: bool
         raise ValueError("bs_mabs_dft: Bbar must be contiguous [n_tri][%d][%d] and out contiguous [n_tri][%d][%d]"
                          % (size, size, nc, nc))
     _check(ctx, lib().bs_mabs_dft(ctx, int(nc), nt, 1 if circular else 0, _ptr(Bbar), float(scale), _ptr(out)))
+
+
+def bs_monopole(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) -> None:
+    """Monopole B(k1, mu, t): Bcyl complex128 [n_tri][nc][nc] on the device, kperp [n_tri][3] and
+    k1_edges [n_k1 + 1] on the host, mean float64 / count int64 [n_k1][5][5] on the device."""
+    nt, nc = int(Bcyl.shape[0]), int(Bcyl.shape[1])
+    kp = [float(x) for row in kperp for x in row]
+    ke = [float(x) for x in k1_edges]
+    nk = len(ke) - 1
+    if (tuple(Bcyl.shape) != (nt, nc, nc) or len(kp) != 3 * nt or tuple(mean.shape) != (nk, 5, 5)
+            or tuple(count.shape) != (nk, 5, 5) or not Bcyl.is_contiguous() or not mean.is_contiguous()
+            or not count.is_contiguous()):
+        raise ValueError("bs_monopole: Bcyl [n_tri][nc][nc], kperp [n_tri][3], mean and count [n_k1][5][5]")
+    kpa = (ctypes.c_double * max(len(kp), 1))(*kp)
+    kea = (ctypes.c_double * len(ke))(*ke)
+    _check(ctx, lib().bs_monopole(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, _ptr(mean), _ptr(count)))
 
 
 def bs_set_timing(ctx: int, enable: bool) -> None:

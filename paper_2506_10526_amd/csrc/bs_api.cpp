@@ -426,6 +426,59 @@ extern "C" int bs_mabs_dft(bs_ctx* c, int32_t nc, int32_t n_tri, int32_t circula
   return BS_OK;
 }
 
+// ------------------------------------------------------------------ monopole B(k1, mu, t)
+extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
+                           const void* Bcyl, int32_t n_k1, const double* k1_edges_host, double* mean,
+                           int64_t* count) {
+  if (!c) return BS_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  if (nc < 1 || nc > 65536) return ctx_fail(c, BS_EINVAL, "bs_monopole: nc must be in [1, 65536]");
+  if (n_tri < 0 || (long long)n_tri * nc > (1LL << 31) - 1)
+    return ctx_fail(c, BS_EINVAL, "bs_monopole: n_tri * nc must be in [0, 2^31)");
+  if (n_k1 < 1 || n_k1 > MONO_MAX_K1) return ctx_fail(c, BS_EINVAL, "bs_monopole: n_k1 must be in [1, 64]");
+  if (!k1_edges_host || !mean || !count) return ctx_fail(c, BS_EINVAL, "bs_monopole: NULL edges or outputs");
+  for (int i = 0; i < n_k1; ++i)
+    if (!(k1_edges_host[i + 1] > k1_edges_host[i]) || !(k1_edges_host[i] >= 0.0))
+      return ctx_fail(c, BS_EINVAL, "bs_monopole: k1 edges must be non-negative and increasing");
+  if (!(kpar_unit > 0.0) || !std::isfinite(kpar_unit)) return ctx_fail(c, BS_EINVAL, "bs_monopole: kpar_unit must be > 0");
+  if (n_tri > 0 && (!kperp_host || !Bcyl)) return ctx_fail(c, BS_EINVAL, "bs_monopole: NULL kperp or Bcyl");
+  for (long long i = 0; i < 3LL * n_tri; ++i)
+    if (!(kperp_host[i] > 0.0) || !std::isfinite(kperp_host[i]))
+      return ctx_fail(c, BS_EINVAL, "bs_monopole: kperp must be positive and finite");
+  const int nb = n_k1 * 25;
+  // one block per 8 rows of 256 cells or so, at most 1024: partial bins then a fixed-order reduction
+  const long long rows = (long long)n_tri * nc;
+  const int nblocks = (int)std::max(1LL, std::min(1024LL, (rows * nc + 2047) / 2048));
+  MonoArgs a{};
+  double* dk = static_cast<double*>(ctx_ws(c, "mono_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
+  a.psum = static_cast<double*>(ctx_ws(c, "mono_psum", (size_t)nblocks * nb * sizeof(double)));
+  a.pcnt = static_cast<int*>(ctx_ws(c, "mono_pcnt", (size_t)nblocks * nb * sizeof(int)));
+  if (!dk || !a.psum || !a.pcnt) return ctx_fail(c, BS_ENOMEM, "bs_monopole workspace");
+  std::vector<double> hk((size_t)3 * n_tri + n_k1 + 1);
+  for (long long i = 0; i < 3LL * n_tri; ++i) hk[i] = kperp_host[i];
+  for (int i = 0; i <= n_k1; ++i) hk[(size_t)3 * n_tri + i] = k1_edges_host[i];
+  HIPCHK(c, hipMemcpyAsync(dk, hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  a.B = static_cast<const double*>(Bcyl);
+  a.kperp = dk;
+  a.k1e = dk + 3 * (size_t)n_tri;
+  a.kpar_unit = kpar_unit;
+  a.nc = nc;
+  a.nt = n_tri;
+  a.nk = n_k1;
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  launch_mono_bin(a, nblocks, c->stream);
+  if (c->timing) { (void)hipEventRecord(c->ev[3], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  launch_mono_fin(a, nblocks, mean, count, c->stream);
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[5], c->stream);
+    (void)hipEventRecord(c->ev[1], c->stream);
+    c->have_timing = true;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the host staging of the tables is released on return
+  if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_monopole launch");
+  return BS_OK;
+}
+
 // ------------------------------------------------------------------ MABS
 extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
                                 const bs_mabs_sel* sel, int32_t precision, double norm, double* B,

@@ -247,3 +247,18 @@ struct MdftArgs {
 };
 void launch_mdft_n(const MdftArgs& a, size_t lds, hipStream_t s);
 void launch_mdft_m(const MdftArgs& a, size_t lds, hipStream_t s);
+
+// ---- monopole B(k1, mu, t) of the cylindrical 3D BS (Eq. shape, Sec. 5 binning) ----
+constexpr int MONO_MAX_K1 = 64;   // k1 bins
+struct MonoArgs {
+  const double* B;       // complex double [nt][nc][nc] (real parts read)
+  const double* kperp;   // [nt][3]
+  const double* k1e;     // [nk + 1] increasing k1 edges
+  double* psum;          // per-block partial sums [nblocks][nk * 25]
+  int* pcnt;             // per-block partial counts [nblocks][nk * 25]
+  double kpar_unit;
+  int nc, nt, nk;
+};
+void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s);
+// mean[b] = sum over blocks of psum / count (NaN where empty), count[b] as int64, fixed block order
+void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s);
