@@ -35,7 +35,8 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
 TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
-                 "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6}   # profiles/mdft_fp64_133x1535x1535_nc768.md
+                 "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
+                 "mono": (1255.3 + 14.8) * 1e6}   # profiles/mono_bin_133x768x768_k1x12.md
 
 
 def log(*a):
@@ -171,6 +172,7 @@ def mabs_dft_block(bs, ctx, w, torch, nt=133):
         got = out[t:t + 1].cpu().numpy()
         errs.append(float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
     t_cpu = (time.perf_counter() - t0) / 2
+    mono = monopole_block(bs, ctx, w, torch, out)
     return {
         "value": nt / t_wall, "unit": "triangles/s", "ms_per_call": t_wall * 1e3, "kernels_ms": ms,
         "pass_n_ms": ms_n, "pass_m_ms": ms_m,
@@ -184,6 +186,53 @@ def mabs_dft_block(bs, ctx, w, torch, nt=133):
         "cpu_oracle": {"value": 1.0 / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "2 of 133 triangles, float64 NumPy, the literal sum as two matrix products"},
         "workload": f"{nt} triangles x collapsed MABS [{size}][{size}] (nc = {nc}) -> [{nc}][{nc}] complex128",
+        "monopole": mono,
+    }
+
+
+def monopole_block(bs, ctx, w, torch, Bcyl):
+    """Monopole B(k1, mu, t) of the cylindrical BS just computed: the 133 ring triples of the
+    cube's rings (k_perp at the geometric centres of the ring edges), k_par unit 2 pi / (r' B_bw),
+    12 log k1 bins over 0.003-1.258 Mpc^-1 x 5 mu x 5 t.  HBM-bound: 16 B (one complex128 entry)
+    read per cell; the oracle on two triangles beside it."""
+    from oracle import estimator as oe
+    redges = w.shell_edges(20)
+    h, ncand = bs.bs_make_bins(None, bs.BS_RING_U, w.n, w.nc, redges / (2 * np.pi * w.du / w.r_mpc))
+    tri, _ = bs.bs_bins_triangles(h, ncand, 20)
+    bs.bs_free_bins(h)
+    kperp = np.sqrt(redges[:-1] * redges[1:])[np.asarray(tri).reshape(-1, 3)]
+    nt, nc = int(Bcyl.shape[0]), int(Bcyl.shape[1])
+    assert kperp.shape[0] == nt
+    unit = 2 * np.pi / (w.rprime * w.dnu * w.nc)
+    edges = np.geomspace(0.003, 1.258, 13)
+    mean = torch.empty((12, 5, 5), dtype=torch.float64, device="cuda")
+    cnt = torch.empty((12, 5, 5), dtype=torch.int64, device="cuda")
+    f = lambda: bs.bs_monopole(ctx, Bcyl, kperp, unit, edges, mean, cnt)
+    f()
+    kb, kr = [], []
+    for _ in range(5):
+        f()
+        tm = bs.bs_last_timing(ctx)
+        kb.append(tm[1])
+        kr.append(tm[2])
+    t_wall = time_steps(f, 5, 0, torch)
+    ms_b = float(np.median(kb))
+    byt = nt * nc * nc * 16
+    ach = byt / (ms_b * 1e-3) / 1e9
+    t0 = time.perf_counter()
+    Bh = Bcyl[:2].cpu().numpy()
+    ref_m, ref_c = oe.bs_monopole(Bh, kperp[:2], unit, edges)
+    t_cpu = (time.perf_counter() - t0) / 2
+    gc = cnt.cpu().numpy()
+    return {
+        "value": nt / t_wall, "unit": "triangles/s", "ms_per_call": t_wall * 1e3, "bin_kernel_ms": ms_b,
+        "reduce_kernel_ms": float(np.median(kr)), "cells_binned": int(gc.sum()), "bins_filled": int((gc > 0).sum()),
+        "roofline": {"bound": "hbm", "kernel": "k_mono_bin", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": byt,
+                     "traffic": TRAFFIC_BYTES.get("mono")},
+        "cpu_oracle": {"value": 1.0 / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                       "sample": "2 of 133 triangles, float64 NumPy"},
+        "workload": f"{nt} triangles x [{nc}][{nc}] cells -> 12 k1 x 5 mu x 5 t bins",
     }
 
 
@@ -397,6 +446,9 @@ def main():
         mdft = mabs_dft_block(bs, ctx, w, torch)
         log(f"[bench] mabs_dft: {mdft['ms_per_call']:.3f} ms/call (pass n {mdft['pass_n_ms']:.3f}, pass m "
             f"{mdft['pass_m_ms']:.3f}), {mdft['roofline']['achieved']:.0f} GB/s algorithmic")
+        mo = mdft["monopole"]
+        log(f"[bench] monopole: {mo['ms_per_call']:.3f} ms/call (binning {mo['bin_kernel_ms']:.3f} ms, "
+            f"{mo['roofline']['achieved']:.0f} GB/s), {mo['cells_binned']} cells in {mo['bins_filled']} bins")
     mc = None
     if not args.no_mc:
         log("[bench] Monte Carlo: 64 flagged realizations from one graph")

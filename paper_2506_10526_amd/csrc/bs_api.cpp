@@ -446,9 +446,9 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
     if (!(kperp_host[i] > 0.0) || !std::isfinite(kperp_host[i]))
       return ctx_fail(c, BS_EINVAL, "bs_monopole: kperp must be positive and finite");
   const int nb = n_k1 * 25;
-  // one block per 8 rows of 256 cells or so, at most 1024: partial bins then a fixed-order reduction
+  // a block per 2048 cells or so, at most 4096: partial bins then a fixed-order reduction
   const long long rows = (long long)n_tri * nc;
-  const int nblocks = (int)std::max(1LL, std::min(1024LL, (rows * nc + 2047) / 2048));
+  const int nblocks = (int)std::max(1LL, std::min(4096LL, (rows * nc + 2047) / 2048));
   MonoArgs a{};
   double* dk = static_cast<double*>(ctx_ws(c, "mono_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
   a.psum = static_cast<double*>(ctx_ws(c, "mono_psum", (size_t)nblocks * nb * sizeof(double)));

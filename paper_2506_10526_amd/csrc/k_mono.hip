@@ -14,15 +14,18 @@
 namespace {
 
 constexpr int MONO_THREADS = 256;
+constexpr int MONO_NB = 4;   // cells of a row per thread and step (loads in flight)
 
 // number of shape edges 0.6 .. 0.9 at or below x in [0.5, 1]: the half-open bin, last bin closed
 __device__ __forceinline__ int shape_bin(double x) {
   return (x >= 0.6) + (x >= 0.7) + (x >= 0.8) + (x >= 0.9);
 }
 
-// (k1, mu, t) of one cell; returns the bin index, or -1 when k1 lies outside the edges
-__device__ int cell_bin(const double* __restrict__ k1e, int nk, double kq0, double kq1, double kq2, double kp1,
-                        double kp2) {
+// (k1, mu, t) of one cell; returns the bin index, or -1 when k1 lies outside the edges.  lo2 / hi2
+// bound the squared largest side from outside the edges with a relative margin of 2^-20 on k1, far above
+// rounding: a cell beyond them is dropped without the square roots, the rest take the exact path.
+__device__ int cell_bin(const double* __restrict__ k1e, int nk, double lo2, double hi2, double kq0, double kq1,
+                        double kq2, double kp1, double kp2) {
 #pragma clang fp contract(off)
   const double kp3 = -(kp1 + kp2);
   const double s0 = kq0 * kq0 + kp1 * kp1;
@@ -30,6 +33,7 @@ __device__ int cell_bin(const double* __restrict__ k1e, int nk, double kq0, doub
   const double s2 = kq2 * kq2 + kp3 * kp3;
   // the three squared sides in descending order (exact selections)
   const double hi = fmax(s0, fmax(s1, s2)), lo = fmin(s0, fmin(s1, s2));
+  if (hi < lo2 || hi > hi2) return -1;
   const double mid = fmax(fmin(s0, s1), fmin(fmax(s0, s1), s2));
   const double k1 = sqrt(hi), k2 = sqrt(mid);
   double mu = ((hi + mid) - lo) / (2.0 * (k1 * k2));
@@ -61,32 +65,45 @@ __global__ __launch_bounds__(MONO_THREADS) void k_mono_bin(MonoArgs a) {
   }
   for (int i = threadIdx.x; i <= a.nk; i += MONO_THREADS) k1e[i] = a.k1e[i];
   __syncthreads();
+  const double elo = k1e[0] * (1.0 - 0x1p-20), ehi = k1e[a.nk] * (1.0 + 0x1p-20);
+  const double lo2 = elo * elo, hi2 = ehi * ehi;
   const int nc = a.nc, lane = threadIdx.x & 63;
   for (int row = blockIdx.x; row < a.nt * nc; row += gridDim.x) {
     const int t = row / nc, ai = row - t * nc;
     const double kq0 = a.kperp[3 * t], kq1 = a.kperp[3 * t + 1], kq2 = a.kperp[3 * t + 2];
     const double kp1 = a.kpar_unit * (double)(2 * ai < nc ? ai : ai - nc);
     const double* __restrict__ rowp = a.B + 2 * (long long)row * nc;
-    for (int b0 = 0; b0 < nc; b0 += MONO_THREADS) {   // the same trip count for every lane
-      const int b = b0 + threadIdx.x;
-      int bin = -1;
-      double v = 0.0;
-      if (b < nc) {
-        bin = cell_bin(k1e, a.nk, kq0, kq1, kq2, kp1, a.kpar_unit * (double)(2 * b < nc ? b : b - nc));
-        v = rowp[2 * b];
+    for (int b0 = 0; b0 < nc; b0 += MONO_NB * MONO_THREADS) {   // the same trip count for every lane
+      // the row's values first (MONO_NB loads in flight), then their bins
+      double v[MONO_NB];
+      int bin[MONO_NB];
+#pragma unroll
+      for (int u = 0; u < MONO_NB; ++u) {
+        const int b = b0 + u * MONO_THREADS + threadIdx.x;
+        v[u] = b < nc ? rowp[2 * b] : 0.0;
       }
-      unsigned long long m = __ballot(bin >= 0);
-      while (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        const int lb = __shfl(bin, leader);
-        const bool mine = bin == lb;
-        const unsigned long long mm = __ballot(mine);
-        const double x = wave_sum(mine ? v : 0.0);
-        if (lane == leader) {
-          atomicAdd(&ssum[lb], x);
-          atomicAdd(&scnt[lb], (int)__popcll(mm));
+#pragma unroll
+      for (int u = 0; u < MONO_NB; ++u) {
+        const int b = b0 + u * MONO_THREADS + threadIdx.x;
+        bin[u] = b < nc ? cell_bin(k1e, a.nk, lo2, hi2, kq0, kq1, kq2, kp1,
+                                   a.kpar_unit * (double)(2 * b < nc ? b : b - nc))
+                        : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < MONO_NB; ++u) {
+        unsigned long long m = __ballot(bin[u] >= 0);
+        while (m) {
+          const int leader = __ffsll((long long)m) - 1;
+          const int lb = __shfl(bin[u], leader);
+          const bool mine = bin[u] == lb;
+          const unsigned long long mm = __ballot(mine);
+          const double x = wave_sum(mine ? v[u] : 0.0);
+          if (lane == leader) {
+            atomicAdd(&ssum[lb], x);
+            atomicAdd(&scnt[lb], (int)__popcll(mm));
+          }
+          m &= ~mm;
         }
-        m &= ~mm;
       }
     }
   }
@@ -97,18 +114,33 @@ __global__ __launch_bounds__(MONO_THREADS) void k_mono_bin(MonoArgs a) {
   }
 }
 
-__global__ void k_mono_fin(MonoArgs a, int nblocks, double* __restrict__ mean, int64_t* __restrict__ count) {
-  const int nb = a.nk * 25;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
+// One block per bin: thread k adds the partials of blocks k, k + 256, ... in order, then a fixed
+// tree in LDS; the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_mono_fin(MonoArgs a, int nblocks, double* __restrict__ mean,
+                                                  int64_t* __restrict__ count) {
+  __shared__ double ss[256];
+  __shared__ long long sc[256];
+  const int nb = a.nk * 25, i = blockIdx.x;
   double s = 0.0;
   long long c = 0;
-  for (int k = 0; k < nblocks; ++k) {
+  for (int k = threadIdx.x; k < nblocks; k += 256) {
     s += a.psum[(long long)k * nb + i];
     c += a.pcnt[(long long)k * nb + i];
   }
-  mean[i] = c > 0 ? s / (double)c : __builtin_nan("");
-  count[i] = c;
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+      sc[threadIdx.x] += sc[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mean[i] = sc[0] > 0 ? ss[0] / (double)sc[0] : __builtin_nan("");
+    count[i] = sc[0];
+  }
 }
 
 }  // namespace
@@ -118,6 +150,5 @@ void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s) {
 }
 
 void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s) {
-  const int nb = a.nk * 25;
-  hipLaunchKernelGGL(k_mono_fin, dim3((nb + 255) / 256), dim3(256), 0, s, a, nblocks, mean, count);
+  hipLaunchKernelGGL(k_mono_fin, dim3(a.nk * 25), dim3(256), 0, s, a, nblocks, mean, count);
 }
