@@ -99,6 +99,39 @@ def round_counts(x: np.ndarray) -> Tuple[np.ndarray, float]:
 # ---------------------------------------------------------------------------
 # MABS
 # ---------------------------------------------------------------------------
+def grid_visibilities(uv: np.ndarray, vis: np.ndarray, flags: Optional[np.ndarray], n: int, du: float,
+                      chan_avg: int = 1):
+    """Eq. (vg): nearest-grid-point gridding of visibilities on the n x n uv grid of spacing du.
+
+    Visibility i has baseline uv[i] (wavelengths, the same in every channel) and values vis[nu][i];
+    F = 1 - flags[nu][i] (flags nonzero = flagged, None = nothing flagged).  Its grid point is
+    q = rint(U / du) per axis; a grid point with q_v < 0 stands for (-q_u, -q_v) with the
+    visibility conjugated (V(-U) = V*(U) for a real sky), so that the grid is the half plane
+    q_v >= 0 stored as [nu][q_u mod n][q_v].  Grid points with |q_u| or |q_v| >= n/2 are dropped.
+    V_g = sum of F V and N_g = sum of F over the visibilities of a grid point; chan_avg consecutive
+    channels are gridded together (the channel collapse of Sec. 4).
+    Returns (V_g [nc / chan_avg][n][n/2+1] complex128, N_g int64 of the same shape).
+    """
+    vis = np.asarray(vis)
+    nc, nvis = vis.shape
+    nco = nc // chan_avg
+    nh = n // 2 + 1
+    q = np.rint(np.asarray(uv, dtype=np.float64) / du).astype(np.int64)
+    neg = q[:, 1] < 0
+    q[neg] = -q[neg]
+    keep = (np.abs(q[:, 0]) < n // 2) & (np.abs(q[:, 1]) < n // 2)
+    cell = (q[:, 0] % n) * nh + q[:, 1]
+    F = np.ones((nc, nvis)) if flags is None else 1.0 - (np.asarray(flags) != 0)
+    V = np.where(neg[None, :], np.conj(vis), vis).astype(np.complex128) * F
+    Vg = np.zeros((nco, n * nh), dtype=np.complex128)
+    Ng = np.zeros((nco, n * nh), dtype=np.int64)
+    for c in range(nco * chan_avg):
+        o = c // chan_avg
+        np.add.at(Vg[o], cell[keep], V[c][keep])
+        np.add.at(Ng[o], cell[keep], F[c][keep].astype(np.int64))
+    return Vg.reshape(nco, n, nh), Ng.reshape(nco, n, nh)
+
+
 class MabsFields:
     """Lazily computed ring-filtered fields D_b(nu) and I_b(nu) (Eqs. iFT, iFT_I)."""
 

@@ -567,3 +567,62 @@ def test_bs_monopole_brute_force_and_constant():
     assert np.allclose(mean[ok], sums[ok] / cref[ok], rtol=1e-12, atol=0) and np.all(np.isnan(mean[~ok]))
     mc, cc = oe.bs_monopole(np.full((nt, nc, nc), 2.5 + 1.0j), kperp, unit, edges)
     assert np.array_equal(cc, cnt) and np.all(mc[cc > 0] == 2.5)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (vg): nearest-grid-point gridding
+# ---------------------------------------------------------------------------
+def test_grid_visibilities_brute_force_nearest_point():
+    """Cell by cell: the grid point nearest each baseline found by a search over every grid point of
+    the full plane (no rounding formula), mirrored into the half plane with the conjugate."""
+    rng = np.random.default_rng(4)
+    n, nc, nvis, du = 16, 6, 300, 1.0254
+    uv = rng.uniform(-9.0 * du, 9.0 * du, size=(nvis, 2))
+    vis = rng.normal(size=(nc, nvis)) + 1j * rng.normal(size=(nc, nvis))
+    flags = rng.random((nc, nvis)) < 0.2
+    Vg, Ng = oe.grid_visibilities(uv, vis, flags, n, du, chan_avg=2)
+    nh = n // 2 + 1
+    ref = np.zeros((nc // 2, n, nh), dtype=complex)
+    cref = np.zeros((nc // 2, n, nh), dtype=np.int64)
+    pts = np.array([(a, b) for a in range(-n, n + 1) for b in range(-n, n + 1)])
+    for i in range(nvis):
+        qa, qb = pts[np.argmin(np.sum((pts * du - uv[i]) ** 2, axis=1))]
+        conj = qb < 0
+        if conj:
+            qa, qb = -qa, -qb
+        if abs(qa) >= n // 2 or abs(qb) >= n // 2:
+            continue
+        for c in range(nc):
+            if not flags[c, i]:
+                ref[c // 2, qa % n, qb] += np.conj(vis[c, i]) if conj else vis[c, i]
+                cref[c // 2, qa % n, qb] += 1
+    assert np.array_equal(Ng, cref) and Ng.sum() > 500
+    assert np.max(np.abs(Vg - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_grid_visibilities_sky_on_grid_points_and_symmetries():
+    """Baselines on grid points, one per point of the half plane: the gridded cube is the sampled
+    visibilities themselves with N_g = 1; a baseline and its negative with the conjugate value add
+    up in one cell; a constant visibility gives V_g = value * N_g."""
+    n, nc, du = 16, 4, 0.75
+    V = synth.make_cube(synth.small_workload(n, nc), 5)             # [nc][n][n/2+1]
+    qa, qb = np.meshgrid(np.arange(-n // 2 + 1, n // 2), np.arange(0, n // 2), indexing="ij")
+    qa, qb = qa.ravel(), qb.ravel()
+    uv = np.stack([qa * du, qb * du], axis=1)
+    vis = V[:, qa % n, qb]
+    Vg, Ng = oe.grid_visibilities(uv, vis, None, n, du)
+    assert np.all(Ng[:, qa % n, qb] == 1) and Ng.sum() == nc * len(qa)
+    assert np.array_equal(Vg[:, qa % n, qb], vis)
+    # mirrored copies (q_v > 0 only) double each value
+    pos = qb > 0
+    uv2 = np.concatenate([uv, -uv[pos]])
+    vis2 = np.concatenate([vis, np.conj(vis[:, pos])], axis=1)
+    Vg2, Ng2 = oe.grid_visibilities(uv2, vis2, None, n, du)
+    assert np.allclose(Vg2[:, qa[pos] % n, qb[pos]], 2 * vis[:, pos], rtol=1e-15, atol=0)
+    assert np.all(Ng2[:, qa[pos] % n, qb[pos]] == 2)
+    # a point source at the phase centre: V = const, so V_g = const * N_g in every cell
+    rng = np.random.default_rng(6)
+    uv3 = rng.uniform(-6 * du, 6 * du, size=(500, 2))
+    flags = rng.random((nc, 500)) < 0.3
+    Vg3, Ng3 = oe.grid_visibilities(uv3, np.full((nc, 500), 2.0 + 0j), flags, n, du)
+    assert np.allclose(Vg3, 2.0 * Ng3, rtol=0, atol=1e-12) and Ng3.sum() == int((~flags).sum())
