@@ -107,7 +107,10 @@ def grid_visibilities(uv: np.ndarray, vis: np.ndarray, flags: Optional[np.ndarra
     F = 1 - flags[nu][i] (flags nonzero = flagged, None = nothing flagged).  Its grid point is
     q = rint(U / du) per axis; a grid point with q_v < 0 stands for (-q_u, -q_v) with the
     visibility conjugated (V(-U) = V*(U) for a real sky), so that the grid is the half plane
-    q_v >= 0 stored as [nu][q_u mod n][q_v].  Grid points with |q_u| or |q_v| >= n/2 are dropped.
+    q_v >= 0 stored as [nu][q_u mod n][q_v].  That half plane holds both halves of the line
+    q_v = 0, so a visibility on it enters at (q_u, 0) and, conjugated, at (-q_u, 0) (the same
+    cell twice for q_u = 0), as its mirror baseline would.  Grid points with |q_u| or |q_v| >= n/2
+    are dropped.
     V_g = sum of F V and N_g = sum of F over the visibilities of a grid point; chan_avg consecutive
     channels are gridded together (the channel collapse of Sec. 4).
     Returns (V_g [nc / chan_avg][n][n/2+1] complex128, N_g int64 of the same shape).
@@ -123,6 +126,12 @@ def grid_visibilities(uv: np.ndarray, vis: np.ndarray, flags: Optional[np.ndarra
     cell = (q[:, 0] % n) * nh + q[:, 1]
     F = np.ones((nc, nvis)) if flags is None else 1.0 - (np.asarray(flags) != 0)
     V = np.where(neg[None, :], np.conj(vis), vis).astype(np.complex128) * F
+    # the mirror entries of the line q_v = 0
+    line = keep & (q[:, 1] == 0)
+    cell = np.concatenate([cell, (-q[line, 0]) % n * nh])
+    keep = np.concatenate([keep, np.ones(int(line.sum()), dtype=bool)])
+    V = np.concatenate([V, np.conj(V[:, line])], axis=1)
+    F = np.concatenate([F, F[:, line]], axis=1)
     Vg = np.zeros((nco, n * nh), dtype=np.complex128)
     Ng = np.zeros((nco, n * nh), dtype=np.int64)
     for c in range(nco * chan_avg):

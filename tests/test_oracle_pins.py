@@ -594,8 +594,12 @@ def test_grid_visibilities_brute_force_nearest_point():
             continue
         for c in range(nc):
             if not flags[c, i]:
-                ref[c // 2, qa % n, qb] += np.conj(vis[c, i]) if conj else vis[c, i]
+                v = np.conj(vis[c, i]) if conj else vis[c, i]
+                ref[c // 2, qa % n, qb] += v
                 cref[c // 2, qa % n, qb] += 1
+                if qb == 0:          # the mirror baseline lands on the stored line too
+                    ref[c // 2, -qa % n, 0] += np.conj(v)
+                    cref[c // 2, -qa % n, 0] += 1
     assert np.array_equal(Ng, cref) and Ng.sum() > 500
     assert np.max(np.abs(Vg - ref)) <= 1e-12 * np.max(np.abs(ref))
 
@@ -611,10 +615,15 @@ def test_grid_visibilities_sky_on_grid_points_and_symmetries():
     uv = np.stack([qa * du, qb * du], axis=1)
     vis = V[:, qa % n, qb]
     Vg, Ng = oe.grid_visibilities(uv, vis, None, n, du)
-    assert np.all(Ng[:, qa % n, qb] == 1) and Ng.sum() == nc * len(qa)
-    assert np.array_equal(Vg[:, qa % n, qb], vis)
-    # mirrored copies (q_v > 0 only) double each value
     pos = qb > 0
+    assert np.all(Ng[:, qa[pos] % n, qb[pos]] == 1) and np.array_equal(Vg[:, qa[pos] % n, qb[pos]], vis[:, pos])
+    # on the line q_v = 0 every point also receives its mirror: V(q) + conj V(-q) = 2 V(q) for a real
+    # sky, two entries; the counts stay symmetric on the line
+    z = ~pos
+    assert np.all(Ng[:, qa[z] % n, 0] == 2) and Ng.sum() == nc * (len(qa) + int(z.sum()))
+    assert np.allclose(Vg[:, qa[z] % n, 0], 2 * vis[:, z], rtol=1e-12, atol=1e-12 * np.abs(vis).max())
+    assert np.array_equal(Ng[:, :, 0], Ng[:, (-np.arange(n)) % n, 0])
+    # mirrored copies (q_v > 0 only) double each value
     uv2 = np.concatenate([uv, -uv[pos]])
     vis2 = np.concatenate([vis, np.conj(vis[:, pos])], axis=1)
     Vg2, Ng2 = oe.grid_visibilities(uv2, vis2, None, n, du)
@@ -625,4 +634,7 @@ def test_grid_visibilities_sky_on_grid_points_and_symmetries():
     uv3 = rng.uniform(-6 * du, 6 * du, size=(500, 2))
     flags = rng.random((nc, 500)) < 0.3
     Vg3, Ng3 = oe.grid_visibilities(uv3, np.full((nc, 500), 2.0 + 0j), flags, n, du)
-    assert np.allclose(Vg3, 2.0 * Ng3, rtol=0, atol=1e-12) and Ng3.sum() == int((~flags).sum())
+    q3 = np.rint(uv3 / du)
+    on_line = (q3[:, 1] == 0) & (np.abs(q3[:, 0]) < n // 2)
+    assert np.allclose(Vg3, 2.0 * Ng3, rtol=0, atol=1e-12)
+    assert Ng3.sum() == int((~flags).sum()) + int((~flags[:, on_line]).sum())
