@@ -127,6 +127,28 @@ typedef enum { BS_FP64 = 0, BS_FP32 = 1, BS_SPLIT_BF16 = 2 } bs_precision;
 int bs_filter_fields(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs_weights* w,
                      int32_t three_d, int32_t precision, void* fields, double* count_fields);
 
+/* ---- gridding of visibilities (Sec. 3.2, Eq. vg) ----
+ * Visibility i has baseline uv[i] = (U, V) in wavelengths (device float64 [n_vis][2], the same in
+ * every channel) and values vis[nu][i] (device complex64 [nc][n_vis]); flags (device uint8
+ * [nc][n_vis], nonzero = flagged, NULL = none) give F = 0 or 1.  Its grid point is
+ * q = rint(U / du_lambda) per axis (round half to even); a point with q_v < 0 stands for
+ * (-q_u, -q_v) with the visibility conjugated (V(-U) = V*(U), a real sky), so that the grid is
+ * the half plane q_v >= 0 of the library's visibility layout; that layout stores both halves of
+ * the line q_v = 0, so a visibility on it also enters at (-q_u, 0) conjugated (as its mirror
+ * baseline would; N_g stays symmetric on the line).  Points with |q_u| or |q_v| >= n/2 are dropped.  chan_avg consecutive channels are gridded into one (the channel collapse of
+ * Sec. 4): V_g = sum of F V, N_g = sum of F over the visibilities and channels of a cell.
+ * Outputs (device): Vg [nc/chan_avg][n][n/2+1] complex64 (out_precision BS_FP32 / BS_SPLIT_BF16)
+ * or complex128 (BS_FP64), in the layout bs_estimate_mabs and bs_estimate_3d take; Ng int32 of
+ * the same shape, the per-cell counts of bs_weights (W_g = 1/N_g; bs_weights takes them as uint16).  Sums are
+ * accumulated in float64 (atomics: the order of additions, hence the last bits of a float64
+ * result, may vary between calls); counts are exact.  Scratch: 20 bytes a cell of context
+ * workspace.  bs_last_timing reports [0] the call, [1] the scatter kernel, [2] the output pass.
+ * Errors: BS_EINVAL (n odd or outside [2, 4096], nc not a multiple of chan_avg, du <= 0,
+ * NULL pointers), BS_ENOMEM, BS_EHIP. */
+int bs_grid_visibilities(bs_ctx* ctx, int32_t n, int32_t nc, double du_lambda, int64_t n_vis, const double* uv,
+                         const void* vis, const uint8_t* flags, int32_t chan_avg, int32_t out_precision, void* Vg,
+                         int32_t* Ng);
+
 /* ---- MABS estimator (Sec. 3.2, Eq. estimator_t; ergodic collapse described before Eq. dft) ----
  * For each selected triangle t = (b1,b2,b3) and channels (nu1,nu2,nu3):
  *   S_D = sum_theta D_b1(nu1) D_b2(nu2) D_b3(nu3),  N_tri = n^4 sum_theta I_b1 I_b2 I_b3 (exact int),

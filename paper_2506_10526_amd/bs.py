@@ -20,7 +20,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
-    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_estimate_3d",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_grid_visibilities", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
                                    vp, vp, vp]
     L.bs_estimate_3d.argtypes = [vp, vp, vp, ctypes.POINTER(bs_weights), i32, dbl, vp, vp, vp]
     L.bs_mabs_dft.argtypes = [vp, i32, i32, i32, vp, dbl, vp]
+    L.bs_grid_visibilities.argtypes = [vp, i32, i32, dbl, ctypes.c_int64, vp, vp, vp, i32, i32, vp, vp]
     L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
@@ -263,6 +264,21 @@ def bs_monopole(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) 
     kpa = (ctypes.c_double * max(len(kp), 1))(*kp)
     kea = (ctypes.c_double * len(ke))(*ke)
     _check(ctx, lib().bs_monopole(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, _ptr(mean), _ptr(count)))
+
+
+def bs_grid_visibilities(ctx: int, n: int, du_lambda: float, uv, vis, Vg, Ng, flags=None, chan_avg: int = 1,
+                         precision: int = BS_FP32) -> None:
+    """Eq. (vg): uv float64 [n_vis][2], vis complex64 [nc][n_vis], flags uint8 [nc][n_vis] or None;
+    Vg complex64 / complex128 (precision BS_FP64) and Ng int32 [nc/chan_avg][n][n/2+1]; all on the device."""
+    nc, nv = int(vis.shape[0]), int(vis.shape[1])
+    nco = nc // max(chan_avg, 1)
+    shp = (nco, n, n // 2 + 1)
+    if (tuple(uv.shape) != (nv, 2) or tuple(Vg.shape) != shp or tuple(Ng.shape) != shp
+            or (flags is not None and tuple(flags.shape) != (nc, nv))
+            or not all(t.is_contiguous() for t in (uv, vis, Vg, Ng) + ((flags,) if flags is not None else ()))):
+        raise ValueError("bs_grid_visibilities: uv [n_vis][2], vis/flags [nc][n_vis], Vg/Ng [nc/chan_avg][n][n/2+1]")
+    _check(ctx, lib().bs_grid_visibilities(ctx, int(n), nc, float(du_lambda), nv, _ptr(uv), _ptr(vis), _ptr(flags),
+                                           int(chan_avg), int(precision), _ptr(Vg), _ptr(Ng)))
 
 
 def bs_set_timing(ctx: int, enable: bool) -> None:

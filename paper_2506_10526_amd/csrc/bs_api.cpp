@@ -479,6 +479,48 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
   return BS_OK;
 }
 
+// ------------------------------------------------------------------ Eq. (vg) gridding
+extern "C" int bs_grid_visibilities(bs_ctx* c, int32_t n, int32_t nc, double du_lambda, int64_t n_vis,
+                                    const double* uv, const void* vis, const uint8_t* flags, int32_t chan_avg,
+                                    int32_t out_precision, void* Vg, int32_t* Ng) {
+  if (!c) return BS_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  if (n < 2 || n > 4096 || n % 2) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: n must be even in [2, 4096]");
+  if (chan_avg < 1 || nc < chan_avg || nc % chan_avg)
+    return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: nc must be a positive multiple of chan_avg");
+  if (!(du_lambda > 0.0) || !std::isfinite(du_lambda)) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: du must be > 0");
+  if (n_vis < 0 || n_vis > (1LL << 40)) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: bad n_vis");
+  if (out_precision < 0 || out_precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
+  if (!Vg || !Ng || (n_vis > 0 && (!uv || !vis))) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: NULL pointer");
+  GridArgs a{};
+  a.uv = uv;
+  a.vis = static_cast<const float*>(vis);
+  a.flags = flags;
+  a.nvis = n_vis;
+  a.n = n;
+  a.nc = nc;
+  a.chan_avg = chan_avg;
+  a.nco = nc / chan_avg;
+  a.du = du_lambda;
+  const size_t cells = (size_t)a.nco * n * (n / 2 + 1);
+  a.acc = static_cast<double*>(ctx_ws(c, "grid_acc", cells * 2 * sizeof(double)));
+  a.cnt = static_cast<int*>(ctx_ws(c, "grid_cnt", cells * sizeof(int)));
+  if (!a.acc || !a.cnt) return ctx_fail(c, BS_ENOMEM, "bs_grid_visibilities workspace");
+  if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
+  launch_grid_zero(a, c->stream);
+  if (c->timing) (void)hipEventRecord(c->ev[2], c->stream);
+  if (n_vis > 0) launch_grid_scatter(a, c->stream);
+  if (c->timing) { (void)hipEventRecord(c->ev[3], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  launch_grid_fin(a, out_precision == BS_FP64, Vg, Ng, c->stream);
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[5], c->stream);
+    (void)hipEventRecord(c->ev[1], c->stream);
+    c->have_timing = true;
+  }
+  if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_grid_visibilities launch");
+  return BS_OK;
+}
+
 // ------------------------------------------------------------------ MABS
 extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
                                 const bs_mabs_sel* sel, int32_t precision, double norm, double* B,

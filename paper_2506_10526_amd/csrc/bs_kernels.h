@@ -262,3 +262,19 @@ struct MonoArgs {
 void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s);
 // mean[b] = sum over blocks of psum / count (NaN where empty), count[b] as int64, fixed block order
 void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s);
+
+// ---- Eq. (vg): nearest-grid-point gridding of visibilities ----
+struct GridArgs {
+  const double* uv;            // [nvis][2] baselines in wavelengths
+  const float* vis;            // complex64 [nc][nvis], interleaved
+  const unsigned char* flags;  // [nc][nvis], nonzero = flagged; may be null
+  double* acc;                 // FP64 sums [nco][n][n/2+1][2]
+  int* cnt;                    // [nco][n][n/2+1]
+  long long nvis;
+  int n, nc, chan_avg, nco;
+  double du;
+};
+void launch_grid_zero(const GridArgs& a, hipStream_t s);
+void launch_grid_scatter(const GridArgs& a, hipStream_t s);
+// out: complex64 (fp64 == 0) or complex128 [nco][n][n/2+1]; ng: int32 of the same shape
+void launch_grid_fin(const GridArgs& a, bool fp64, void* out, int32_t* ng, hipStream_t s);

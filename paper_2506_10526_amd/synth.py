@@ -232,3 +232,23 @@ def collapsed_mabs(nt: int, nc: int, seed: int, circular: bool = False, gap_frac
         B[:, np.abs(d[None, :] - d[:, None]) >= nc] = np.nan
     B[rng.random((nt, size, size)) < gap_frac] = np.nan
     return B
+
+
+def uv_tracks(nvis: int, seed: int, umin: float, umax: float) -> np.ndarray:
+    """Seeded stand-in for a baseline distribution (the MWA baselines are not available): float64
+    [nvis][2] baselines in wavelengths, radius log-uniform in [umin, umax] (number density falling
+    as 1/U^2 in the plane, denser at short baselines like a compact array) and uniform angle."""
+    rng = np.random.default_rng(seed)
+    r = np.exp(rng.uniform(math.log(umin), math.log(umax), size=nvis))
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=nvis)
+    return np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1)
+
+
+def rfi_flags(nc: int, nvis: int, seed: int, rate: float, chan_w: Optional[np.ndarray] = None) -> np.ndarray:
+    """uint8 [nc][nvis] flags: whole channels where chan_w is 0 (periodic band flags) plus a random
+    `rate` of (channel, baseline) samples (RFI)."""
+    rng = np.random.default_rng(seed)
+    f = (rng.random((nc, nvis)) < rate).astype(np.uint8)
+    if chan_w is not None:
+        f[np.asarray(chan_w) == 0, :] = 1
+    return f
