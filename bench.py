@@ -11,9 +11,10 @@ first call).  The metric counts one product per valid triangle per voxel.
 
 Also reported on the same cube: the plain FP32 path of the same step, and the MABS
 contraction on MFMA for 133 ring triples x 8 nu1 rows (768 x 768 x 65536 GEMMs); the 2D DFT of
-Eq. (dft) on a collapsed MABS of 133 triples; Monte Carlo, batch and surrogate blocks.
+Eq. (dft) on a collapsed MABS of 133 triples and its monopole; Eq. (vg) gridding of 262,144
+baselines x 768 channels; Monte Carlo, batch and surrogate blocks.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mabs] [--no-mabs-dft]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mabs] [--no-mabs-dft] [--no-grid]
 """
 from __future__ import annotations
 
@@ -36,7 +37,8 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # were taken on; None once that kernel changes until the counters are taken again.
 TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_split2.md
                  "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
-                 "mono": (1255.3 + 14.8) * 1e6}   # profiles/mono_bin_133x768x768_k1x12.md
+                 "mono": (1255.3 + 14.8) * 1e6,   # profiles/mono_bin_133x768x768_k1x12.md
+                 "grid": (0.0 + 126.8 + 1718.9 + 2103.1 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
 
 
 def log(*a):
@@ -53,6 +55,7 @@ def parse():
     p.add_argument("--no-mabs", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-mabs-dft", action="store_true")
+    p.add_argument("--no-grid", action="store_true")
     p.add_argument("--no-mc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-surrogate", action="store_true")
@@ -233,6 +236,59 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
         "cpu_oracle": {"value": 1.0 / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "2 of 133 triangles, float64 NumPy"},
         "workload": f"{nt} triangles x [{nc}][{nc}] cells -> 12 k1 x 5 mu x 5 t bins",
+    }
+
+
+def grid_block(bs, ctx, w, torch, nvis=262144):
+    """Eq. (vg) gridding of the cube's shape: 262,144 seeded baselines (log-uniform radius over
+    0.5-120 cells, uniform angle) x 768 channels of complex64 visibilities in HBM, the periodic
+    channel flags plus 1 % random RFI flags, onto the 256 x 256 half-plane grid, four channels
+    collapsed into one (Sec. 4), complex64 output.  HBM-bound: the algorithmic bytes are the
+    visibilities (8 B) and flags (1 B) read once and the gridded cube and counts (12 B a cell)
+    written once.  The oracle on 24 of the 768 channels beside it."""
+    from oracle import estimator as oe
+    from paper_2506_10526_amd import synth
+    n, nc, avg = w.n, w.nc, 4
+    uv = synth.uv_tracks(nvis, 31, 0.5 * w.du, 120 * w.du)
+    flags = synth.rfi_flags(nc, nvis, 32, 0.01, synth.mwa_flags(nc))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(33)
+    vd = torch.randn((nc, nvis), dtype=torch.complex64, device="cuda", generator=g)
+    uvd = torch.from_numpy(uv).cuda()
+    fd = torch.from_numpy(flags).cuda()
+    shp = (nc // avg, n, n // 2 + 1)
+    Vg = torch.empty(shp, dtype=torch.complex64, device="cuda")
+    Ng = torch.empty(shp, dtype=torch.int32, device="cuda")
+    f = lambda: bs.bs_grid_visibilities(ctx, n, w.du, uvd, vd, Vg, Ng, flags=fd, chan_avg=avg)
+    f()
+    torch.cuda.synchronize()
+    ks, kf, tot = [], [], []
+    for _ in range(5):
+        f()
+        tm = bs.bs_last_timing(ctx)
+        tot.append(tm[0])
+        ks.append(tm[1])
+        kf.append(tm[2])
+    t_wall = time_steps(f, 5, 0, torch)
+    ms_s, ms_f, ms = float(np.median(ks)), float(np.median(kf)), float(np.median(tot))
+    cells = shp[0] * n * (n // 2 + 1)
+    alg = nc * nvis * 9 + cells * 12
+    ach = alg / (ms * 1e-3) / 1e9
+    t0 = time.perf_counter()
+    sub = 24
+    rV, rN = oe.grid_visibilities(uv, vd[:sub].cpu().numpy().astype(np.complex128), flags[:sub], n, w.du, avg)
+    t_cpu = (time.perf_counter() - t0) * nc / sub
+    counts_ok = bool(np.array_equal(Ng[:sub // avg].cpu().numpy(), rN))
+    return {
+        "value": nc * nvis / t_wall, "unit": "visibility samples/s", "ms_per_call": t_wall * 1e3,
+        "kernels_ms": ms, "scatter_ms": ms_s, "output_ms": ms_f,
+        "roofline": {"bound": "hbm", "kernel": "k_grid_scatter + k_grid_fin (zero, scatter, output)", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": alg, "traffic": TRAFFIC_BYTES.get("grid")},
+        "counts_match_oracle_on_24_channels": counts_ok,
+        "cpu_oracle": {"value": nc * nvis / t_cpu, "unit": "visibility samples/s", "cores": 1, "kind": "oracle",
+                       "sample": f"{sub} of {nc} channels, float64 NumPy, scaled to all channels"},
+        "workload": f"{nvis} baselines x {nc} channels -> {shp[0]} x {n} x {n // 2 + 1} cells (4:1 channel collapse)",
     }
 
 
@@ -449,6 +505,12 @@ def main():
         mo = mdft["monopole"]
         log(f"[bench] monopole: {mo['ms_per_call']:.3f} ms/call (binning {mo['bin_kernel_ms']:.3f} ms, "
             f"{mo['roofline']['achieved']:.0f} GB/s), {mo['cells_binned']} cells in {mo['bins_filled']} bins")
+    grid = None
+    if not args.no_grid:
+        log("[bench] Eq. (vg): gridding 262,144 baselines x 768 channels")
+        grid = grid_block(bs, ctx, w, torch)
+        log(f"[bench] grid: {grid['ms_per_call']:.3f} ms/call (scatter {grid['scatter_ms']:.3f}, output "
+            f"{grid['output_ms']:.3f}), {grid['roofline']['achieved']:.0f} GB/s algorithmic")
     mc = None
     if not args.no_mc:
         log("[bench] Monte Carlo: 64 flagged realizations from one graph")
@@ -492,6 +554,7 @@ def main():
         "fp32": fp32,
         "mabs": mabs,
         "mabs_dft": mdft,
+        "grid": grid,
         "mc": mc,
         "batch": batch,
         "surrogate": sur,
