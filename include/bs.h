@@ -144,7 +144,7 @@ int bs_filter_fields(bs_ctx* ctx, const bs_bins* bins, const void* vis, const bs
  * result, may vary between calls); counts are exact.  Scratch: 20 bytes a cell of context
  * workspace.  bs_last_timing reports [0] the call, [1] the scatter kernel, [2] the output pass.
  * Errors: BS_EINVAL (n odd or outside [2, 4096], nc not a multiple of chan_avg, du <= 0,
- * NULL pointers), BS_ENOMEM, BS_EHIP. */
+ * n_vis outside [0, 2^34], NULL pointers), BS_ENOMEM, BS_EHIP. */
 int bs_grid_visibilities(bs_ctx* ctx, int32_t n, int32_t nc, double du_lambda, int64_t n_vis, const double* uv,
                          const void* vis, const uint8_t* flags, int32_t chan_avg, int32_t out_precision, void* Vg,
                          int32_t* Ng);

@@ -489,7 +489,8 @@ extern "C" int bs_grid_visibilities(bs_ctx* c, int32_t n, int32_t nc, double du_
   if (chan_avg < 1 || nc < chan_avg || nc % chan_avg)
     return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: nc must be a positive multiple of chan_avg");
   if (!(du_lambda > 0.0) || !std::isfinite(du_lambda)) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: du must be > 0");
-  if (n_vis < 0 || n_vis > (1LL << 40)) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: bad n_vis");
+  // the scatter launch has n_vis / 8 work-items along x, which must stay below 2^32
+  if (n_vis < 0 || n_vis > (1LL << 34)) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: n_vis must be in [0, 2^34]");
   if (out_precision < 0 || out_precision > 2) return ctx_fail(c, BS_EINVAL, "bad precision");
   if (!Vg || !Ng || (n_vis > 0 && (!uv || !vis))) return ctx_fail(c, BS_EINVAL, "bs_grid_visibilities: NULL pointer");
   GridArgs a{};
