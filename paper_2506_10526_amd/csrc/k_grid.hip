@@ -24,12 +24,13 @@ __global__ void k_grid_zero(GridArgs a) {
   }
 }
 
-// Short baselines crowd into the few cells around the origin, so the cells |q_u| < GRID_HOT,
+// Short baselines crowd into the cells around the origin, so the cells |q_u| < GRID_HOT,
 // q_v < GRID_HOT of a block's visibilities are summed in LDS and added to the grid once per block
-// and channel group; the other cells take global atomics directly.
-constexpr int GRID_HOT = 16;
+// and channel group; the other cells take global atomics directly.  Large blocks of visibilities
+// (GRID_VPB) give the LDS cells many samples to combine.
+constexpr int GRID_HOT = 32;
 constexpr int GRID_NHOT = (2 * GRID_HOT - 1) * GRID_HOT;
-constexpr int GRID_VPT = 8;   // visibilities a thread
+constexpr int GRID_VPB = 16384;   // visibilities a block
 
 __device__ __forceinline__ void cell_add(const GridArgs& a, long long o, long long cell, double re, double im, int c) {
   const long long plane = (long long)a.n * (a.n / 2 + 1);
@@ -39,43 +40,14 @@ __device__ __forceinline__ void cell_add(const GridArgs& a, long long o, long lo
   atomicAdd(a.cnt + o * plane + cell, c);
 }
 
-// blockIdx.x: GRID_VPT * GRID_THREADS visibilities; blockIdx.y: output channels o = blockIdx.y,
-// blockIdx.y + gridDim.y, ...
+// blockIdx.x: GRID_VPB visibilities; blockIdx.y: output channels o = blockIdx.y, blockIdx.y +
+// gridDim.y, ...  The grid point of a visibility is recomputed for every channel group.
 __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
   __shared__ double hre[GRID_NHOT], him[GRID_NHOT];
   __shared__ int hc[GRID_NHOT];
   const int n = a.n, nh = n / 2 + 1, half = n / 2;
-  // grid points of this thread's visibilities: cell, mirror cell on the line q_v = 0, LDS slots
-  int cell[GRID_VPT], cellm[GRID_VPT];   // cell indices fit 32 bits (n <= 4096)
-  int hot[GRID_VPT], hotm[GRID_VPT];
-  bool neg[GRID_VPT];
-  const long long i0 = (long long)blockIdx.x * GRID_VPT * GRID_THREADS + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < GRID_VPT; ++u) {
-    const long long i = i0 + (long long)u * GRID_THREADS;
-    cell[u] = -1;
-    cellm[u] = -1;
-    hot[u] = -1;
-    hotm[u] = -1;
-    neg[u] = false;
-    if (i < a.nvis) {
-      double qu = rint(a.uv[2 * i] / a.du), qv = rint(a.uv[2 * i + 1] / a.du);
-      neg[u] = qv < 0.0;
-      if (neg[u]) {
-        qu = -qu;
-        qv = -qv;
-      }
-      if (fabs(qu) < (double)half && fabs(qv) < (double)half) {
-        const int iu = (int)qu, iv = (int)qv;
-        cell[u] = (iu < 0 ? iu + n : iu) * nh + iv;
-        if (iu > -GRID_HOT && iu < GRID_HOT && iv < GRID_HOT) hot[u] = (iu + GRID_HOT - 1) * GRID_HOT + iv;
-        if (iv == 0) {   // the mirror baseline on the stored line q_v = 0: (-q_u, 0), conjugated
-          cellm[u] = (iu > 0 ? n - iu : -iu) * nh;
-          if (hot[u] >= 0) hotm[u] = (-iu + GRID_HOT - 1) * GRID_HOT;
-        }
-      }
-    }
-  }
+  const long long vb = (long long)blockIdx.x * GRID_VPB;
+  const long long ve = vb + GRID_VPB < a.nvis ? vb + GRID_VPB : a.nvis;
   const float2* __restrict__ vis = reinterpret_cast<const float2*>(a.vis);
   for (int o = blockIdx.y; o < a.nco; o += gridDim.y) {
     for (int h = threadIdx.x; h < GRID_NHOT; h += GRID_THREADS) {
@@ -84,10 +56,15 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
       hc[h] = 0;
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < GRID_VPT; ++u) {
-      if (cell[u] < 0) continue;
-      const long long i = i0 + (long long)u * GRID_THREADS;
+    for (long long i = vb + threadIdx.x; i < ve; i += GRID_THREADS) {
+      double qu = rint(a.uv[2 * i] / a.du), qv = rint(a.uv[2 * i + 1] / a.du);
+      const bool neg = qv < 0.0;
+      if (neg) {
+        qu = -qu;
+        qv = -qv;
+      }
+      if (!(fabs(qu) < (double)half && fabs(qv) < (double)half)) continue;
+      const int iu = (int)qu, iv = (int)qv;
       double re = 0.0, im = 0.0;
       int c = 0;
       for (int k = 0; k < a.chan_avg; ++k) {
@@ -95,22 +72,24 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
         if (a.flags && a.flags[j]) continue;
         const float2 v = vis[j];
         re += (double)v.x;
-        im += neg[u] ? -(double)v.y : (double)v.y;
+        im += neg ? -(double)v.y : (double)v.y;
         ++c;
       }
       if (!c) continue;
-      if (hot[u] >= 0) {
-        atomicAdd(&hre[hot[u]], re);
-        atomicAdd(&him[hot[u]], im);
-        atomicAdd(&hc[hot[u]], c);
-        if (hotm[u] >= 0) {
-          atomicAdd(&hre[hotm[u]], re);
-          atomicAdd(&him[hotm[u]], -im);
-          atomicAdd(&hc[hotm[u]], c);
+      if (iu > -GRID_HOT && iu < GRID_HOT && iv < GRID_HOT) {
+        const int h = (iu + GRID_HOT - 1) * GRID_HOT + iv;
+        atomicAdd(&hre[h], re);
+        atomicAdd(&him[h], im);
+        atomicAdd(&hc[h], c);
+        if (iv == 0) {   // the mirror baseline on the stored line q_v = 0: (-q_u, 0), conjugated
+          const int hm = (-iu + GRID_HOT - 1) * GRID_HOT;
+          atomicAdd(&hre[hm], re);
+          atomicAdd(&him[hm], -im);
+          atomicAdd(&hc[hm], c);
         }
       } else {
-        cell_add(a, o, cell[u], re, im, c);
-        if (cellm[u] >= 0) cell_add(a, o, cellm[u], re, -im, c);
+        cell_add(a, o, (long long)(iu < 0 ? iu + n : iu) * nh + iv, re, im, c);
+        if (iv == 0) cell_add(a, o, (long long)(iu > 0 ? n - iu : -iu) * nh, re, -im, c);
       }
     }
     __syncthreads();
@@ -141,7 +120,7 @@ void launch_grid_zero(const GridArgs& a, hipStream_t s) {
 }
 
 void launch_grid_scatter(const GridArgs& a, hipStream_t s) {
-  const unsigned bx = (unsigned)((a.nvis + GRID_VPT * GRID_THREADS - 1) / (GRID_VPT * GRID_THREADS));
+  const unsigned bx = (unsigned)((a.nvis + GRID_VPB - 1) / GRID_VPB);
   const unsigned by = (unsigned)(a.nco < 64 ? a.nco : 64);
   hipLaunchKernelGGL(k_grid_scatter, dim3(bx, by), dim3(GRID_THREADS), 0, s, a);
 }
