@@ -360,6 +360,9 @@ extern "C" int bs_mabs_dft(bs_ctx* c, int32_t nc, int32_t n_tri, int32_t circula
   if (!Bbar || !out) return ctx_fail(c, BS_EINVAL, "bs_mabs_dft: Bbar and out must be non-NULL");
   MdftArgs a{};
   a.plan = make_fft_plan(nc);
+  // smallest radices first: the first pass writes with a lane stride of R elements, and radix 3
+  // spreads those writes over the LDS banks better than radix 8 (any order gives the same DFT)
+  if (!getenv("BS_MDFT_RADIX_DESC")) std::reverse(a.plan.rad, a.plan.rad + a.plan.nr);
   a.tw = ctx_twiddle(c, nc, true);
   if (!a.tw) return ctx_fail(c, BS_ENOMEM, "twiddle table");
   a.B = Bbar;

@@ -159,6 +159,9 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
     Delay3Args d{};
     d.g = g; d.vis = vis; d.chw = w ? w->chan_w : nullptr; d.out = fd.D; d.tw = fd.tw_nc;
     d.plan = make_fft_plan(nc); d.NL = p.NLd;
+    // smallest radices first: the first pass writes with a lane stride of R elements, and the small
+    // radices spread those writes over the LDS banks better (any order gives the same DFT)
+    if (!getenv("BS_3D_RADIX_DESC")) std::reverse(d.plan.rad, d.plan.rad + d.plan.nr);
     d.ip = two ? 0 : fft_ip_fits(d.plan, p.NLd, 256, 2) ? 2 : fft_ip_fits(d.plan, p.NLd, 256, 4) ? 4 : 0;
     size_t lds = ((d.ip ? 1 : 2) * (size_t)p.NLd * (nc + 1) + nc) * cz;
     if (fd.fp64) launch_delay3_f64(d, c->stream, lds); else launch_delay3_f32(d, c->stream, lds);
@@ -169,6 +172,7 @@ int fields3_enqueue(bs_ctx* c, const void* vis, const bs_weights* w, const Plan3
   // v pass
   a.work = fd.d_wv; a.off_in = nullptr; a.off_out = fd.d_offT; a.in = fd.D; a.out = fd.Tm; a.tw = fd.tw_n;
   a.plan = make_fft_plan(n); a.NL = p.NLv; a.indicator = fd.indicator ? 1 : 0;
+  if (!getenv("BS_3D_RADIX_DESC")) std::reverse(a.plan.rad, a.plan.rad + a.plan.nr);   // as for the delay pass
   a.shell_iv = p.shell_iv && !getenv("BS_3D_SHELL_TABLE") ? 1 : 0;
   a.ip = two ? 0 : fft_ip_fits(a.plan, p.NLv, 256, 2) ? 2 : fft_ip_fits(a.plan, p.NLv, 256, 4) ? 4 : 0;
   launch_vpass3(a, (int)p.wv.size(), fd.fp64, c->stream, ((a.ip ? 1 : 2) * (size_t)p.NLv * (n + 1) + n) * cz);
