@@ -3,6 +3,9 @@
 // accumulators), replayed from a captured hipGraph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include <cmath>
 #include <string>
 #include <vector>
@@ -57,6 +60,11 @@ GenArgs gen_args(bs_ctx* c, const bs_field_desc* d, int& rc) {
   if (!a.tw_n || !a.tw_nc) rc = ctx_fail(c, BS_ENOMEM, "twiddle tables");
   a.pn = make_fft_plan(d->n);
   a.pnc = make_fft_plan(d->nc);
+  // smallest radices first (first-pass LDS writes spread over more banks; the same DFT)
+  if (!getenv("BS_GEN_RADIX_DESC")) {
+    std::reverse(a.pn.rad, a.pn.rad + a.pn.nr);
+    std::reverse(a.pnc.rad, a.pnc.rad + a.pnc.nr);
+  }
   a.NL = d->n <= 256 ? 16 : (d->n <= 512 ? 8 : 4);
   a.NLx = a.NL;
   auto ip_of = [](const FftPlan& p, int nl) { return fft_ip_fits(p, nl, 256, 2) ? 2 : fft_ip_fits(p, nl, 256, 4) ? 4 : 0; };
