@@ -270,6 +270,11 @@ int ring_fields_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, bool f
   a.tw_n = tw;
   a.pcol = make_fft_plan(n / g.G);
   a.prow = make_fft_plan(n / 2);
+  // smallest radices first (first-pass LDS writes spread over more banks; the same DFT)
+  if (!getenv("BS_MABS_RADIX_DESC")) {
+    std::reverse(a.pcol.rad, a.pcol.rad + a.pcol.nr);
+    std::reverse(a.prow.rad, a.prow.rad + a.prow.nr);
+  }
   a.scale = 1.0 / ((double)n * (double)n);
   lds = g.lds;
   return BS_OK;
