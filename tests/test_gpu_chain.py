@@ -1,6 +1,6 @@
 """The paper's whole route on the GPU, from baselines and visibilities to the monopole, against the
 same route in the oracle: Eq. (vg) gridding -> Eq. (estimator_t) MABS with W_g = 1/N_g (FP64) ->
-ergodic collapse -> Eq. (dft) -> monopole B(k1, mu, t).
+ergodic collapse (non-circular, or circular over the channels) -> Eq. (dft) -> monopole B(k1, mu, t).
 
 Monopole counts depend only on the geometry and must be equal; each mean must lie within 1e-9 of
 the bin's mean |Re B| (the FP64 MABS agrees with the oracle to about 1e-12 relative per entry,
@@ -25,7 +25,8 @@ def ctx():
     c.close()
 
 
-def test_baselines_to_monopole(ctx):
+@pytest.mark.parametrize("circular", [False, True])
+def test_baselines_to_monopole(ctx, circular):
     n, nc, nvis, du = 32, 12, 3000, synth.DU_G
     redges = np.array([1.0, 2.5, 4.0, 6.0, 9.0])
     uv = synth.uv_tracks(nvis, 51, 0.8 * du, 12 * du)
@@ -36,8 +37,8 @@ def test_baselines_to_monopole(ctx):
     rV, rN = oe.grid_visibilities(uv, vis.astype(np.complex128), flags, n, du)
     b = ob.make_bins(ob.RING_U, n, nc, redges)
     B, N, _, _ = oe.estimate_mabs(b, rV, oe.Weights(ng=rN))
-    Bbar, Nnu, _ = oe.collapse_mabs(B, N)
-    Bc = oe.mabs_dft(Bbar)
+    Bbar, Nnu, _ = oe.collapse_mabs(B, N, circular=circular)
+    Bc = oe.mabs_dft(Bbar, circular=circular)
     cen = np.sqrt(redges[:-1] * redges[1:]) * 2 * np.pi / n
     kperp = np.array([[cen[i] for i in tri] for tri in b.triangles])
     unit = 2 * np.pi / nc
@@ -52,16 +53,16 @@ def test_baselines_to_monopole(ctx):
     ng16 = Ng.to(torch.int16)
     assert int(Ng.max().item()) < 32768
     h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, n, nc, redges)
-    size = 2 * nc - 1
+    size = nc if circular else 2 * nc - 1
     Bd = torch.empty((ncand, size, size), dtype=torch.float64, device="cuda")
     Nd = torch.empty((ncand, size, size), dtype=torch.int64, device="cuda")
     Nn = torch.empty((ncand, size, size), dtype=torch.int32, device="cuda")
-    bs.bs_estimate_mabs(ctx, h, Vg, bs.BS_FP64, Bd, Nd, N_nu=Nn, collapse=1, ng=ng16)
+    bs.bs_estimate_mabs(ctx, h, Vg, bs.BS_FP64, Bd, Nd, N_nu=Nn, collapse=2 if circular else 1, ng=ng16)
     bs.bs_free_bins(h)
     assert ncand == len(b.triangles)
     assert np.array_equal(host(Nn), Nnu)
     out = torch.empty((ncand, nc, nc), dtype=torch.complex128, device="cuda")
-    bs.bs_mabs_dft(ctx, nc, Bd, out)
+    bs.bs_mabs_dft(ctx, nc, Bd, out, circular=circular)
     mean = torch.empty((8, 5, 5), dtype=torch.float64, device="cuda")
     cnt = torch.empty((8, 5, 5), dtype=torch.int64, device="cuda")
     bs.bs_monopole(ctx, out, kperp, unit, edges, mean, cnt)
