@@ -385,13 +385,14 @@ extern "C" int bs_mabs_dft(bs_ctx* c, int32_t nc, int32_t n_tri, int32_t circula
     return e ? atoi(e) : def;
   };
   // Pass n: column pairs per group (at most BS_MDFT_NCOLS, default 4), line stride 4 mod 16
-  // elements so that the transposing store spreads over the LDS banks.  Pass m: rows per
+  // elements (BS_MDFT_LDMOD) so that the transposing store spreads over the LDS banks.  Pass m: rows per
   // group (at most BS_MDFT_MROWS, default 2).  A block of 256 threads is tried first where asked
   // for (512 threads fit every length up to 4096); each pass takes the fewest butterflies per
   // thread (2 or 4) that its in-place FFT fits.
   const int nwant = std::max(1, std::min(8, knob("BS_MDFT_NCOLS", 4)));
   const int mwant = std::max(1, std::min(4, knob("BS_MDFT_MROWS", 2)));
-  const int ld = nc + (20 - nc % 16) % 16;
+  const int ldr = knob("BS_MDFT_LDMOD", 4) & 15;
+  const int ld = nc + (16 + ldr - nc % 16) % 16;
   int nnl = 0, mnl = 0, nthreads = 0, mthreads = 0, nbm = 0, mbm = 0;
   for (int th : {knob("BS_MDFT_NCOLS_THREADS", 512) > 256 ? 512 : 256, 512})
     for (int nl : {8, 4, 2, 1})
