@@ -353,7 +353,7 @@ def batch_block(bs, ctx, torch, ncubes=64, seed=4):
 
 
 def surrogate_block(bs, ctx, bins, ncand, w, torch):
-    """Labels (4 flag patterns x 256 realizations), GPU training, judge against 1024 fresh
+    """Labels (4 flag patterns x 256 realizations), GPU training, evaluation against 1024 fresh
     realizations of a training pattern and of an unseen one; next to 200-realization Monte Carlo."""
     from paper_2506_10526_amd import surrogate, synth
     desc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, du_lambda=w.du, r_mpc=w.r_mpc,
@@ -395,8 +395,8 @@ def surrogate_block(bs, ctx, bins, ncand, w, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the library runs on one GPU; sharding over several is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2506_10526_amd import bs, synth
@@ -524,7 +524,7 @@ def main():
             f"{batch['mfma_tflops_incl_generation_and_fields']:.0f} TFLOP/s")
     sur = None
     if not args.no_surrogate:
-        log("[bench] variance surrogate: labels, training, judge")
+        log("[bench] variance surrogate: labels, training, evaluation against Monte Carlo")
         sur = surrogate_block(bs, ctx, bins, ncand, w, torch)
         log(f"[bench] surrogate: {sur['rel_err_vs_mc1024_training_pattern']}, unseen {sur['rel_err_vs_mc1024_unseen_pattern']}")
     cpu = None

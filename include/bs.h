@@ -43,7 +43,7 @@ extern "C" {
 #define BS_ENOMEM (-2)        /* device allocation failed */
 #define BS_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
 #define BS_ECOUNT (-4)        /* an FP64 triangle count was farther than 0.25 from an integer */
-#define BS_EUNSUPPORTED (-5)  /* valid request this build does not implement (e.g. 3D with per-cell N_g) */
+#define BS_EUNSUPPORTED (-5)  /* valid request the library does not implement (e.g. 3D with per-cell N_g) */
 
 typedef struct bs_ctx bs_ctx;
 typedef struct bs_bins bs_bins;
@@ -314,7 +314,7 @@ void bs_batch_destroy(bs_batch* batch);
  * (Mpc^-1) and rho = sum_nu w(nu) / nc the flag summary, relative to the Gaussian-shaped baseline
  * log(N_vox / T3D) + n_s sum_i log k_i (P ~ k^n_s).  Training runs on the GPU in FP32 (hand-written
  * forward, backward and Adam kernels, one training step captured into a hipGraph and replayed);
- * prediction runs in FP32 or BF16 (MFMA).  Monte Carlo (bs_mc_*) makes the labels and judges it.
+ * prediction runs in FP32 or BF16 (MFMA).  Monte Carlo (bs_mc_*) makes the labels and evaluates it.
  * State: BS_MLP_NSTATE floats on the device: the 133,121 parameters (W1 [256][4], b1, W2 [256][256],
  *   b2, W3 [256][256], b3, w4 [256], b4, row-major) then mu_x[4], s_x[4], mu_t, s_t (normalisation
  *   x' = (x - mu_x) / s_x, t' = (t - mu_t) / s_t, fitted by bs_mlp_set_data).

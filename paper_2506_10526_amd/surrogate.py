@@ -1,7 +1,7 @@
 """Variance surrogate pipeline over the C ABI (argument marshalling and orchestration only).
 
 Monte Carlo labels (bs_mc_*) -> features (bs_var_features) -> training on the GPU (bs_mlp_*) ->
-prediction of per-triangle Var(B_hat), with the plain Monte Carlo as fallback and judge.
+prediction of per-triangle Var(B_hat), with the plain Monte Carlo as fallback and reference.
 
 Flag family used for labels: in every 32-channel block the centre channel 16 and the e outermost
 channels at each edge are flagged (Sec. 4 describes edge and centre flagging of every 1.28 MHz

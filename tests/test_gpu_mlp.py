@@ -3,7 +3,7 @@
 Parity: Philox initialisation, normalisation, forward, loss and gradient, Adam trajectories
 (constant and cosine learning rate), BF16 inference against FP32.
 Gain: on the flagged MWA-shaped cube the surrogate, trained on Monte Carlo labels of four flag
-patterns, is judged against fresh Monte Carlo runs of a training pattern and of an unseen one,
+patterns, is checked against fresh Monte Carlo runs of a training pattern and of an unseen one,
 next to small Monte Carlo runs and the Gaussian-shaped baseline alone.
 """
 import time
@@ -167,7 +167,7 @@ def rel_err(pred, ref):
 
 
 def test_surrogate_gain_on_flagged_mwa_cube(ctx):
-    """Train on 4 flag patterns x 256 realizations of the 256 x 256 x 768 cube; judge against 1024
+    """Train on 4 flag patterns x 256 realizations of the 256 x 256 x 768 cube; checked against 1024
     fresh realizations of a training pattern (e = 1) and of an unseen one (e = 3)."""
     w = synth.config2()
     edges = w.shell_edges(20)
@@ -189,24 +189,24 @@ def test_surrogate_gain_on_flagged_mwa_cube(ctx):
         X, tgt = surrogate.training_set(h, ncand, T3D, train, -2.0)
         sur = surrogate.Surrogate(ctx, seed=1)
         fit = sur.fit(X, tgt, steps=4000, lr=3e-3, cosine=True)
-        judge1 = surrogate.mc_run(ctx, h, ncand, desc, flags[1], 1024, 1000)
-        judge3 = surrogate.mc_run(ctx, h, ncand, desc, flags[3], 1024, 2000)
+        ref1 = surrogate.mc_run(ctx, h, ncand, desc, flags[1], 1024, 1000)
+        ref3 = surrogate.mc_run(ctx, h, ncand, desc, flags[3], 1024, 2000)
         small = {R: surrogate.mc_run(ctx, h, ncand, desc, flags[1], R, 3000 + R) for R in (50, 200)}
         t0 = time.perf_counter()
-        p1 = surrogate.predict_var(sur, h, ncand, T3D, judge1.rho, -2.0)
+        p1 = surrogate.predict_var(sur, h, ncand, T3D, ref1.rho, -2.0)
         t_pred = time.perf_counter() - t0
-        p3 = surrogate.predict_var(sur, h, ncand, T3D, judge3.rho, -2.0)
-        p1b = surrogate.predict_var(sur, h, ncand, T3D, judge1.rho, -2.0, bf16=True)
+        p3 = surrogate.predict_var(sur, h, ncand, T3D, ref3.rho, -2.0)
+        p1b = surrogate.predict_var(sur, h, ncand, T3D, ref1.rho, -2.0, bf16=True)
         # the Gaussian-shaped baseline alone, its constant fitted on the training labels
-        _, base = bs.bs_var_features(h, ncand, T3D, -2.0, judge1.rho)
+        _, base = bs.bs_var_features(h, ncand, T3D, -2.0, ref1.rho)
         g1 = np.where(T3D > 0, np.exp(base + np.mean(tgt)), np.nan)
     finally:
         if sur:
             sur.close()
         bs.bs_free_bins(h)
-    e_s1, e_s3, e_b = rel_err(p1, judge1.var), rel_err(p3, judge3.var), rel_err(p1b, judge1.var)
-    e_g = rel_err(g1, judge1.var)
-    e50, e200 = rel_err(small[50].var, judge1.var), rel_err(small[200].var, judge1.var)
+    e_s1, e_s3, e_b = rel_err(p1, ref1.var), rel_err(p3, ref3.var), rel_err(p1b, ref1.var)
+    e_g = rel_err(g1, ref1.var)
+    e50, e200 = rel_err(small[50].var, ref1.var), rel_err(small[200].var, ref1.var)
     print(f"labels: 4 x 256 realizations in {t_labels:.2f} s; training {fit['steps']} steps in {fit['seconds']:.2f} s "
           f"(loss {fit['final_loss']:.3e}); prediction of {ncand} triangles in {t_pred * 1e3:.2f} ms")
     print(f"median / p90 relative error vs 1024-realization Monte Carlo:")
