@@ -429,7 +429,12 @@ def main():
         return lambda: bs.bs_estimate_3d(ctx, bins, Vd, prec, B, N)
 
     log("[bench] 3D split-BF16: warmup + timed steps")
+    # the timed steps run without the library's kernel events; one more step with them gives the
+    # per-kernel times
+    bs.bs_set_timing(ctx, False)
     t_split = time_steps(step(bs.BS_SPLIT_BF16), args.steps, args.warmup, torch)
+    bs.bs_set_timing(ctx, True)
+    step(bs.BS_SPLIT_BF16)()
     tim_split = bs.bs_last_timing(ctx)
     Bs = B.cpu().numpy().copy()
     Nt = N.cpu().numpy().copy()
@@ -442,7 +447,10 @@ def main():
     fp32 = None
     if not args.no_fp32:
         log("[bench] 3D FP32: timed steps")
+        bs.bs_set_timing(ctx, False)
         t32 = time_steps(step(bs.BS_FP32), max(3, args.steps // 2), 1, torch)
+        bs.bs_set_timing(ctx, True)
+        step(bs.BS_FP32)()
         tim32 = bs.bs_last_timing(ctx)
         B32 = B.cpu().numpy()
         ok = Nt > 0
