@@ -142,8 +142,10 @@ def baseline_log_var(edges: np.ndarray, tri: np.ndarray, T3D: np.ndarray, nvox: 
     """log(N_vox / T3D) + index * sum_i log k_i per triangle (-inf where T3D = 0)."""
     c = np.log(np.sqrt(edges[:-1] * edges[1:]))
     tri = np.asarray(tri)
+    T = np.asarray(T3D, dtype=np.float64)
     with np.errstate(divide="ignore"):
-        return np.log(nvox / np.asarray(T3D, dtype=np.float64)) + index * c[tri].sum(1)
+        out = np.log(nvox / np.where(T > 0, T, 1.0)) + index * c[tri].sum(1)
+    return np.where(T > 0, out, -np.inf)
 
 
 def train(theta: np.ndarray, x: np.ndarray, t: np.ndarray, steps: int, lr: float = 1e-3, cosine: bool = False):
