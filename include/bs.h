@@ -42,7 +42,7 @@ extern "C" {
 #define BS_EINVAL (-1)        /* bad argument: shapes, edges, pointers, unsupported combination of inputs */
 #define BS_ENOMEM (-2)        /* device allocation failed */
 #define BS_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
-#define BS_ECOUNT (-4)        /* an FP64 triangle count was farther than 0.25 from an integer */
+#define BS_ECOUNT (-4)        /* FP64 triangle counts could not be certified exact (bs_last_count_bound) */
 #define BS_EUNSUPPORTED (-5)  /* valid request the library does not implement (e.g. 3D with per-cell N_g) */
 
 typedef struct bs_ctx bs_ctx;
@@ -360,10 +360,19 @@ int bs_var_features(const bs_bins* bins, const int64_t* T3D_host, double pk_inde
  * Returns BS_EINVAL if timing was not enabled with bs_set_timing(ctx, 1). */
 int bs_set_timing(bs_ctx* ctx, int32_t enable);
 int bs_last_timing(const bs_ctx* ctx, double* out_ms_host, int32_t n);
-/* Largest |x - rint(x)| over the FP64 triangle counts x of the last estimate (or of the cached
- * counts it used).  Counts are rounded only when this is <= 0.25, else the call fails with
- * BS_ECOUNT. */
+/* Certified triangle counts (Sec. 3.2, Eq. iFT_I: N_tri = N^2 sum I1 I2 I3 is an integer).
+ * A count is computed in float64 as x = N^2 sum_x I_a I_b I_c from FFT'd bin indicators; before
+ * rounding, the library bounds |x - N_tri| a priori from the bins' cell counts |S_j|, the FFT
+ * lengths and the summation structure (first order in u = 2^-53: normwise FFT error per radix-2
+ * stage mu + gamma_4 (sqrt 2 + mu), radix-3 stages counted twice, the whole doubled; Parseval
+ * ||I_j||_2 = sqrt(|S_j| / N) and max |I_j| <= |S_j| / N; the longest chain of roundings in the
+ * sum).  The call fails with BS_ECOUNT when that bound is not below 1/2 (rint(x) would not be
+ * guaranteed to be N_tri) or when some |x - rint(x)| exceeds it (a computation outside the model).
+ * bs_last_count_dev: the largest |x - rint(x)| over the counts of the last estimate (or of the
+ * cached counts it used).  bs_last_count_bound: the bound that certified them (largest over the
+ * call's triangles). */
 int bs_last_count_dev(const bs_ctx* ctx, double* dev_host);
+int bs_last_count_bound(const bs_ctx* ctx, double* bound_host);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
     "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_grid_visibilities", "bs_estimate_3d",
-    "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
+    "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_last_count_bound", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
     "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.bs_last_count_bound.argtypes = [vp, ctypes.POINTER(dbl)]
     u64 = ctypes.c_uint64
     L.bs_generate_cube.argtypes = [vp, ctypes.POINTER(bs_field_desc), u64, u64, vp, vp]
     L.bs_mc_create.argtypes = [vp, vp, ctypes.POINTER(bs_field_desc), ctypes.POINTER(bs_weights), i32, dbl,
@@ -294,6 +295,12 @@ def bs_last_timing(ctx: int):
 def bs_last_count_dev(ctx: int) -> float:
     d = ctypes.c_double()
     _check(ctx, lib().bs_last_count_dev(ctx, ctypes.byref(d)))
+    return d.value
+
+
+def bs_last_count_bound(ctx: int) -> float:
+    d = ctypes.c_double()
+    _check(ctx, lib().bs_last_count_bound(ctx, ctypes.byref(d)))
     return d.value
 
 

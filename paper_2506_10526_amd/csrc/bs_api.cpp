@@ -140,6 +140,12 @@ extern "C" int bs_last_count_dev(const bs_ctx* c, double* dev) {
   return BS_OK;
 }
 
+extern "C" int bs_last_count_bound(const bs_ctx* c, double* bound) {
+  if (!c || !bound) return BS_EINVAL;
+  *bound = c->last_count_bound;
+  return BS_OK;
+}
+
 extern "C" int bs_set_stream(bs_ctx* c, void* s) {
   if (!c) return BS_EINVAL;
   c->stream = (hipStream_t)s;
@@ -532,6 +538,18 @@ extern "C" int bs_grid_visibilities(bs_ctx* c, int32_t n, int32_t nc, double du_
 }
 
 // ------------------------------------------------------------------ MABS
+// Certified rounding bound (bsplan::count_error_bound) of the FP64 ring counts of triangles `tri`
+// ([n][3] bins): ring fields from a folded C2C along u and a C2R along v, two normalisations, and
+// a summation whose longest chain of roundings is `depth`.
+double ring_count_bound(const bsplan::Plan& P, const std::vector<int>& tri, double depth) {
+  const double eps = bsplan::field_error_units(2 * bsplan::fft_stage_units(P.n) + 2, 2);
+  double bound = 0.0;
+  for (size_t t = 0; t + 2 < tri.size(); t += 3)
+    bound = std::max(bound, bsplan::count_error_bound((double)P.modes[tri[t]], (double)P.modes[tri[t + 1]],
+                                                      (double)P.modes[tri[t + 2]], eps, depth));
+  return bound;
+}
+
 extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, const bs_weights* w,
                                 const bs_mabs_sel* sel, int32_t precision, double norm, double* B,
                                 int64_t* N_tri, int32_t* N_nu) {
@@ -625,6 +643,13 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
     key = hash_bytes(key, tri.data(), tri.size() * sizeof(int));
     auto it = c->counts.find(key);
     if (it == c->counts.end()) {
+      // ring count fields: C2C along u (folded), C2R along v; the triple sum is 256 strided
+      // chains of Ppix / 256 fused multiply-adds and an 8-level tree
+      const double bound = ring_count_bound(P, tri, (double)((Ppix + 255) / 256) + 8.0);
+      c->last_count_bound = bound;
+      if (!(bound < 0.5))
+        return ctx_fail(c, BS_ECOUNT, "triangle counts cannot be certified at this size (FP64 error bound " +
+                                          std::to_string(bound) + " >= 1/2)");
       double* Ic = (double*)ctx_ws(c, "mabs_Iperp", (size_t)nbu * Ppix * 8);
       double* Ts = (double*)ctx_ws(c, "mabs_Tsum", (size_t)ntri * 8 + 16);
       if (!Ic || !Ts) return ctx_fail(c, BS_ENOMEM, "workspace (counts)");
@@ -642,12 +667,18 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
       HIPCHK(c, hipMemcpyAsync(&dev, bad, sizeof(dev), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       c->last_count_dev = dev;
-      if (!(dev <= kCountTol)) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev)); }
+      if (!(dev <= bound)) {
+        (void)hipFree(cc.d_counts);
+        return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev) + ", beyond its error bound " +
+                                          std::to_string(bound));
+      }
       cc.dev = dev;
+      cc.bound = bound;
       it = c->counts.emplace(key, std::move(cc)).first;
     }
     d_tperp = it->second.d_counts;
     c->last_count_dev = it->second.dev;
+    c->last_count_bound = it->second.bound;
   } else {
     I64 = (double*)ctx_ws(c, "mabs_I64", (size_t)nbu * bstride * 8);
     if (!I64) return ctx_fail(c, BS_ENOMEM, "workspace (count fields)");
@@ -676,6 +707,13 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
     if (k >= 1 && Ppix % k == 0 && (Ppix / k) % 32 == 0) kchunks = k;
   }
   int kchunk = Ppix / kchunks;
+  if (!separable) {
+    // per-channel count fields, FP64 GEMM: chains of kchunk products, then the chunk sums
+    c->last_count_bound = ring_count_bound(P, tri, (double)kchunk + (double)kchunks + 4.0);
+    if (!(c->last_count_bound < 0.5))
+      return ctx_fail(c, BS_ECOUNT, "triangle counts cannot be certified at this size (FP64 error bound " +
+                                        std::to_string(c->last_count_bound) + " >= 1/2)");
+  }
   // the batch must hold kchunks partial copies
   tb = (int)std::max<size_t>(1, std::min<size_t>(ntri, budget / std::max<size_t>(per_tri * kchunks, 1)));
   double* S = (double*)ctx_ws(c, "mabs_S", per_tri * kchunks * tb);
@@ -748,7 +786,9 @@ extern "C" int bs_estimate_mabs(bs_ctx* c, const bs_bins* b, const void* vis, co
     HIPCHK(c, hipMemcpyAsync(&dev, bad, sizeof(dev), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->last_count_dev = dev;
-    if (!(dev <= kCountTol)) return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev));
+    if (!(dev <= c->last_count_bound))
+      return ctx_fail(c, BS_ECOUNT, "triangle count off an integer by " + std::to_string(dev) + ", beyond its error bound " +
+                                        std::to_string(c->last_count_bound));
   }
   return BS_OK;
 }

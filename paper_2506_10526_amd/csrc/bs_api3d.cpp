@@ -371,6 +371,21 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
   auto it = c->counts.find(key);
   if (it == c->counts.end()) {
     const long long nvox = e.nvox;
+    // Certification of the rounding: the FP64 count fields come from C2C passes along v and u
+    // and a C2R pass along eta (three rounded normalisations); the contraction's longest chain
+    // of roundings is one slab (8 MFMA steps of 4 products), one flush per slab of the block's
+    // chunk, the four waves of the block, and the two stages of the fixed-order partial sums.
+    const double eps_field = bsplan::field_error_units(2 * bsplan::fft_stage_units(P.n) + bsplan::fft_stage_units(P.nc) + 2, 3);
+    const double depth = 33.0 + (double)(e.chunk / 128) + 5.0 + (double)kReduceGroup +
+                         (double)((e.nblk + kReduceGroup - 1) / kReduceGroup) + 1.0;
+    double bound = 0.0;
+    for (int t = 0; t < ntri; ++t)
+      bound = std::max(bound, bsplan::count_error_bound((double)P.modes[P.tri[3 * t]], (double)P.modes[P.tri[3 * t + 1]],
+                                                        (double)P.modes[P.tri[3 * t + 2]], eps_field, depth));
+    c->last_count_bound = bound;
+    if (!(bound < 0.5))
+      return ctx_fail(c, BS_ECOUNT, "3D triangle counts cannot be certified at this size (FP64 error bound " +
+                                        std::to_string(bound) + " >= 1/2)");
     Plan3 pc;
     build_plan3(P, e.blocks, true, pc);
     void* F64 = ctx_ws(c, "c3_F64", (size_t)e.blocks.size() * nvox * 8);
@@ -399,13 +414,19 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
     HIPCHK(c, hipMemcpyAsync(&dev, bad, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->last_count_dev = dev;
-    if (!(dev <= kCountTol)) { (void)hipFree(cc.d_counts); return ctx_fail(c, BS_ECOUNT, "3D triangle count off an integer by " + std::to_string(dev)); }
+    if (!(dev <= bound)) {
+      (void)hipFree(cc.d_counts);
+      return ctx_fail(c, BS_ECOUNT, "3D triangle count off an integer by " + std::to_string(dev) + ", beyond its error bound " +
+                                        std::to_string(bound));
+    }
     cc.dev = dev;
+    cc.bound = bound;
     cc.tri.assign(P.tri.begin(), P.tri.end());
     it = c->counts.emplace(key, std::move(cc)).first;
   }
   e.d_counts = it->second.d_counts;
   e.count_dev = it->second.dev;
+  e.count_bound = it->second.bound;
   // ---- data fields and contraction ----
   build_plan3(P, e.blocks, e.fp64, e.pd);
   // Delay-axis grid of the fused path.  With true closure (3 H < nc) any grid M > 3 H closes the
@@ -575,6 +596,7 @@ extern "C" int bs_estimate_3d(bs_ctx* c, const bs_bins* b, const void* vis, cons
   Est3& e = *held;
   if (e.ntri == 0) return BS_OK;
   c->last_count_dev = e.count_dev;
+  c->last_count_bound = e.count_bound;
   rc = est3_enqueue(c, b, vis, w, e, norm, B, N_tri, N_eff);
   if (rc) return rc;
   c->last_grid_M = e.M;

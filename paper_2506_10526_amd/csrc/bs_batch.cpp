@@ -284,7 +284,9 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
     rc = ring_fields_prepare(c, q.bins, nullptr, false, false, false, q.d_blocks, nullptr, (long long)q.nc * q.n * q.n,
                              q.fa, q.flds);
     if (rc) return restore_fail(rc);
-    // channel-independent counts T_perp = n^4 sum_p I1 I2 I3
+    // channel-independent counts T_perp = n^4 sum_p I1 I2 I3, certified like the MABS counts
+    const double bound = ring_count_bound(q.bins->P, q.tri, (double)((q.n * q.n + 255) / 256) + 8.0);
+    if (!(bound < 0.5)) return restore_fail(ctx_fail(c, BS_ECOUNT, "batch triangle counts cannot be certified at this size"));
     double* Ic = nullptr;
     double* Ts = nullptr;
     unsigned long long* bad = nullptr;
@@ -311,7 +313,7 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
     (void)hipFree(Ic); (void)hipFree(Ts); (void)hipFree(bad);
     if (rc) return restore_fail(rc);
     if (e != hipSuccess || !q.d_tperp) return restore_fail(ctx_fail(c, BS_EHIP, "batch counts"));
-    if (!(dev <= kCountTol)) return restore_fail(ctx_fail(c, BS_ECOUNT, "batch triangle count off an integer"));
+    if (!(dev <= bound)) return restore_fail(ctx_fail(c, BS_ECOUNT, "batch triangle count off an integer beyond its error bound"));
     q.tperp.resize(q.ntri);
     HIPCHK(c, hipMemcpy(q.tperp.data(), q.d_tperp, (size_t)q.ntri * 8, hipMemcpyDeviceToHost));
     for (int t = 0; t < q.ntri; ++t)

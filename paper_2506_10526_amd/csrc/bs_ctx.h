@@ -23,10 +23,8 @@ struct CountCache {
   int64_t* d_counts = nullptr;    // device int64 per triangle
   std::vector<int64_t> h_counts;  // host copy
   double dev = 0.0;               // max |count - rint(count)| when the counts were made
+  double bound = 0.0;             // certified bound on that distance (bsplan::count_error_bound)
 };
-
-// Largest distance of an FP64 triangle count from an integer that is accepted before rounding.
-constexpr double kCountTol = 0.25;
 
 struct Est3;
 
@@ -43,6 +41,7 @@ struct bs_ctx {
   double last_ms[4] = {0, 0, 0, 0};
   bool have_timing = false;
   double last_count_dev = 0.0;
+  double last_count_bound = 0.0;   // error bound that certified the rounding of the last counts
   int last_grid_M = 0;   // delay-axis grid of the last 3D contraction
   double last_flops_vox = 0.0, last_vox = 0.0;   // algorithmic MFMA flops per voxel, voxels (MFMA synthesis path)
   std::map<std::string, int> tuned;       // autotuned launch parameters, by shape key
@@ -60,6 +59,9 @@ struct bs_bins {
 };
 
 // ---- helpers implemented in bs_api.cpp ----
+// Certified bound on |x - T| of the FP64 ring counts of triangles `tri` ([n][3] bins) whose
+// triple sum has a longest chain of `depth` roundings (bsplan::count_error_bound).
+double ring_count_bound(const bsplan::Plan& P, const std::vector<int>& tri, double depth);
 int ctx_fail(bs_ctx* c, int code, const std::string& msg);
 void* ctx_ws(bs_ctx* c, const char* name, size_t bytes);       // grow-only; NULL on failure
 const void* ctx_twiddle(bs_ctx* c, int L, bool fp64);          // NULL on failure

@@ -59,7 +59,7 @@ struct Est3 {
   double *partial = nullptr, *reduced = nullptr;
   double rho3 = 1.0;
   const int64_t* d_counts = nullptr;
-  double count_dev = 0.0;
+  double count_dev = 0.0, count_bound = 0.0;
   Plan3 pd;
   Fields3Dev fd;
   int M = 0;

@@ -6,6 +6,10 @@
 
 #include "fft_lds.h"
 
+// Parts summed per group in the first stage of the fixed-order reduction of per-block partials
+// (3D contractions).
+constexpr int kReduceGroup = 32;
+
 // ---------------------------------------------------------------- ring fields
 struct MabsFieldArgs {
   const void* vis;          // complex64 (T=float) or complex128 (T=double), [nc][n][nh]

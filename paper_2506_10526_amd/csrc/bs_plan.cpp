@@ -4,6 +4,7 @@
 #include "bs_plan.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 namespace bsplan {
@@ -24,6 +25,31 @@ static uint64_t fnv(uint64_t h, const void* p, size_t n) {
   const unsigned char* c = (const unsigned char*)p;
   for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ULL; }
   return h;
+}
+
+double fft_stage_units(int L) {
+  double a = 0, b = 0;
+  while (L > 1 && L % 2 == 0) { L /= 2; a += 1; }
+  while (L > 1 && L % 3 == 0) { L /= 3; b += 1; }
+  if (L > 1) a += std::ceil(std::log2((double)L)) * 2;   // not produced by the library's plans
+  return a + 2 * b;
+}
+
+double field_error_units(double stages, int scalings) {
+  const double u = std::ldexp(1.0, -53), mu = 1.0;       // twiddles rounded once from long double
+  const double g4 = 4.0 / (1.0 - 4.0 * u);                // gamma_4 / u
+  const double eta = mu + g4 * (std::sqrt(2.0) + mu * u); // per radix-2 stage, units of u
+  return 2.0 * eta * stages + scalings;
+}
+
+double count_error_bound(double Sa, double Sb, double Sc, double eps_field, double depth) {
+  const double u = std::ldexp(1.0, -53);
+  const double r = std::sqrt(Sa * Sb * Sc);
+  const double field = eps_field * r * (std::sqrt(std::min(Sb, Sc)) + std::sqrt(std::min(Sa, Sc)) + std::sqrt(std::min(Sa, Sb)));
+  const double m = std::min(std::min(std::sqrt(Sa * Sb) * Sc, std::sqrt(Sa * Sc) * Sb), std::sqrt(Sb * Sc) * Sa);
+  const double t = std::min(std::min(Sa * Sb, Sa * Sc), Sb * Sc);
+  // second-order terms are below 1e-3 of the first-order ones for every bound below 1/2
+  return 1.001 * u * (field + (depth + 3.0) * m + t);
 }
 
 std::string build_plan(int kind, int n, int nc, int nbins, const double* edges, double umax,

@@ -466,7 +466,9 @@ __global__ __launch_bounds__(256) void k3_contract(Con3Args a) {
     con3_step<MODE, T>(sF, C3_LDS, a.nbu, wave * 32, sp, RT, CT, acc);
     __syncthreads();
     since += C3_SLAB;
-    if (MODE != 0 && since >= 512) { since = 0; con3_flush<MODE>(acc, acc64); }
+    // FP32 forms: FP64 flush every 512 voxels.  FP64 form (the triangle counts): every slab, so
+    // that no accumulation chain is longer than one slab plus the slab count of the block.
+    if (since >= (MODE == 0 ? C3_SLAB : 512)) { since = 0; con3_flush<MODE>(acc, acc64); }
   }
   con3_store<MODE>(acc, acc64, red, a.partial + (size_t)blockIdx.x * 112 * 32);
 }
@@ -876,7 +878,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
 // first slot (in place), then the group sums are added in group order.
 // Parts are pstride slots apart; only the first nent entries of each are summed (the rows of the
 // pair tiles in use), the rest of `out` is cleared.
-constexpr int RGROUP = 32;
+constexpr int RGROUP = kReduceGroup;
 __global__ void k3_reduce_groups(double* __restrict__ partial, int nparts, int pstride, int nent) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nent) return;
