@@ -400,9 +400,11 @@ def rho3(weights: Optional[Weights], nc: int) -> float:
 
 def estimate_3d(bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None,
                 tri: Optional[np.ndarray] = None, norm: float = 1.0,
-                fields: Optional[ShellFields] = None):
+                fields: Optional[ShellFields] = None, counts: Optional[np.ndarray] = None):
     """3D bispectrum per candidate triangle.
 
+    counts: the triangle counts T3D of `tri` when already known (e.g. the exact integers of
+    oracle.counts.exact_counts); otherwise they come from the count fields, rounded.
     Returns (B [nt], T3D [nt] int64, N_eff [nt], S_D [nt], max count deviation).
     """
     f = fields or ShellFields(bins, vis, weights)
@@ -413,8 +415,12 @@ def estimate_3d(bins: Bins, vis: np.ndarray, weights: Optional[Weights] = None,
     SI = np.empty(nt)
     for t, (a, b, c) in enumerate(tri):
         S[t] = np.sum(f.data(a) * f.data(b) * f.data(c))
-        SI[t] = np.sum(f.count(a) * f.count(b) * f.count(c))
-    T, dev = round_counts(float(nvox) * float(nvox) * SI)
+        if counts is None:
+            SI[t] = np.sum(f.count(a) * f.count(b) * f.count(c))
+    if counts is None:
+        T, dev = round_counts(float(nvox) * float(nvox) * SI)
+    else:
+        T, dev = np.asarray(counts, dtype=np.int64).reshape(nt), 0.0
     neff = T.astype(np.float64) * rho3(weights, bins.nc)
     with np.errstate(invalid="ignore", divide="ignore"):
         B = np.where(T > 0, norm * nvox * S / np.where(neff > 0, neff, 1.0), np.nan)

@@ -26,7 +26,49 @@ def host(t):
     return t.cpu().numpy()
 
 
-KAPPA0 = 10.0
+# Entries with cond = B_abs / |B_ref| up to KAPPA0 are held to the relative tolerance; beyond
+# that (near-zero realisations) the bound is normwise, tol times B_abs.
+KAPPA0 = 1e3
+
+
+def per_bin_errors(Bg, Bref, N, abs_scale):
+    """Per-entry error record of the entries with N_tri > 0: rel = |B_gpu - B_ref| / |B_ref|,
+    cond = B_abs / |B_ref| and the count (arrays over the valid entries, flattened)."""
+    Bg = np.asarray(Bg, dtype=np.float64).ravel()
+    Bref = np.asarray(Bref, dtype=np.float64).ravel()
+    N = np.asarray(N).ravel()
+    ok = N > 0
+    err = np.abs(Bg[ok] - Bref[ok])
+    ref = np.abs(Bref[ok])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(ref > 0, err / ref, np.where(err > 0, np.inf, 0.0))
+        cond = np.where(ref > 0, np.asarray(abs_scale, dtype=np.float64).ravel()[ok] / ref, np.inf)
+    return rel, cond, N[ok], err
+
+
+def write_per_bin_report(label, Bg, Bref, N, abs_scale, tol, extra=None):
+    """Writes the per-bin error table (rel, cond, N_tri per valid entry, plus a summary by
+    conditioning band) as JSON into $BS_PER_BIN_DIR when that is set."""
+    import json
+    import os
+    d = os.environ.get("BS_PER_BIN_DIR")
+    if not d:
+        return
+    os.makedirs(d, exist_ok=True)
+    rel, cond, n, _ = per_bin_errors(Bg, Bref, N, abs_scale)
+    bands = {}
+    for name, lo, hi in (("cond<=10", 0, 10), ("10<cond<=1e3", 10, 1e3), ("cond>1e3", 1e3, np.inf)):
+        m = (cond > lo) & (cond <= hi) if lo > 0 else cond <= hi
+        bands[name] = {"entries": int(m.sum()), "max_rel": float(rel[m].max()) if m.any() else None}
+    rep = {"label": label, "tol": tol, "kappa0": KAPPA0, "valid_entries": int(len(rel)), "bands": bands,
+           "max_rel_cond_le_kappa0": float(rel[cond <= KAPPA0].max()) if (cond <= KAPPA0).any() else None}
+    if len(rel) <= 5000:
+        rep["entries"] = [{"rel": float(a), "cond": float(b), "N_tri": int(c)} for a, b, c in zip(rel, cond, n)]
+    if extra:
+        rep.update(extra)
+    safe = "".join(ch if ch.isalnum() or ch in "-_." else "_" for ch in label)
+    with open(os.path.join(d, safe + ".json"), "w") as fh:
+        json.dump(rep, fh)
 
 
 def compare_B(Bg, Bref, N, abs_scale, tol, label=""):
@@ -44,6 +86,7 @@ def compare_B(Bg, Bref, N, abs_scale, tol, label=""):
     ref = np.abs(Bref[ok])
     scale = np.asarray(abs_scale, dtype=np.float64)[ok]
     bound = np.maximum(tol * ref, (tol / KAPPA0) * scale)
+    write_per_bin_report(label, Bg, Bref, N, abs_scale, tol)
     bad = err > bound
     assert not bad.any(), (f"{label}: {bad.sum()} entries above max(tol|B|, tol/{KAPPA0:g} B_abs); "
                            f"worst err/bound {float((err / bound).max()):.3g}")
