@@ -1,8 +1,8 @@
 """GPU parity of the MABS estimator (C ABI) against the FP64 oracle.
 
 Counts must be bit-exact.  B: relative error <= 1e-10 (FP64 path), 1e-5 (FP32 MFMA) and 1e-4 (split-BF16
-MFMA) where the entry is well conditioned (cond = sum |F1 F2 F3| / |sum F1 F2 F3| <= 10),
-and error <= tol/10 of the |F1 F2 F3| estimate beyond (see gpu_common.compare_B).
+MFMA) where cond = sum |F1 F2 F3| / |sum F1 F2 F3| <= 1e3, or within the precision's normwise
+floor there, and error <= tol of the |F1 F2 F3| estimate beyond (see gpu_common.compare_B).
 """
 import numpy as np
 import pytest
@@ -159,8 +159,12 @@ def test_sign_flip_and_scaling_are_exact(ctx, prec):
         assert np.array_equal(B2[ok], -B1[ok])
         assert np.array_equal(B3[ok], 8 * B1[ok])
     else:
-        # the bf16 MFMA accumulation is not sign-symmetric in its last bit (measured), so the
-        # split path is checked to a few FP32 ulps of the entry
+        # the bf16 MFMAs do not round their internal sum symmetrically: on the MI355X one
+        # v_mfma_f32_*_bf16 whose products span many binades is off by -0.7 ulp on average
+        # (toward -inf), and D(-A, B, -C) differs from -D(A, B, C) by one ulp in about 30 % of
+        # outputs (measured with ones as B and known exact sums); the split hi/lo of -x is exactly
+        # -(hi, lo), so this is the one asymmetric step, and the split path is checked to a few
+        # FP32 ulps of the entry
         assert np.all(np.abs(B2[ok] + B1[ok]) <= 1e-6 * (np.abs(B1[ok]) + np.nanmax(np.abs(B1))))
         assert np.array_equal(B3[ok], 8 * B1[ok]) or np.allclose(B3[ok], 8 * B1[ok], rtol=1e-6)
 
