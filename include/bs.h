@@ -217,6 +217,24 @@ int bs_mabs_dft(bs_ctx* ctx, int32_t nc, int32_t n_tri, int32_t circular, const 
 int bs_monopole(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
                 const void* Bcyl, int32_t n_k1, const double* k1_edges_host, double* mean, int64_t* count);
 
+/* ---- allocation-free monopole ----
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): bs_monopole with the same inputs, outputs, binning and
+ * results (up to the order of the float64 additions: fewer blocks may share the cells), except
+ *  - kperp [n_tri][3] and k1_edges [n_k1 + 1] are DEVICE float64 arrays (not checked on the host:
+ *    kperp must be positive and the edges non-negative and increasing, as for bs_monopole);
+ *  - the call only enqueues work on the context's stream: no host staging, no synchronisation,
+ *    no bs_last_timing figures;
+ *  - the per-block partial bins live in a fixed 8 MiB device array of the library, one per GPU,
+ *    held until the process ends (at most 8 MiB / (25 n_k1 * 12 bytes) blocks, 436 at n_k1 = 64).
+ * Calls on one GPU share that array: calls that overlap on one GPU (two streams, two contexts)
+ * race.  Every block writes all of its partial bins before they are read, so nothing has to be
+ * cleared between calls.  It allocates nothing: no hipMalloc, hipFree or allocating library call.
+ * Errors: BS_EINVAL (n_k1 outside [1, 64], nc outside [1, 65536], n_tri * nc >= 2^31, kpar_unit not
+ * positive, NULL pointers), BS_EHIP (launch failure, or the scratch address of the device unknown). */
+int bs_monopole_noalloc(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp, double kpar_unit,
+                        const void* Bcyl, int32_t n_k1, const double* k1_edges, double* mean, int64_t* count);
+
 /* ---- 3D bispectrum (delay transform along frequency, |k| shells; Sec. 2.2, Eq. dft) ----
  * Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) exp(-2 pi i eta nu / nc); F_j = inverse 3D FT of Vt on shell j;
  * for each candidate triangle (a,b,c): S_D = sum_x F_a F_b F_c over the nc*n*n voxels,

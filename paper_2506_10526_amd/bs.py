@@ -20,7 +20,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
-    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_grid_visibilities", "bs_estimate_3d",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_monopole_noalloc", "bs_grid_visibilities", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_last_count_bound", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.bs_mabs_dft.argtypes = [vp, i32, i32, i32, vp, dbl, vp]
     L.bs_grid_visibilities.argtypes = [vp, i32, i32, dbl, ctypes.c_int64, vp, vp, vp, i32, i32, vp, vp]
     L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
+    L.bs_monopole_noalloc.argtypes = [vp, i32, i32, vp, dbl, vp, i32, vp, vp, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
@@ -265,6 +266,18 @@ def bs_monopole(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) 
     kpa = (ctypes.c_double * max(len(kp), 1))(*kp)
     kea = (ctypes.c_double * len(ke))(*ke)
     _check(ctx, lib().bs_monopole(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, _ptr(mean), _ptr(count)))
+
+
+def bs_monopole_noalloc(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) -> None:
+    """Allocation-free monopole: as bs_monopole, but kperp float64 [n_tri][3] and k1_edges float64
+    [n_k1 + 1] are device tensors, and the call only enqueues work on the context's stream."""
+    nt, nc = int(Bcyl.shape[0]), int(Bcyl.shape[1])
+    nk = int(k1_edges.shape[0]) - 1
+    if (tuple(Bcyl.shape) != (nt, nc, nc) or tuple(kperp.shape) != (nt, 3) or tuple(mean.shape) != (nk, 5, 5)
+            or tuple(count.shape) != (nk, 5, 5) or not all(t.is_contiguous() for t in (Bcyl, kperp, k1_edges, mean, count))):
+        raise ValueError("bs_monopole_noalloc: Bcyl [n_tri][nc][nc], kperp [n_tri][3], mean and count [n_k1][5][5]")
+    _check(ctx, lib().bs_monopole_noalloc(ctx, nc, nt, _ptr(kperp), float(kpar_unit), _ptr(Bcyl), nk, _ptr(k1_edges),
+                                          _ptr(mean), _ptr(count)))
 
 
 def bs_grid_visibilities(ctx: int, n: int, du_lambda: float, uv, vis, Vg, Ng, flags=None, chan_avg: int = 1,

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbs.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["k_mabs.hip", "k_3d.hip", "k_gen.hip", "k_mlp.hip", "k_mdft.hip", "k_mono.hip", "k_grid.hip", "bs_api.cpp", "bs_api3d.cpp", "bs_mc.cpp", "bs_mlp.cpp", "bs_batch.cpp"]
+HIP_SOURCES = ["k_mabs.hip", "k_3d.hip", "k_gen.hip", "k_mlp.hip", "k_mdft.hip", "k_mono.hip", "k_grid.hip", "bs_api.cpp", "bs_api3d.cpp", "bs_mc.cpp", "bs_mlp.cpp", "bs_batch.cpp", "bs_noalloc.cpp"]
 HOST_SOURCES = ["bs_plan.cpp"]
 ARCH = os.environ.get("BS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

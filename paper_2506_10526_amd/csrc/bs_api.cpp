@@ -109,6 +109,7 @@ extern "C" int bs_create(int device, void* hip_stream, bs_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { (void)hipGetLastError(); return BS_EHIP; }
   if (device < 0 || device >= ndev) return BS_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return BS_EHIP;
+  if (noalloc_scratch_init(device) != BS_OK) return BS_EHIP;
   bs_ctx* c = new bs_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;

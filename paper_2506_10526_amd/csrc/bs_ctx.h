@@ -58,6 +58,10 @@ struct bs_bins {
   int8_t* d_lut = nullptr;
 };
 
+// Device address of the allocation-free entry points' scratch array on `device` (current), looked
+// up once per device (bs_noalloc.cpp).
+int noalloc_scratch_init(int device);
+
 // ---- helpers implemented in bs_api.cpp ----
 // Certified bound on |x - T| of the FP64 ring counts of triangles `tri` ([n][3] bins) whose
 // triple sum has a longest chain of `depth` roundings (bsplan::count_error_bound).
