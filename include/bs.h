@@ -149,6 +149,30 @@ int bs_grid_visibilities(bs_ctx* ctx, int32_t n, int32_t nc, double du_lambda, i
                          const void* vis, const uint8_t* flags, int32_t chan_avg, int32_t out_precision, void* Vg,
                          int32_t* Ng);
 
+/* ---- primary-beam decorrelation of the gridded estimator (Sec. 3.1 Eq. S3, Sec. 3.2 Eq. vg) ----
+ * Eq. S3: the correlation of three baselines whose sum is dU instead of zero is the closed one times
+ * exp(-a |dU|^2), a = pi^2 theta_0^2 / 3 (theta_0 = 0.6 theta_F).  Gridding (Eq. vg, as
+ * bs_grid_visibilities: nearest point, reversed baselines for q_v < 0, the line q_v = 0 stored whole)
+ * makes a closed grid triangle correlate baseline triplets that do not close: with offsets
+ * delta = U - U_g from their grid points, dU = delta_1 + delta_2 + delta_3.  With the cell-average
+ * weight W_g = 1/N_g the expected estimate of each ring triangle is the true MABS times
+ *   D = mean over its closed grid triangles (all cells sampled) of the mean over the baseline
+ *       triplets of the three cells of exp(-a |dU|^2);
+ * dividing an estimate by D removes this bias (largest for the smallest rings).
+ * Computed as D = sum over nodes k of w_k * (mean over closed grid triangles of prod_j phi_gj(k)),
+ * phi_g(k) = mean over cell g of exp(i k . delta), using exp(-a |dU|^2) = E[exp(i sqrt(2a) z . dU)]
+ * for a 2D standard normal z and the n_nodes-point Gauss rule per axis (Golub-Welsch); each node's
+ * triangle average is the FP64 MABS of the phi grid with the N_g weights (bs_estimate_mabs).  The
+ * rule is exact to 4e-14 at n_nodes = 12 for the offsets of a cell of dU_g = sqrt(ln 2)/(pi theta_0).
+ * rings: BS_RING_U bins (their n, edges and umax are used); uv: device float64 [n_vis][2] baselines in
+ * wavelengths, the same in every channel, no flags.  D_host: host float64 [n_candidates], NaN where
+ * no closed grid triangle has all three cells sampled.  Synchronises the context's stream.
+ * Scratch: about (n_nodes^2 / 2) n (n/2+1) 40 bytes of context workspace.
+ * Errors: BS_EINVAL (not ring bins, n_nodes not even in [2, 32], du or theta0 not positive, more than
+ * 65535 baselines in one cell, bad pointers), BS_ENOMEM, BS_EHIP, and those of bs_estimate_mabs. */
+int bs_decorrelation(bs_ctx* ctx, const bs_bins* rings, int64_t n_vis, const double* uv, double du_lambda,
+                     double theta0_rad, int32_t n_nodes, double* D_host);
+
 /* ---- MABS estimator (Sec. 3.2, Eq. estimator_t; ergodic collapse described before Eq. dft) ----
  * For each selected triangle t = (b1,b2,b3) and channels (nu1,nu2,nu3):
  *   S_D = sum_theta D_b1(nu1) D_b2(nu2) D_b3(nu3),  N_tri = n^4 sum_theta I_b1 I_b2 I_b3 (exact int),

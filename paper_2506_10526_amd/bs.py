@@ -20,7 +20,7 @@ BS_FP64, BS_FP32, BS_SPLIT_BF16 = 0, 1, 2
 
 EXPORTED = [
     "bs_create", "bs_destroy", "bs_last_error", "bs_set_stream", "bs_make_bins", "bs_bins_triangles",
-    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_monopole_noalloc", "bs_grid_visibilities", "bs_estimate_3d",
+    "bs_bins_info", "bs_free_bins", "bs_filter_fields", "bs_estimate_mabs", "bs_mabs_dft", "bs_monopole", "bs_monopole_noalloc", "bs_grid_visibilities", "bs_decorrelation", "bs_estimate_3d",
     "bs_set_timing", "bs_last_timing", "bs_last_count_dev", "bs_last_count_bound", "bs_generate_cube", "bs_mc_create", "bs_mc_run",
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
     L.bs_grid_visibilities.argtypes = [vp, i32, i32, dbl, ctypes.c_int64, vp, vp, vp, i32, i32, vp, vp]
     L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
     L.bs_monopole_noalloc.argtypes = [vp, i32, i32, vp, dbl, vp, i32, vp, vp, vp]
+    L.bs_decorrelation.argtypes = [vp, vp, ctypes.c_int64, vp, dbl, dbl, i32, vp]
     L.bs_set_timing.argtypes = [vp, i32]
     L.bs_last_timing.argtypes = [vp, ctypes.POINTER(dbl), i32]
     L.bs_last_count_dev.argtypes = [vp, ctypes.POINTER(dbl)]
@@ -278,6 +279,19 @@ def bs_monopole_noalloc(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean,
         raise ValueError("bs_monopole_noalloc: Bcyl [n_tri][nc][nc], kperp [n_tri][3], mean and count [n_k1][5][5]")
     _check(ctx, lib().bs_monopole_noalloc(ctx, nc, nt, _ptr(kperp), float(kpar_unit), _ptr(Bcyl), nk, _ptr(k1_edges),
                                           _ptr(mean), _ptr(count)))
+
+
+def bs_decorrelation(ctx: int, rings: int, n_cand: int, uv, du_lambda: float, theta0_rad: float, n_nodes: int = 12):
+    """Eq. (S3) decorrelation factor D per candidate ring triangle (host float64 [n_cand]) for the
+    baselines uv (device float64 [n_vis][2], wavelengths) gridded with spacing du_lambda."""
+    import numpy as np
+    nv = int(uv.shape[0])
+    if uv.dim() != 2 or int(uv.shape[1]) != 2 or not uv.is_contiguous():
+        raise ValueError("bs_decorrelation: uv [n_vis][2]")
+    D = np.zeros(max(n_cand, 1), dtype=np.float64)
+    _check(ctx, lib().bs_decorrelation(ctx, rings, nv, _ptr(uv), float(du_lambda), float(theta0_rad), int(n_nodes),
+                                       D.ctypes.data))
+    return D[:n_cand]
 
 
 def bs_grid_visibilities(ctx: int, n: int, du_lambda: float, uv, vis, Vg, Ng, flags=None, chan_avg: int = 1,

@@ -538,6 +538,149 @@ extern "C" int bs_grid_visibilities(bs_ctx* c, int32_t n, int32_t nc, double du_
   return BS_OK;
 }
 
+// ------------------------------------------------------------------ Eq. (S3) decorrelation
+// Nodes z and weights w of the Q-point Gauss rule for the standard normal weight (probabilists'
+// Hermite), from the eigen-decomposition of the symmetric tridiagonal Jacobi matrix of the
+// recurrence x He_k = He_{k+1} + k He_{k-1} (off-diagonal sqrt(k)): the nodes are its eigenvalues,
+// the weights the squared first components of its unit eigenvectors (Golub and Welsch 1969).
+// Cyclic Jacobi rotations on the dense Q x Q matrix; Q <= 32.
+static void gauss_normal_rule(int Q, std::vector<double>& z, std::vector<double>& w) {
+  std::vector<double> A((size_t)Q * Q, 0.0), V((size_t)Q * Q, 0.0);
+  for (int i = 0; i < Q; ++i) V[(size_t)i * Q + i] = 1.0;
+  for (int k = 1; k < Q; ++k) A[(size_t)(k - 1) * Q + k] = A[(size_t)k * Q + (k - 1)] = std::sqrt((double)k);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < Q; ++p)
+      for (int q = p + 1; q < Q; ++q) off += A[(size_t)p * Q + q] * A[(size_t)p * Q + q];
+    if (off < 1e-34) break;
+    for (int p = 0; p < Q; ++p)
+      for (int q = p + 1; q < Q; ++q) {
+        const double apq = A[(size_t)p * Q + q];
+        if (apq == 0.0) continue;
+        const double th = (A[(size_t)q * Q + q] - A[(size_t)p * Q + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < Q; ++k) {   // A <- A J (columns p, q)
+          const double akp = A[(size_t)k * Q + p], akq = A[(size_t)k * Q + q];
+          A[(size_t)k * Q + p] = c * akp - sn * akq;
+          A[(size_t)k * Q + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < Q; ++k) {   // A <- J^T A (rows p, q)
+          const double apk = A[(size_t)p * Q + k], aqk = A[(size_t)q * Q + k];
+          A[(size_t)p * Q + k] = c * apk - sn * aqk;
+          A[(size_t)q * Q + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < Q; ++k) {   // V <- V J
+          const double vkp = V[(size_t)k * Q + p], vkq = V[(size_t)k * Q + q];
+          V[(size_t)k * Q + p] = c * vkp - sn * vkq;
+          V[(size_t)k * Q + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  z.resize(Q);
+  w.resize(Q);
+  double ws = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    z[i] = A[(size_t)i * Q + i];
+    w[i] = V[(size_t)i] * V[(size_t)i];   // first component of eigenvector i
+    ws += w[i];
+  }
+  for (int i = 0; i < Q; ++i) w[i] /= ws;
+}
+
+extern "C" int bs_decorrelation(bs_ctx* c, const bs_bins* rings, int64_t n_vis, const double* uv, double du_lambda,
+                                double theta0_rad, int32_t n_nodes, double* D_host) {
+  if (!c) return BS_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  if (!rings || rings->P.kind != BS_RING_U) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: ring bins required");
+  if (!D_host) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: D_host is NULL");
+  if (n_vis < 0 || n_vis > (1LL << 34) || (n_vis > 0 && !uv)) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: bad baselines");
+  if (!(du_lambda > 0.0) || !std::isfinite(du_lambda)) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: du must be > 0");
+  if (!(theta0_rad > 0.0) || !std::isfinite(theta0_rad)) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: theta0 must be > 0");
+  if (n_nodes < 2 || n_nodes > 32 || n_nodes % 2) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: n_nodes must be even in [2, 32]");
+  const bsplan::Plan& P = rings->P;
+  const int n = P.n, nh = n / 2 + 1, ncand = (int)(P.tri.size() / 3);
+  // exp(-a |dU|^2) = E_z[exp(i sqrt(2a) z . dU)] over a standard normal z in 2D; z -> -z conjugates
+  // every cell value and leaves the (real) triangle averages unchanged, so the nodes with z_x > 0
+  // carry twice their weight
+  const double a = M_PI * M_PI * theta0_rad * theta0_rad / 3.0, t = std::sqrt(2.0 * a);
+  std::vector<double> z, w;
+  gauss_normal_rule(n_nodes, z, w);
+  std::vector<double> kn, wn;
+  for (int i = 0; i < n_nodes; ++i) {
+    if (!(z[i] > 0.0)) continue;
+    for (int j = 0; j < n_nodes; ++j) {
+      kn.push_back(t * z[i]);
+      kn.push_back(t * z[j]);
+      wn.push_back(2.0 * w[i] * w[j]);
+    }
+  }
+  const int nk = (int)wn.size();
+  // per-node cell averages phi_g(k) = mean over the cell's baselines of exp(i k . delta) (Eq. vg,
+  // phase mode of the gridding kernel), and the counts N_g
+  const size_t plane = (size_t)n * nh;
+  GridArgs g{};
+  g.uv = uv;
+  g.nvis = n_vis;
+  g.n = n;
+  g.nc = nk;
+  g.chan_avg = 1;
+  g.nco = nk;
+  g.du = du_lambda;
+  double* dk = static_cast<double*>(ctx_ws(c, "dec_k", (size_t)nk * 2 * sizeof(double)));
+  g.acc = static_cast<double*>(ctx_ws(c, "grid_acc", (size_t)nk * plane * 2 * sizeof(double)));
+  g.cnt = static_cast<int*>(ctx_ws(c, "grid_cnt", (size_t)nk * plane * sizeof(int)));
+  void* phi = ctx_ws(c, "dec_phi", (size_t)nk * plane * 2 * sizeof(double));
+  int32_t* ng32 = static_cast<int32_t*>(ctx_ws(c, "dec_ng32", (size_t)nk * plane * sizeof(int32_t)));
+  uint16_t* ng16 = static_cast<uint16_t*>(ctx_ws(c, "dec_ng16", plane * sizeof(uint16_t)));
+  double* dB = static_cast<double*>(ctx_ws(c, "dec_B", (size_t)std::max(ncand, 1) * sizeof(double)));
+  int64_t* dN = static_cast<int64_t*>(ctx_ws(c, "dec_N", (size_t)std::max(ncand, 1) * sizeof(int64_t)));
+  if (!dk || !g.acc || !g.cnt || !phi || !ng32 || !ng16 || !dB || !dN) return ctx_fail(c, BS_ENOMEM, "bs_decorrelation workspace");
+  g.knode = dk;
+  HIPCHK(c, hipMemcpyAsync(dk, kn.data(), kn.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_grid_zero(g, c->stream);
+  if (n_vis > 0) launch_grid_scatter(g, c->stream);
+  launch_grid_fin(g, true, phi, ng32, c->stream);
+  if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_decorrelation gridding");
+  // the counts do not depend on the node: N_g of node 0 as the per-cell weights (uint16)
+  std::vector<int32_t> hn(plane);
+  HIPCHK(c, hipMemcpyAsync(hn.data(), ng32, plane * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<uint16_t> h16(plane);
+  for (size_t i = 0; i < plane; ++i) {
+    if (hn[i] > 65535) return ctx_fail(c, BS_EINVAL, "bs_decorrelation: more than 65535 baselines in one grid cell");
+    h16[i] = (uint16_t)hn[i];
+  }
+  HIPCHK(c, hipMemcpyAsync(ng16, h16.data(), plane * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+  // one-channel ring bins of the same geometry
+  bs_bins_desc d{};
+  d.kind = BS_RING_U;
+  d.n = n;
+  d.nc = 1;
+  d.nbins = P.nbins;
+  d.edges_host = P.edges.data();
+  d.umax = P.umax;
+  bs_bins* b1 = nullptr;
+  int32_t nc1 = 0;
+  int rc = bs_make_bins(c, &d, &b1, &nc1);
+  if (rc) return rc;
+  std::vector<double> acc(ncand, 0.0), hb(ncand);
+  bs_weights wt{ng16, nullptr, nullptr};
+  for (int q = 0; q < nk && !rc; ++q) {
+    // mean over the closed grid triangles of prod phi (norm n^2: the estimator's B is that mean / n^2)
+    rc = bs_estimate_mabs(c, b1, static_cast<const char*>(phi) + (size_t)q * plane * 2 * sizeof(double), &wt, nullptr,
+                          BS_FP64, (double)n * (double)n, dB, dN, nullptr);
+    if (!rc && hipMemcpyAsync(hb.data(), dB, (size_t)ncand * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      rc = ctx_fail(c, BS_EHIP, "bs_decorrelation copy");
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = ctx_fail(c, BS_EHIP, "bs_decorrelation sync");
+    for (int tt = 0; !rc && tt < ncand; ++tt) acc[tt] += wn[q] * hb[tt];   // NaN (no triangle) propagates
+  }
+  bs_free_bins(b1);
+  if (rc) return rc;
+  for (int tt = 0; tt < ncand; ++tt) D_host[tt] = acc[tt];
+  return BS_OK;
+}
+
 // ------------------------------------------------------------------ MABS
 // Certified rounding bound (bsplan::count_error_bound) of the FP64 ring counts of triangles `tri`
 // ([n][3] bins): ring fields from a folded C2C along u and a C2R along v, two normalisations, and

@@ -277,6 +277,10 @@ struct GridArgs {
   long long nvis;
   int n, nc, chan_avg, nco;
   double du;
+  // phase mode (vis and flags unused, chan_avg 1): the value of baseline i in output channel o is
+  // exp(i k_o . delta_i), k_o = knode[2o], knode[2o+1] (radians per wavelength), delta_i = U_i - du q_i
+  // its offset from its grid point
+  const double* knode;
 };
 void launch_grid_zero(const GridArgs& a, hipStream_t s);
 void launch_grid_scatter(const GridArgs& a, hipStream_t s);

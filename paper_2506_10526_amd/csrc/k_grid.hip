@@ -57,7 +57,9 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
     }
     __syncthreads();
     for (long long i = vb + threadIdx.x; i < ve; i += GRID_THREADS) {
-      double qu = rint(a.uv[2 * i] / a.du), qv = rint(a.uv[2 * i + 1] / a.du);
+      const double U = a.uv[2 * i], Vb = a.uv[2 * i + 1];
+      double qu = rint(U / a.du), qv = rint(Vb / a.du);
+      const double du_off = U - a.du * qu, dv_off = Vb - a.du * qv;   // offset from the grid point
       const bool neg = qv < 0.0;
       if (neg) {
         qu = -qu;
@@ -67,7 +69,14 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
       const int iu = (int)qu, iv = (int)qv;
       double re = 0.0, im = 0.0;
       int c = 0;
-      for (int k = 0; k < a.chan_avg; ++k) {
+      if (a.knode) {   // phase mode: exp(i k_o . delta), conjugated for a reversed baseline
+        double sn, cs;
+        sincos(a.knode[2 * o] * du_off + a.knode[2 * o + 1] * dv_off, &sn, &cs);
+        re = cs;
+        im = neg ? -sn : sn;
+        c = 1;
+      }
+      for (int k = 0; !a.knode && k < a.chan_avg; ++k) {
         const long long j = (long long)(o * a.chan_avg + k) * a.nvis + i;
         if (a.flags && a.flags[j]) continue;
         const float2 v = vis[j];
