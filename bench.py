@@ -7,7 +7,10 @@ band), quadratic non-Gaussian field delta = g + 0.5 (g^2 - <g^2>) with P(k) ~ k^
 (483).  One step = one bs_estimate_3d call on a cube already resident in HBM: delay
 transform, shell-filtered 3D inverse transforms, the triple-product contraction and the
 normalisation (triangle counts depend only on the geometry and are cached after the
-first call).  The metric counts one product per valid triangle per voxel.
+first call).  The metric counts one product per valid triangle per voxel of the cube
+(`value`); the contraction itself runs on the exact 384-point delay grid, and the products it
+forms there are reported as `value_formed`.  `cpu_baseline` is the FP64 oracle on the whole step
+on up to 16 host threads (its single-thread figure on a bounded sample beside it).
 
 Also reported on the same cube: the plain FP32 path of the same step, and the MABS
 contraction on MFMA for 133 ring triples x 8 nu1 rows (768 x 768 x 65536 GEMMs); the 2D DFT of
@@ -59,6 +62,9 @@ def parse():
     p.add_argument("--no-mc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-surrogate", action="store_true")
+    p.add_argument("--full-mabs", action="store_true",
+                   help="only time the full MABS of the cube (all 133 ring triples x all 768^3 channel triples, "
+                        "ergodic collapse), unflagged and flagged, once each, and print that JSON line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     return p.parse_args()
@@ -83,6 +89,49 @@ def time_steps(fn, steps, warmup, torch):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def host_cpu_info():
+    """Cores this process may use and the CPU model (lscpu / /proc/cpuinfo)."""
+    info = {"nproc_affinity": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline_allcore(w, V, edges, gpu_B, gpu_T, threads):
+    """The FP64 oracle on the whole step of the same workload, its independent pieces run on
+    `threads` host threads (NumPy's FFTs and elementwise products release the GIL): the delay
+    transform, the 20 shell fields (one task per shell) and the triple sums of every candidate
+    triangle (one task per triangle).  Counts are excluded as on the GPU (cached per geometry):
+    B = N_vox S_D / T3D with the GPU's T3D, checked against the GPU's B."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import bins as ob
+    from oracle import estimator as oe
+    b = ob.make_bins(ob.SHELL_K, w.n, w.nc, edges, du=w.du, r_mpc=w.r_mpc, rprime=w.rprime, dnu=w.dnu)
+    Vh = V.astype(np.complex128)
+    t0 = time.perf_counter()
+    sf = oe.ShellFields(b, Vh)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(sf.data, range(b.nbins)))
+        S = np.array(list(ex.map(lambda t: float(np.sum(sf.data(t[0]) * sf.data(t[1]) * sf.data(t[2]))), b.triangles)))
+    dt = time.perf_counter() - t0
+    nvox = w.nc * w.n * w.n
+    ok = gpu_T > 0
+    Bref = np.where(ok, nvox * S / np.maximum(gpu_T, 1), np.nan)
+    err = np.abs(gpu_B[ok] - Bref[ok]) / np.abs(Bref[ok])
+    del sf
+    return {"value": int(ok.sum()) * nvox / dt, "unit": "products/s", "cores": threads, "kind": "oracle",
+            "seconds": dt,
+            "sample": (f"the whole step: float64 NumPy oracle, delay transform, 20 shell fields and all {len(b.triangles)} "
+                       f"candidate triangle sums on {threads} threads, counts excluded as on the GPU"),
+            "median_rel_err_vs_gpu": float(np.median(err)), "host": host_cpu_info()}
 
 
 def cpu_baseline(w, V, edges, gpu_B, tri_all):
@@ -392,6 +441,43 @@ def surrogate_block(bs, ctx, bins, ncand, w, torch):
             "rel_err_mc200_vs_mc1024": err(m200.var, j1.var), "mc200_seconds": m200.seconds}
 
 
+def full_mabs(bs, ctx, w, Vd, torch):
+    """The paper's own workload on the cube (Sec. 6: every combination of three rings and three
+    channels): all 133 valid ring triples x all 768^3 channel triples, split-BF16 contraction,
+    collapsed to (d1, d2) (non-circular, Sec. 3.2), once unflagged and once with channels
+    {0, 16, 31} of every 32 flagged (the counts then carry w1 w2 w3 and N_nu, Sec. 5 / Fig. 2)."""
+    from paper_2506_10526_amd import synth
+    redges = w.shell_edges(20) / (2 * np.pi * w.du / w.r_mpc)
+    rb, rcand = bs.bs_make_bins(ctx, bs.BS_RING_U, w.n, w.nc, redges)
+    D = 2 * w.nc - 1
+    B = torch.empty((rcand, D, D), dtype=torch.float64, device="cuda")
+    N = torch.empty((rcand, D, D), dtype=torch.int64, device="cuda")
+    Nn = torch.empty((rcand, D, D), dtype=torch.int32, device="cuda")
+    out = {"workload": f"{rcand} ring triples x all {w.nc}^3 channel triples of the {w.n}^2 x {w.nc} cube, split-BF16, "
+                       "ergodic collapse to (d1, d2)"}
+    for name, cw in (("unflagged", None), ("flagged", synth.mwa_flags(w.nc, (0, 16, 31)))):
+        kw = {} if cw is None else {"chan_w": torch.from_numpy(cw.astype(np.float32)).cuda()}
+        bs.bs_set_timing(ctx, True)
+        torch.cuda.synchronize()
+        log(f"[bench] full MABS {name}: {rcand} triples x {w.nc}^3 channel triples")
+        t0 = time.perf_counter()
+        bs.bs_estimate_mabs(ctx, rb, Vd, bs.BS_SPLIT_BF16, B, N, Nn, collapse=1, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tm = bs.bs_last_timing(ctx)
+        tperp_valid = int((N.view(rcand, -1) > 0).any(dim=1).sum().item())
+        prods = tperp_valid * float(w.nc) ** 3 * w.n * w.n
+        flops = 6.0 * rcand * float(w.nc) ** 3 * w.n * w.n
+        out[name] = {"seconds": dt, "contraction_s": tm[1] * 1e-3, "products": prods, "products_per_s": prods / dt,
+                     "mfma_TFLOPs_contraction": flops / (tm[1] * 1e-3) / 1e12,
+                     "frac_of_bf16_peak": flops / (tm[1] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                     "valid_triples": tperp_valid}
+        log(f"[bench] full MABS {name}: {dt:.2f} s, contraction {tm[1] * 1e-3:.2f} s, "
+            f"{out[name]['mfma_TFLOPs_contraction']:.0f} TFLOP/s")
+    bs.bs_free_bins(rb)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -417,6 +503,10 @@ def main():
     Vd = torch.empty((w.nc, w.n, w.nh), dtype=torch.complex64, device=dev)
     bs.bs_generate_cube(ctx, gdesc, args.seed, 0, Vd)
     torch.cuda.synchronize()
+    if args.full_mabs:
+        print(json.dumps(full_mabs(bs, ctx, w, Vd, torch)))
+        bs.bs_destroy(ctx)
+        return
     bins, ncand = bs.bs_make_bins(ctx, bs.BS_SHELL_K, w.n, w.nc, edges, du_lambda=w.du, r_mpc=w.r_mpc,
                                   rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
     tri, modes = bs.bs_bins_triangles(bins, ncand, 20)
@@ -439,6 +529,7 @@ def main():
     Bs = B.cpu().numpy().copy()
     Nt = N.cpu().numpy().copy()
     count_dev = bs.bs_last_count_dev(ctx)
+    count_bound = bs.bs_last_count_bound(ctx)
     log(f"[bench] triangle counts: max |x - rint(x)| = {count_dev:.3e}, max count {Nt.max():.3e}")
     n_valid = int(np.count_nonzero(Nt))
     products = n_valid * nvox
@@ -464,17 +555,30 @@ def main():
     # voxel (reported by the library): 3 bf16 products x 2 flops x 2 (H_j + 1) real modes per
     # field for the synthesis, 3 x 2 x P x F for the contraction (P product rows, F fields), on
     # the M n^2 voxels of the M-point delay grid.
+    # Dominant kernel of the split step: k3_dft (eta synthesis of every shell field on MFMA fused
+    # with the pair x field contraction).  Priced on the unit of the hot-path scope: the shell
+    # fields are read once per voxel, F x 4 bytes (FP32) per voxel of the M-point delay grid
+    # (F = 20 non-empty shells, 80 B), HBM-bound; beside it the MFMA view at the method's own
+    # split-BF16 work (3 bf16 products = 6 flops per valid triangle per voxel) and the dense
+    # equivalent the kernel executes (whole 16-mode steps and 16 x 16 tiles).
     M = int(tim_split[3]) or w.nc
-    flops_per_vox = tim_split[4]
+    flops_exec = tim_split[4]
     vox_c = int(tim_split[5]) or M * w.n * w.n
     con_ms = tim_split[1]
     fld_ms = tim_split[2]
-    ach = flops_per_vox * vox_c / (con_ms * 1e-3) / 1e12
-    roof = {"bound": "mfma", "kernel": "k3_dft (eta synthesis + contraction, split-BF16 MFMA)", "achieved": ach,
-            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
-            "traffic": TRAFFIC_BYTES.get("k3_dft"), "algorithmic_flops_per_voxel": float(flops_per_vox), "voxels_per_launch": vox_c,
-            "delay_grid_M": M, "avg_ms": con_ms,
-            "fields_kernels_ms": fld_ms}
+    nfields = int(np.count_nonzero(modes))
+    byt = 4.0 * nfields * vox_c
+    ach = byt / (con_ms * 1e-3) / 1e9
+    meth_flops = 6.0 * n_valid * vox_c
+    roof = {"bound": "hbm", "kernel": "k3_dft (eta synthesis + contraction, split-BF16 MFMA)", "achieved": ach,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": TRAFFIC_BYTES.get("k3_dft"), "algorithmic_bytes_per_voxel": 4.0 * nfields,
+            "voxels_per_launch": vox_c, "delay_grid_M": M, "avg_ms": con_ms, "fields_kernels_ms": fld_ms,
+            "mfma_view": {"method_flops_per_voxel": 6.0 * n_valid,
+                          "achieved_TFLOPs": meth_flops / (con_ms * 1e-3) / 1e12,
+                          "frac_of_bf16_peak": meth_flops / (con_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                          "executed_dense_equivalent_flops_per_voxel": float(flops_exec),
+                          "executed_TFLOPs": flops_exec * vox_c / (con_ms * 1e-3) / 1e12}}
     mabs = None
     if not args.no_mabs:
         log("[bench] MABS contraction: 133 ring triples x 8 nu1 rows")
@@ -537,12 +641,18 @@ def main():
         log(f"[bench] surrogate: {sur['rel_err_vs_mc1024_training_pattern']}, unseen {sur['rel_err_vs_mc1024_unseen_pattern']}")
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w, Vd.cpu().numpy(), edges, Bs, tri)
+        Vh = Vd.cpu().numpy()
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"[bench] CPU oracle baseline: the whole step on {threads} threads")
+        cpu = cpu_baseline_allcore(w, Vh, edges, Bs, Nt, threads)
+        log(f"[bench] CPU oracle: {cpu['seconds']:.1f} s on {threads} threads")
+        log("[bench] CPU oracle baseline: single thread (bounded sample)")
+        cpu["single_thread"] = cpu_baseline(w, Vh, edges, Bs, tri)
     out = {
         "metric": "bin-triangle·voxel products/s, split-BF16 MFMA vs FP32 at ≤1e-4 rel err",
         "value": products / t_split,
         "unit": "products/s",
+        "value_formed": n_valid * vox_c / t_split,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -556,7 +666,8 @@ def main():
                                "0.003-1.258 Mpc^-1, all k1>=k2>=k3 candidates",
                    "triangles_candidate": int(ncand), "triangles_valid": n_valid, "voxels": nvox,
                    "products_per_step": products, "parallelism": "single GPU",
-                   "count_max_dev_from_integer": count_dev},
+                   "products_formed_per_step": n_valid * vox_c,
+                   "count_max_dev_from_integer": count_dev, "count_error_bound": count_bound},
         "roofline": roof,
         "kernel_ms": {"step_events": tim_split[0], "contraction": tim_split[1], "fields": tim_split[2]},
         "fp32": fp32,

@@ -29,7 +29,7 @@ from gpu_common import Ctx, compare_B, cuda, host, torch, vis_tensor
 
 pytestmark = pytest.mark.gpu
 
-TOL = {bs.BS_FP32: 1e-5, bs.BS_SPLIT_BF16: 1e-4}
+TOL = {bs.BS_FP64: 1e-10, bs.BS_FP32: 1e-5, bs.BS_SPLIT_BF16: 1e-4}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "mwa256x768_3d.json")
 
 
@@ -111,7 +111,7 @@ def _golden():
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("cube", ["unflagged", "flagged"])
 def test_mwa_full_cube_matches_golden(ctx, cube):
-    """All 483 candidate triangles of the 256^2 x 768 cube in FP32 and split-BF16: T3D equal to the
+    """All 483 candidate triangles of the 256^2 x 768 cube in FP64, FP32 and split-BF16: T3D equal to the
     exact integer counts, N_eff = T3D rho3, B per triangle against the FP64 oracle."""
     g = _golden()
     gc = g["cubes"][cube]
@@ -128,14 +128,15 @@ def test_mwa_full_cube_matches_golden(ctx, cube):
     try:
         tri, _ = bs.bs_bins_triangles(h, ncand, 20)
         assert np.array_equal(tri, np.asarray(g["triangles"], dtype=np.int32))
-        for prec in (bs.BS_FP32, bs.BS_SPLIT_BF16):
+        for prec in (bs.BS_FP64, bs.BS_FP32, bs.BS_SPLIT_BF16):
             bs.bs_set_timing(ctx, 1)
             Bg, Tg, Eg = run3(ctx, h, V, prec, ncand, w.chan_w() if gc["flags_mod32"] else None)
             tm = bs.bs_last_timing(ctx)
             bs.bs_set_timing(ctx, 0)
             dev, bound = bs.bs_last_count_dev(ctx), bs.bs_last_count_bound(ctx)
             print(f"[mwa full {cube} prec={prec}] count dev {dev:.3g} bound {bound:.3g} M={tm[3]:.0f}", flush=True)
-            assert tm[3] == 384
+            if prec != bs.BS_FP64:   # the FP64 path contracts materialised fields on the 768-point grid
+                assert tm[3] == 384
             assert 0.0 <= dev <= bound < 0.5
             assert np.array_equal(Tg, Texact)
             assert np.array_equal(Eg, Nref)
