@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--no-mabs", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-mabs-dft", action="store_true")
+    p.add_argument("--no-mabs-fp32", action="store_true", help="MABS block in split-BF16 only")
     p.add_argument("--no-grid", action="store_true")
     p.add_argument("--no-mc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
@@ -588,7 +589,8 @@ def main():
         Bm = torch.empty((rcand, len(nu1), w.nc, w.nc), dtype=torch.float64, device=dev)
         Nm = torch.empty((rcand, len(nu1), w.nc, w.nc), dtype=torch.int64, device=dev)
         res = {}
-        for name, prec in (("split_bf16", bs.BS_SPLIT_BF16), ("fp32", bs.BS_FP32)):
+        precs = (("split_bf16", bs.BS_SPLIT_BF16),) + (() if args.no_mabs_fp32 else (("fp32", bs.BS_FP32),))
+        for name, prec in precs:
             f = lambda: bs.bs_estimate_mabs(ctx, rb, Vd, prec, Bm, Nm, nu1=nu1)
             tt = time_steps(f, 2, 1, torch)
             tm = bs.bs_last_timing(ctx)
@@ -603,7 +605,8 @@ def main():
                          "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                                       "frac": ach / peak, "mfma_flops_per_launch": flops}}
             log(f"[bench] mabs {name}: {tt * 1e3:.1f} ms/call, contraction {tm[1]:.1f} ms, {ach:.0f} TFLOP/s")
-        res["split_over_fp32"] = res["fp32"]["contraction_ms"] / res["split_bf16"]["contraction_ms"]
+        if "fp32" in res:
+            res["split_over_fp32"] = res["fp32"]["contraction_ms"] / res["split_bf16"]["contraction_ms"]
         res["workload"] = "133 ring triples (10 rings, k_perp of the 20 shells) x nu1 in {0,96,...,672} x all (nu2, nu3)"
         mabs = res
         bs.bs_free_bins(rb)

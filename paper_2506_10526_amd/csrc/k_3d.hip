@@ -34,6 +34,12 @@ typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t dft_pk(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x, y}, bf16x2_t));
 }
+// Split of two floats into packed bf16 hi = rne(x) and lo = rne(x - hi) (x in the low halves);
+// x - hi is exact (hi lies within a factor two of x and shares its grid).
+__device__ __forceinline__ void dft_split2(float x, float y, uint32_t& hp, uint32_t& lp) {
+  hp = dft_pk(x, y);
+  lp = dft_pk(x - __builtin_bit_cast(float, hp << 16), y - __builtin_bit_cast(float, hp & 0xffff0000u));
+}
 
 // --------------------------------------------------------------- delay transform
 // Vt(eta, U) = sum_nu w(nu) m(U) V(U, nu) e^{-2 pi i eta nu / nc}, with the v = 0 column
@@ -238,8 +244,7 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
             re = z.x * (dc ? sc : 2.f * sc);
             im = dc ? 0.f : z.y * (2.f * sc);
           }
-          hw[c] = dft_pk(re, im);
-          lw[c] = dft_pk(re - __builtin_bit_cast(float, hw[c] << 16), im - __builtin_bit_cast(float, hw[c] & 0xffff0000u));
+          dft_split2(re, im, hw[c], lw[c]);
         }
         uint4* o = out + ((size_t)(xv * nxub + xub) * S + s) * 128;
         o[lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
@@ -306,9 +311,7 @@ __device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& l) {
   uint32_t hw[4], lw[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    hw[q] = dft_pk(v[2 * q], v[2 * q + 1]);
-    const float h0 = __builtin_bit_cast(float, hw[q] << 16), h1 = __builtin_bit_cast(float, hw[q] & 0xffff0000u);
-    lw[q] = dft_pk(v[2 * q] - h0, v[2 * q + 1] - h1);
+    dft_split2(v[2 * q], v[2 * q + 1], hw[q], lw[q]);
   }
   h = __builtin_bit_cast(bf16x8, v4u_t{hw[0], hw[1], hw[2], hw[3]});
   l = __builtin_bit_cast(bf16x8, v4u_t{lw[0], lw[1], lw[2], lw[3]});
@@ -821,8 +824,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float cs = wv[c].x, sn = -wv[c].y;
-            hw[c] = dft_pk(cs, sn);
-            lw[c] = dft_pk(cs - __builtin_bit_cast(float, hw[c] << 16), sn - __builtin_bit_cast(float, hw[c] & 0xffff0000u));
+            dft_split2(cs, sn, hw[c], lw[c]);
           }
           const bf16x8 wh = __builtin_bit_cast(bf16x8, v4u_t{hw[0], hw[1], hw[2], hw[3]});
           const bf16x8 wl = __builtin_bit_cast(bf16x8, v4u_t{lw[0], lw[1], lw[2], lw[3]});

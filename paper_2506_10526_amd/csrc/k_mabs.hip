@@ -140,6 +140,12 @@ typedef float f32x2_m __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t bf16_pk(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_m{x, y}, bf16x2_m));
 }
+// hi = rne(x), lo = rne(x - hi) for two floats, packed (x in the low halves); x - hi is exact
+// (hi lies within a factor two of x and shares its grid).
+__device__ __forceinline__ void bf16_split2(float x, float y, uint32_t& hp, uint32_t& lp) {
+  hp = bf16_pk(x, y);
+  lp = bf16_pk(x - __builtin_bit_cast(float, hp << 16), y - __builtin_bit_cast(float, hp & 0xffff0000u));
+}
 
 __global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ F, uint16_t* __restrict__ hi,
                                                       uint16_t* __restrict__ lo, long long n) {
@@ -349,9 +355,10 @@ __global__ __launch_bounds__(256) void k_mabs_gemm(MabsGemmArgs a) {
 // ---------------------------------------------------------------------------
 // Split-BF16 contraction, large tiles.  Block tile 128 x 256 (rows R = i*nc + nu2, columns nu3),
 // four waves of 64 x 128 (2 x 4 MFMA 32x32x16 tiles, 128 FP32 accumulators per lane), pixel
-// stages of 32 in two LDS buffers, software-pipelined around the MFMAs:
-//  * the pre-split B rows (bf16 hi/lo of F_b3) of stage s+1 go from global memory straight into
-//    the other LDS buffer with 16-byte global_load_lds, issued during stage s;
+// stages of 32 in three LDS buffers, software-pipelined around the MFMAs:
+//  * the pre-split B rows (bf16 hi/lo of F_b3) of stage s+2 go from global memory straight into
+//    the buffer of stage s+2 with 16-byte global_load_lds, issued during stage s, so a copy has two
+//    stages to land;
 //  * the F1 and F2 values of stage s+2 are loaded into registers during stage s, and the A
 //    operand of stage s+1 (A = F_b1(nu1) .* F_b2(nu2), split into bf16 hi/lo) is formed from
 //    the registers loaded one stage earlier and written into the other buffer, interleaved with
@@ -359,7 +366,8 @@ __global__ __launch_bounds__(256) void k_mabs_gemm(MabsGemmArgs a) {
 //  * the fragments of the second half of a stage are read while the first half's MFMAs run,
 //    and the last twelve MFMAs of a stage are issued after the stage barrier, covering the
 //    reads of the next stage's first fragments.
-// Each stage ends with a wait for all of this wave's memory operations and one barrier.  LDS rows
+// Each stage ends with a wait for this wave's LDS operations and for its global loads except the
+// 16 issued in this stage (the copies and loads of stage s+2), and one barrier.  LDS rows
 // hold 32 bf16 as four 16-byte chunks XOR-swizzled by row.  The block's FP32 tile is added into
 // its FP64 output every SFLUSH pixels.  Blocks are mapped to tiles so that tiles sharing a B
 // column block and neighbouring A rows run on the same XCD (blocks are dealt to the eight XCDs
@@ -369,6 +377,11 @@ constexpr int S_TM = 128, S_TN = 256, S_TK = 32, SFLUSH = 8192;
 // uint16 offsets inside one stage buffer
 constexpr int S_AH = 0, S_AL = S_TM * S_TK, S_BH = 2 * S_TM * S_TK, S_BL = S_BH + S_TN * S_TK;
 constexpr int S_BUF = S_BL + S_TN * S_TK;
+constexpr int S_NBUF = 3;   // stage buffers in LDS (147,456 bytes)
+// s_waitcnt encoding (gfx9 family): vmcnt(16) lgkmcnt(0), expcnt not waited for
+constexpr int S_WAIT_VM16_LGKM0 = (16 & 15) | ((16 >> 4) << 14) | (7 << 4) | (0 << 8);
+// vmcnt(16) alone (expcnt and lgkmcnt not waited for)
+constexpr int S_WAIT_VM16 = (16 & 15) | ((16 >> 4) << 14) | (7 << 4) | (15 << 8);
 
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(3))) const char lds_cchar;
@@ -385,7 +398,7 @@ struct SplitFrags {
 // One block tile of GEMM `a`; b0 is the block's index within this GEMM's nb = rtiles ctiles ntri
 // kchunks blocks.
 __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
-  uint16_t* lds = (uint16_t*)smem_raw;   // [2][S_BUF]
+  uint16_t* lds = (uint16_t*)smem_raw;   // [S_NBUF][S_BUF]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int nrows = a.n_nu1 * a.nc;
@@ -408,11 +421,11 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   const int nst = (kend - kbeg) / S_TK;   // >= 1; pixel ranges are multiples of S_TK
   const int klast = kend - S_TK;          // loads past the range re-read the last stage
 
-  // A operand: thread (ar, ahalf) owns row ar, pixels ahalf .. ahalf+15 of each stage
+  // A operand: thread (ar, ahalf) owns row ar, pixels ahalf .. ahalf+15 of each stage; rows past
+  // the last repeat it (their output rows are never stored)
   const int ar = tid >> 1, ahalf = (tid & 1) * 16;
   const int R = row0 + ar;
-  const bool rok = R < nrows;
-  const int Rc = rok ? R : nrows - 1;
+  const int Rc = R < nrows ? R : nrows - 1;
   const int ia = Rc / a.nc, nu2 = Rc - ia * a.nc;
   const float* f1 = a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[ia] * a.P + ahalf;
   const float* f2 = a.F + (size_t)b2 * a.bin_stride + (size_t)nu2 * a.P + ahalf;
@@ -459,11 +472,10 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   auto form1 = [&](int m, const float4* p1, const float4* p2, uint32_t (&hw)[2][4], uint32_t (&lw)[2][4]) {
     const int g = m >> 1, u = (m & 1) * 2;   // float4 index, component
     const float4 x = p1[g], y = p2[g];
-    const float v0 = u ? x.z * y.z : x.x * y.x;
-    const float v1 = u ? x.w * y.w : x.y * y.y;
-    const float w0 = rok ? v0 : 0.f, w1 = rok ? v1 : 0.f;
-    const uint32_t hp = bf16_pk(w0, w1);
-    const uint32_t lp = bf16_pk(w0 - __builtin_bit_cast(float, hp << 16), w1 - __builtin_bit_cast(float, hp & 0xffff0000u));
+    const float w0 = u ? x.z * y.z : x.x * y.x;
+    const float w1 = u ? x.w * y.w : x.y * y.y;
+    uint32_t hp, lp;
+    bf16_split2(w0, w1, hp, lp);
     hw[g >> 1][(g & 1) * 2 + (u >> 1)] = hp;
     lw[g >> 1][(g & 1) * 2 + (u >> 1)] = lp;
   };
@@ -555,34 +567,41 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   zero_frags(F1);   // the first stage's deferred MFMAs add zeros
   float4 P[2][2][4];   // [set][F1 / F2][4]: register-staged A inputs, set = stage parity
 
-  // prologue: stage 0 into buffer 0, registers of stage 1 in flight
+  // prologue: stage 0 into buffer 0, the B rows of stage 1 into buffer 1, registers of stage 1
 #pragma unroll
   for (int m = 0; m < 8; ++m) copy_b1(m, kbeg, lds);
 #pragma unroll
   for (int m = 0; m < 8; ++m) load_a1(m, kbeg, P[0][0], P[0][1]);
 #pragma unroll
   for (int m = 0; m < 8; ++m) load_a1(m, min(kbeg + S_TK, klast), P[1][0], P[1][1]);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) copy_b1(m, min(kbeg + S_TK, klast), lds + S_BUF);
   form(P[0][0], P[0][1], lds);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
   read_frags(F0, lds, 0);
 
-  // Stage s (buffer s&1, its kk = 0 fragments in F0, the deferred MFMAs of stage s-1 in F1), as
-  // 48 issue slots of one MFMA each plus, in program order: the B copies of stage s+1 and the
-  // register loads of stage s+2 (slots 0-11), the kk = 1 fragment reads (12-23), the A formation
-  // of stage s+1 (24-33); sched_barrier keeps every slot's instructions in place.
+  // Stage s (buffer s mod 3, its kk = 0 fragments in F0, the deferred MFMAs of stage s-1 in F1),
+  // as 48 issue slots of one MFMA each plus, in program order: the B copies and the register loads
+  // of stage s+2 (slots 0-11), the kk = 1 fragment reads (12-23), the A formation of stage s+1
+  // (24-33); sched_barrier keeps every slot's instructions in place.  The buffer of stage s+2 was
+  // last read in stage s-1 and that of stage s+1 in stage s-2, both before a barrier.
   auto stage = [&](int s, auto par) {
     constexpr int PAR = decltype(par)::value;
-    uint16_t* cur = lds + PAR * S_BUF;
-    uint16_t* nxt = lds + (PAR ^ 1) * S_BUF;
-    const int kb = min(kbeg + (s + 1) * S_TK, klast), ka = min(kbeg + (s + 2) * S_TK, klast);
+    const int b0i = s % S_NBUF, b1i = b0i + 1 == S_NBUF ? 0 : b0i + 1, b2i = b1i + 1 == S_NBUF ? 0 : b1i + 1;
+    uint16_t* cur = lds + b0i * S_BUF;
+    uint16_t* nxt = lds + b1i * S_BUF;
+    uint16_t* nx2 = lds + b2i * S_BUF;
+    // wave-uniform: kept in a scalar register (a vector temporary here can be the destination of
+    // a load still in flight, which would force a wait for every load)
+    const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 2) * S_TK, klast)), ka = kb;
     uint32_t hw[2][4], lw[2][4];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
       mfma1(F1, 12 + m);   // deferred, stage s-1
       if (m < 8) {
-        copy_b1(m, kb, nxt);
+        copy_b1(m, kb, nx2);
       } else {
         load_a1(2 * (m - 8), ka, P[PAR][0], P[PAR][1]);
         load_a1(2 * (m - 8) + 1, ka, P[PAR][0], P[PAR][1]);
@@ -593,6 +612,9 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
     for (int m = 0; m < 24; ++m) {
       mfma1(F0, m);
       if (m < 12) read_frag1(F1, cur, 1, m);
+      // the registers of stage s+1 were loaded in stage s-1; only this stage's 16 loads may still
+      // be in flight (without this the compiler waits for all of them before the formation)
+      if (m == 11) __builtin_amdgcn_s_waitcnt(S_WAIT_VM16);
       else if (m < 20) form1(m - 12, P[PAR ^ 1][0], P[PAR ^ 1][1], hw, lw);
       else if (m < 22) store_a(m - 20, hw, lw, nxt);
       __builtin_amdgcn_sched_barrier(0);
@@ -602,7 +624,9 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
       mfma1(F1, m);
       __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_s_waitcnt(0);   // B of stage s+1 and the registers of stage s+2 landed, A stored
+    // B of stage s+1 landed (copied during stage s-1), A of stage s+1 stored; the 16 loads of
+    // stage s+2 issued in this stage stay in flight
+    __builtin_amdgcn_s_waitcnt(S_WAIT_VM16_LGKM0);
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
     read_frags(F0, nxt, 0);
@@ -875,7 +899,7 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
   }
   const int nrows = a.n_nu1 * a.nc;
   const long long nb = (long long)((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
-  const size_t lds = 2 * (size_t)S_BUF * 2;
+  const size_t lds = S_NBUF * (size_t)S_BUF * 2;
   (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_mabs_gemm_split2, dim3((unsigned)nb), dim3(256), lds, s, a);
 }
@@ -886,7 +910,7 @@ int mabs_split_blocks(const MabsGemmArgs& a) {
 void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* offs_dev, int ngroups, int nblocks,
                                     hipStream_t s) {
   if (nblocks <= 0) return;
-  const size_t lds = 2 * (size_t)S_BUF * 2;
+  const size_t lds = S_NBUF * (size_t)S_BUF * 2;
   (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_mabs_gemm_split2_grouped, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
 }
