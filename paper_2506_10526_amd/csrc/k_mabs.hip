@@ -653,6 +653,319 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
   split2_tile(a, blockIdx.x, smem_raw);
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 contraction, 256 x 192 tiles.  Rows are tiled as (nu1 block of m1) x (nu2 block of
+// m2), m1 m2 = 256 (m1 = 16, 8 or 4): the A tile is formed from m1 + m2 loaded field rows
+// (F_b1(nu1) and F_b2(nu2)) instead of one row per A row.  Four waves of 128 x 96 (4 x 3 MFMA
+// 32x32x16 tiles, 192 FP32 accumulators per lane), pixel stages of 32 in two LDS stage buffers
+// (A and B hi/lo, 56 KB each) and two raw buffers of the m1 + m2 FP32 input rows:
+//  * the B rows of stage s+1 (pre-split F_b3) and the raw rows of stage s+2 are copied from
+//    global memory straight into LDS (16-byte global_load_lds) at the start of stage s;
+//  * the A operand of stage s+1 is formed from the raw rows of stage s+1 (products F1 F2 split
+//    into bf16 hi / lo) and stored into the other stage buffer during stage s;
+//  * one set of fragments: each kind (A lo / hi, B hi / lo) is reloaded for the next half stage as
+//    soon as its last MFMA has issued, and the last 16 MFMAs of a stage are issued at the start of
+//    the next one, covering the reads of its first fragments.
+// Each stage ends with a wait for all of this wave's memory operations and one barrier.  Per MFMA
+// this moves about a fifth less data through LDS than 128 x 256 tiles with 64 x 128 per wave, and
+// the A inputs a fifth of the bytes.  (128 x 128 per wave, 256 accumulators, does not fit the
+// register file without spills.)
+// ---------------------------------------------------------------------------
+constexpr int T3_NJ = 3;   // 32-column MFMA tiles per wave
+constexpr int T3_M = 256, T3_N = 64 * T3_NJ, T3_K = 32, T3_FLUSH = 8192;
+constexpr int T3_AH = 0, T3_AL = T3_M * T3_K, T3_BH = 2 * T3_M * T3_K, T3_BL = T3_BH + T3_N * T3_K;
+constexpr int T3_BUF = T3_BL + T3_N * T3_K;   // uint16 per stage buffer (56 KB)
+constexpr int T3_RAWLD = 36;                   // floats per raw row: 8 data chunks + 1 pad (bank spread)
+constexpr int T3_RAWMAX = 4 + 64;              // raw rows m1 + m2 at most
+constexpr int T3_RAW = T3_RAWMAX * T3_RAWLD;   // floats per raw buffer
+constexpr size_t T3_LDS = 2 * (size_t)T3_BUF * 2 + 2 * (size_t)T3_RAW * 4;
+
+
+__device__ __forceinline__ int t3_m1(int n_nu1) { return n_nu1 >= 16 ? 16 : (n_nu1 >= 8 ? 8 : 4); }
+
+__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
+  uint16_t* lds = (uint16_t*)smem_raw;                          // [2][T3_BUF]
+  float* raws = (float*)(smem_raw + 2 * (size_t)T3_BUF * 2);    // [2][T3_RAW]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m1 = t3_m1(a.n_nu1), m2 = T3_M / m1, lm2 = __builtin_ctz(m2);
+  const int r1t = (a.n_nu1 + m1 - 1) / m1, r2t = (a.nc + m2 - 1) / m2, rtiles = r1t * r2t;
+  const int ctiles = (a.nc + T3_N - 1) / T3_N;
+  const int nb = rtiles * ctiles * a.ntri * a.kchunks;
+  // XCD-aware remap of the linear block id (blocks are dealt to the eight XCDs round-robin): the
+  // row tiles of one (column tile, triangle, pixel chunk), which share B, run on one XCD
+  int b = b0;
+  const int full = (nb / 8) * 8;
+  if (b < full) b = (b & 7) * (full / 8) + (b >> 3);
+  const int rt = b % rtiles;
+  int rest = b / rtiles;
+  const int ct = rest % ctiles;
+  rest /= ctiles;
+  const int kc = rest % a.kchunks;
+  const int t = rest / a.kchunks;
+  const int i0 = (rt / r2t) * m1, n20 = (rt % r2t) * m2, col0 = ct * T3_N;
+  const int b1 = a.tri[3 * t], b2 = a.tri[3 * t + 1], b3 = a.tri[3 * t + 2];
+  const int kbeg = __builtin_amdgcn_readfirstlane(kc * a.kchunk);
+  const int kend = __builtin_amdgcn_readfirstlane(min(a.P, kbeg + a.kchunk));
+  const int nst = (kend - kbeg) / T3_K;   // >= 1; pixel ranges are multiples of T3_K
+  const int klast = kend - T3_K;          // copies past the range re-read the last stage
+
+  // raw copies: chunk g of (m1 + m2) x 9 (row q = g / 9, chunk c = g % 9, the ninth a pad that
+  // re-reads chunk 0); rows q < m1 are F_b1 at nu1[i0 + q], the rest F_b2 at nu2 = n20 + q - m1,
+  // clamped to the last valid row (their products are never stored)
+  const int nraw = (m1 + m2) * 9;
+  const int nri = (nraw + 63) / 64;       // copy instructions per stage, dealt to the waves
+  const float* rsrc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int g = (wave + 4 * k) * 64 + lane;
+    const int q = min(g / 9, m1 + m2 - 1), c = g % 9 == 8 ? 0 : g % 9;
+    const float* row = q < m1 ? a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[min(i0 + q, a.n_nu1 - 1)] * a.P
+                              : a.F + (size_t)b2 * a.bin_stride + (size_t)min(n20 + q - m1, a.nc - 1) * a.P;
+    rsrc[k] = row + 4 * c;
+  }
+  // B copies: this wave's columns w*16NJ .. w*16NJ+16NJ-1, 16 per instruction, hi then lo
+  size_t boff[T3_NJ];
+#pragma unroll
+  for (int q = 0; q < T3_NJ; ++q) {
+    const int br = wave * 16 * T3_NJ + q * 16 + (lane >> 2);
+    const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
+    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 8 * swz(br, lane & 3);
+  }
+  // A formation: thread r = tid owns tile row r = (i1, i2), i2 = r mod m2
+  const int fr = tid, fi1 = fr >> lm2, fi2 = fr & (m2 - 1);
+  const int rawf1 = fi1 * T3_RAWLD, rawf2 = (m1 + fi2) * T3_RAWLD;
+  // fragment offsets (uint16, inside a stage buffer) per half-stage kk
+  int oa[2][4], ob[2][T3_NJ];
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int chunk = kk * 2 + (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 128 + i * 32 + (lane & 31);
+      oa[kk][i] = r * T3_K + swz(r, chunk) * 8;
+    }
+#pragma unroll
+    for (int j = 0; j < T3_NJ; ++j) {
+      const int c = wn * 32 * T3_NJ + j * 32 + (lane & 31);
+      ob[kk][j] = c * T3_K + swz(c, chunk) * 8;
+    }
+  }
+
+  auto copy_b1 = [&](int m, int k0, uint16_t* buf) {   // copy m of 2 NJ: columns q = m/2, hi or lo
+    const int q = m >> 1;
+    __builtin_amdgcn_global_load_lds((const void*)((m & 1 ? a.Fl : a.Fh) + boff[q] + k0),
+                                     (lds_void*)(buf + (m & 1 ? T3_BL : T3_BH) + (wave * 16 * T3_NJ + q * 16) * T3_K),
+                                     16, 0, 0);
+  };
+  auto copy_raw1 = [&](int k, int k0, float* rb) {    // raw copy instruction wave + 4 k
+    const int ins = wave + 4 * k;
+    if (ins < nri) {
+      if (ins * 64 + lane < nraw)
+        __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + ins * 256), 16, 0, 0);
+    }
+  };
+  // A formation piece pc of 4 (pixels 8 pc .. 8 pc + 7 of row fr): the raw reads (into R[pc]) are
+  // issued several MFMA slots before the products, splits and stores that use them
+  float4 R[4][4];
+  auto form_read = [&](int pc, const float* rb) {
+    R[pc][0] = *(const float4*)&rb[rawf1 + 8 * pc];
+    R[pc][1] = *(const float4*)&rb[rawf1 + 8 * pc + 4];
+    R[pc][2] = *(const float4*)&rb[rawf2 + 8 * pc];
+    R[pc][3] = *(const float4*)&rb[rawf2 + 8 * pc + 4];
+  };
+  auto form_store = [&](int pc, uint16_t* buf) {
+    const float4 x0 = R[pc][0], x1 = R[pc][1], y0 = R[pc][2], y1 = R[pc][3];
+    uint32_t hw[4], lw[4];
+    bf16_split2(x0.x * y0.x, x0.y * y0.y, hw[0], lw[0]);
+    bf16_split2(x0.z * y0.z, x0.w * y0.w, hw[1], lw[1]);
+    bf16_split2(x1.x * y1.x, x1.y * y1.y, hw[2], lw[2]);
+    bf16_split2(x1.z * y1.z, x1.w * y1.w, hw[3], lw[3]);
+    const v4u h = {hw[0], hw[1], hw[2], hw[3]};
+    const v4u l = {lw[0], lw[1], lw[2], lw[3]};
+    // written in asm: the compiler cannot tell these stores from the copies into the same buffer
+    // and would otherwise wait for every copy in flight; they touch only the A region, and the
+    // wait at the end of the stage covers their completion
+    asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:%3"
+                 :
+                 : "v"(lds_addr(buf + T3_AH + fr * T3_K + swz(fr, pc) * 8)), "v"(h), "v"(l), "n"(2 * (T3_AL - T3_AH))
+                 : "memory");
+  };
+  auto form_piece = [&](int pc, const float* rb, uint16_t* buf) {
+    form_read(pc, rb);
+    form_store(pc, buf);
+  };
+  // One set of fragments (A lo / hi of four 32-row tiles, B hi / lo of NJ 32-column tiles): each
+  // kind is reloaded for the next half stage as soon as its last MFMA of the current one has issued.
+  bf16x8 fal[4], fah[4], fbh[T3_NJ], fbl[T3_NJ];
+  // read kind w (0: A lo, 1: A hi, 2: B hi, 3: B lo) of tile i for half stage kk from buf
+  auto read1 = [&](int w, int i, const uint16_t* buf, int kk) {
+    if (w == 0) fal[i] = *(const bf16x8*)&buf[T3_AL + oa[kk][i]];
+    else if (w == 1) fah[i] = *(const bf16x8*)&buf[T3_AH + oa[kk][i]];
+    else if (w == 2) fbh[i] = *(const bf16x8*)&buf[T3_BH + ob[kk][i]];
+    else fbl[i] = *(const bf16x8*)&buf[T3_BL + ob[kk][i]];
+  };
+
+  f32x16 acc[4][T3_NJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < T3_NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  constexpr int G = 4 * T3_NJ;   // MFMAs of a product group
+  // MFMA m of G of product group p (0: A lo B hi, 1: A hi B lo, 2: A hi B hi) over the 4 x NJ tiles
+  auto mfma1 = [&](int p, int m) {
+    const int i = m / T3_NJ, j = m % T3_NJ;
+    const bf16x8 x = p == 0 ? fal[i] : fah[i];
+    const bf16x8 y = p == 1 ? fbl[j] : fbh[j];
+    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc[i][j], 0, 0, 0);
+  };
+
+  const int nrows = a.n_nu1 * a.nc;
+  double* S = a.S + ((size_t)kc * a.ntri + t) * (size_t)nrows * a.nc;
+  bool first_flush = true;
+  auto flush = [&]() {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < T3_NJ; ++j) {
+        const int col = col0 + wn * 32 * T3_NJ + j * 32 + (ln & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int r = wm * 128 + i * 32 + (e >> 2) * 8 + (ln >> 5) * 4 + (e & 3);
+          const int ii = i0 + (r >> lm2), nu2 = n20 + (r & (m2 - 1));
+          if (ii < a.n_nu1 && nu2 < a.nc && col < a.nc) {
+            double* d = &S[((size_t)ii * a.nc + nu2) * a.nc + col];
+            const double v = (double)acc[i][j][e];
+            if (first_flush) *d = v;
+            else unsafeAtomicAdd(d, v);
+          }
+          acc[i][j][e] = 0.f;
+        }
+      }
+    first_flush = false;
+  };
+
+  const bf16x8 zf = {};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fah[i] = zf;   // the deferred group of stage -1 adds zeros
+#pragma unroll
+  for (int j = 0; j < T3_NJ; ++j) fbl[j] = zf;
+  // prologue: B of stage 0 and raw rows of stages 0 and 1 land, A of stage 0 is formed
+#pragma unroll
+  for (int m = 0; m < 2 * T3_NJ; ++m) copy_b1(m, kbeg, lds);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) copy_raw1(k, kbeg, raws);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) copy_raw1(k, min(kbeg + T3_K, klast), raws + T3_RAW);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+#pragma unroll
+  for (int pc = 0; pc < 4; ++pc) form_piece(pc, raws, lds);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+
+  // Stage s (buffer s&1; raw rows of stage s+1 in raw buffer (s+1)&1), six product groups of G
+  // MFMA slots, sched_barrier keeping every slot in place; every LDS read is issued at least eight
+  // slots before its first use:
+  //   G0  group (A hi, B lo) of half 1 of stage s-1 (deferred); B copies of stage s+1, raw copies
+  //       of stage s+2; reads of A lo, B hi of half 0
+  //   G1  (A lo, B hi) half 0; reads of A hi, B lo of half 0; raw reads of formation pieces 0, 1
+  //   G2  (A hi, B hi) half 0; reads of A lo of half 1; pieces 0, 1 formed; raw reads of 2, 3
+  //   G3  (A hi, B lo) half 0; reads of B hi of half 1; pieces 2, 3 formed
+  //   G4  (A lo, B hi) half 1; reads of A hi, B lo of half 1
+  //   G5  (A hi, B hi) half 1
+  // then the wait for this wave's memory operations and the barrier.
+  auto stage = [&](int s, auto par) {
+    constexpr int PAR = decltype(par)::value;
+    uint16_t* cur = lds + PAR * T3_BUF;
+    uint16_t* nxt = lds + (PAR ^ 1) * T3_BUF;
+    const float* rawc = raws + (PAR ^ 1) * T3_RAW;   // raw rows of stage s+1
+    float* rawn = raws + PAR * T3_RAW;               // raw rows of stage s+2 land here
+    const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 1) * T3_K, klast));
+    const int kr = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 2) * T3_K, klast));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G0
+      mfma1(1, m);
+      if (m < 2 * T3_NJ) copy_b1(m, kb, nxt);
+      else if (m < 2 * T3_NJ + 3) copy_raw1(m - 2 * T3_NJ, kr, rawn);
+      if (m < 4) read1(0, m, cur, 0);
+      else if (m < 4 + T3_NJ) read1(2, m - 4, cur, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G1
+      mfma1(0, m);
+      if (m < 4) read1(1, m, cur, 0);
+      else if (m < 4 + T3_NJ) read1(3, m - 4, cur, 0);
+      else if (m == 8) form_read(0, rawc);
+      else if (m == 10) form_read(1, rawc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G2
+      mfma1(2, m);
+      if (m < 4) read1(0, m, cur, 1);
+      else if (m == 5) form_store(0, nxt);
+      else if (m == 7) form_store(1, nxt);
+      else if (m == 8) form_read(2, rawc);
+      else if (m == 10) form_read(3, rawc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G3
+      mfma1(1, m);
+      if (m < T3_NJ) read1(2, m, cur, 1);
+      else if (m == 5) form_store(2, nxt);
+      else if (m == 8) form_store(3, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G4
+      mfma1(0, m);
+      if (m < 4) read1(1, m, cur, 1);
+      else if (m < 4 + T3_NJ) read1(3, m - 4, cur, 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) {   // G5
+      mfma1(2, m);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // B of stage s+1, raw rows of stage s+2 landed; A of stage s+1 stored
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  for (int s = 0; s < nst;) {
+    const int se = min(nst, s + T3_FLUSH / T3_K);   // s is even here
+    while (true) {
+      stage(s, std::integral_constant<int, 0>{});
+      if (++s >= se) break;
+      stage(s, std::integral_constant<int, 1>{});
+      if (++s >= se) break;
+    }
+#pragma unroll
+    for (int m = 0; m < G; ++m) mfma1(1, m);   // the deferred group of the last stage
+    flush();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fah[i] = zf;
+#pragma unroll
+    for (int j = 0; j < T3_NJ; ++j) fbl[j] = zf;
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS may outlive the block
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_split3(MabsGemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  split3_tile(a, blockIdx.x, smem_raw);
+}
+
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
 // [offs[g], offs[g+1]); offsets are multiples of 8 so that the XCD remap of each group holds.
 __global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemmArgs* __restrict__ groups,
@@ -895,6 +1208,15 @@ static dim3 gemm_grid(const MabsGemmArgs& a, int tm, int tn) {
 void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
   if (getenv("BS_MABS_SMALL_TILES")) {
     hipLaunchKernelGGL(k_mabs_gemm<2>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
+    return;
+  }
+  if (a.n_nu1 >= 4 && !getenv("BS_MABS_TILE128")) {
+    // 256 x 256 tiles over (nu1 block x nu2 block) rows
+    const int m1 = a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4), m2 = T3_M / m1;
+    const long long nb = (long long)((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) *
+                         a.ntri * a.kchunks;
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)T3_LDS);
+    hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), T3_LDS, s, a);
     return;
   }
   const int nrows = a.n_nu1 * a.nc;
