@@ -677,15 +677,17 @@ constexpr int T3_AH = 0, T3_AL = T3_M * T3_K, T3_BH = 2 * T3_M * T3_K, T3_BL = T
 constexpr int T3_BUF = T3_BL + T3_N * T3_K;   // uint16 per stage buffer (56 KB)
 constexpr int T3_RAWLD = 36;                   // floats per raw row: 8 data chunks + 1 pad (bank spread)
 constexpr int T3_RAWMAX = 4 + 64;              // raw rows m1 + m2 at most
-constexpr int T3_RAW = T3_RAWMAX * T3_RAWLD;   // floats per raw buffer
-constexpr size_t T3_LDS = 2 * (size_t)T3_BUF * 2 + 2 * (size_t)T3_RAW * 4;
+constexpr int T3_RAW = 12 * 64 * 4;             // floats per raw buffer: 12 copy instructions of 64 chunks
+static_assert(T3_RAW >= T3_RAWMAX * T3_RAWLD, "raw buffer holds every raw row");
+static_assert(2 * (size_t)T3_BUF * 2 + 2 * (size_t)T3_RAW * 4 <= 160 * 1024, "stage and raw buffers fit in LDS");
 
 
 __device__ __forceinline__ int t3_m1(int n_nu1) { return n_nu1 >= 16 ? 16 : (n_nu1 >= 8 ? 8 : 4); }
 
-__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
-  uint16_t* lds = (uint16_t*)smem_raw;                          // [2][T3_BUF]
-  float* raws = (float*)(smem_raw + 2 * (size_t)T3_BUF * 2);    // [2][T3_RAW]
+// The four LDS buffers are separate variables, so that the compiler can tell the copies into one
+// from the reads of another and does not wait for every copy in flight before a read.
+__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint16_t* buf0, uint16_t* buf1, float* raw0,
+                                            float* raw1) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
@@ -713,9 +715,10 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsig
 
   // raw copies: chunk g of (m1 + m2) x 9 (row q = g / 9, chunk c = g % 9, the ninth a pad that
   // re-reads chunk 0); rows q < m1 are F_b1 at nu1[i0 + q], the rest F_b2 at nu2 = n20 + q - m1,
-  // clamped to the last valid row (their products are never stored)
-  const int nraw = (m1 + m2) * 9;
-  const int nri = (nraw + 63) / 64;       // copy instructions per stage, dealt to the waves
+  // clamped to the last valid row (their products are never stored).  Every wave issues three
+  // copy instructions per stage (12 x 64 chunks, at least the 612 of the largest row set): chunks
+  // past the row set re-read the last row into the unused tail of the raw buffer, so the copies
+  // carry no branch
   const float* rsrc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -760,11 +763,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsig
                                      16, 0, 0);
   };
   auto copy_raw1 = [&](int k, int k0, float* rb) {    // raw copy instruction wave + 4 k
-    const int ins = wave + 4 * k;
-    if (ins < nri) {
-      if (ins * 64 + lane < nraw)
-        __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + ins * 256), 16, 0, 0);
-    }
+    __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + (wave + 4 * k) * 256), 16, 0, 0);
   };
   // A formation piece pc of 4 (pixels 8 pc .. 8 pc + 7 of row fr): the raw reads (into R[pc]) are
   // issued several MFMA slots before the products, splits and stores that use them
@@ -857,15 +856,15 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsig
   for (int j = 0; j < T3_NJ; ++j) fbl[j] = zf;
   // prologue: B of stage 0 and raw rows of stages 0 and 1 land, A of stage 0 is formed
 #pragma unroll
-  for (int m = 0; m < 2 * T3_NJ; ++m) copy_b1(m, kbeg, lds);
+  for (int m = 0; m < 2 * T3_NJ; ++m) copy_b1(m, kbeg, buf0);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) copy_raw1(k, kbeg, raws);
+  for (int k = 0; k < 3; ++k) copy_raw1(k, kbeg, raw0);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) copy_raw1(k, min(kbeg + T3_K, klast), raws + T3_RAW);
+  for (int k = 0; k < 3; ++k) copy_raw1(k, min(kbeg + T3_K, klast), raw1);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
 #pragma unroll
-  for (int pc = 0; pc < 4; ++pc) form_piece(pc, raws, lds);
+  for (int pc = 0; pc < 4; ++pc) form_piece(pc, raw0, buf0);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
 
@@ -882,10 +881,10 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsig
   // then the wait for this wave's memory operations and the barrier.
   auto stage = [&](int s, auto par) {
     constexpr int PAR = decltype(par)::value;
-    uint16_t* cur = lds + PAR * T3_BUF;
-    uint16_t* nxt = lds + (PAR ^ 1) * T3_BUF;
-    const float* rawc = raws + (PAR ^ 1) * T3_RAW;   // raw rows of stage s+1
-    float* rawn = raws + PAR * T3_RAW;               // raw rows of stage s+2 land here
+    uint16_t* cur = PAR ? buf1 : buf0;
+    uint16_t* nxt = PAR ? buf0 : buf1;
+    const float* rawc = PAR ? raw0 : raw1;   // raw rows of stage s+1
+    float* rawn = PAR ? raw1 : raw0;         // raw rows of stage s+2 land here
     const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 1) * T3_K, klast));
     const int kr = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 2) * T3_K, klast));
     __builtin_amdgcn_sched_barrier(0);
@@ -962,8 +961,9 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, unsig
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_split3(MabsGemmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  split3_tile(a, blockIdx.x, smem_raw);
+  __shared__ __attribute__((aligned(16))) uint16_t buf0[T3_BUF], buf1[T3_BUF];
+  __shared__ __attribute__((aligned(16))) float raw0[T3_RAW], raw1[T3_RAW];
+  split3_tile(a, blockIdx.x, buf0, buf1, raw0, raw1);
 }
 
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
@@ -1215,8 +1215,7 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
     const int m1 = a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4), m2 = T3_M / m1;
     const long long nb = (long long)((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) *
                          a.ntri * a.kchunks;
-    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)T3_LDS);
-    hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), T3_LDS, s, a);
+    hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), 0, s, a);
     return;
   }
   const int nrows = a.n_nu1 * a.nc;
