@@ -657,12 +657,12 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
 // Split-BF16 contraction, 256 x 192 tiles.  Rows are tiled as (nu1 block of m1) x (nu2 block of
 // m2), m1 m2 = 256 (m1 = 16, 8 or 4): the A tile is formed from m1 + m2 loaded field rows
 // (F_b1(nu1) and F_b2(nu2)) instead of one row per A row.  Four waves of 128 x 96 (4 x 3 MFMA
-// 32x32x16 tiles, 192 FP32 accumulators per lane), pixel stages of 32 in two LDS stage buffers
-// (A and B hi/lo, 56 KB each) and two raw buffers of the m1 + m2 FP32 input rows:
+// 32x32x16 tiles, 192 FP32 accumulators per lane), pixel stages of 32 in two A buffers (hi/lo,
+// 32 KB each), two B buffers (hi/lo, 24 KB each) and two raw buffers of the m1 + m2 FP32 rows:
 //  * the B rows of stage s+1 (pre-split F_b3) and the raw rows of stage s+2 are copied from
 //    global memory straight into LDS (16-byte global_load_lds) at the start of stage s;
 //  * the A operand of stage s+1 is formed from the raw rows of stage s+1 (products F1 F2 split
-//    into bf16 hi / lo) and stored into the other stage buffer during stage s;
+//    into bf16 hi / lo) and stored into the other A buffer during stage s;
 //  * one set of fragments: each kind (A lo / hi, B hi / lo) is reloaded for the next half stage as
 //    soon as its last MFMA has issued, and the last 16 MFMAs of a stage are issued at the start of
 //    the next one, covering the reads of its first fragments.
@@ -673,21 +673,22 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int T3_NJ = 3;   // 32-column MFMA tiles per wave
 constexpr int T3_M = 256, T3_N = 64 * T3_NJ, T3_K = 32, T3_FLUSH = 8192;
-constexpr int T3_AH = 0, T3_AL = T3_M * T3_K, T3_BH = 2 * T3_M * T3_K, T3_BL = T3_BH + T3_N * T3_K;
-constexpr int T3_BUF = T3_BL + T3_N * T3_K;   // uint16 per stage buffer (56 KB)
+constexpr int T3_AL = T3_M * T3_K, T3_ABUF = 2 * T3_M * T3_K;   // A stage buffer: hi rows, then lo rows (32 KB)
+constexpr int T3_BL = T3_N * T3_K, T3_BBUF = 2 * T3_N * T3_K;   // B stage buffer: hi columns, then lo (24 KB)
 constexpr int T3_RAWLD = 36;                   // floats per raw row: 8 data chunks + 1 pad (bank spread)
 constexpr int T3_RAWMAX = 4 + 64;              // raw rows m1 + m2 at most
 constexpr int T3_RAW = 12 * 64 * 4;             // floats per raw buffer: 12 copy instructions of 64 chunks
 static_assert(T3_RAW >= T3_RAWMAX * T3_RAWLD, "raw buffer holds every raw row");
-static_assert(2 * (size_t)T3_BUF * 2 + 2 * (size_t)T3_RAW * 4 <= 160 * 1024, "stage and raw buffers fit in LDS");
+static_assert(2 * (size_t)(T3_ABUF + T3_BBUF) * 2 + 2 * (size_t)T3_RAW * 4 <= 160 * 1024, "stage and raw buffers fit in LDS");
 
 
 __device__ __forceinline__ int t3_m1(int n_nu1) { return n_nu1 >= 16 ? 16 : (n_nu1 >= 8 ? 8 : 4); }
 
-// The four LDS buffers are separate variables, so that the compiler can tell the copies into one
-// from the reads of another and does not wait for every copy in flight before a read.
-__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint16_t* buf0, uint16_t* buf1, float* raw0,
-                                            float* raw1) {
+// The six LDS buffers (A, B and raw rows, two of each) are separate variables, so that the compiler
+// can tell the copies into one from the reads and stores of another and does not wait for every
+// copy in flight before them.
+__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint16_t* abuf0, uint16_t* abuf1,
+                                            uint16_t* bbuf0, uint16_t* bbuf1, float* raw0, float* raw1) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
@@ -759,7 +760,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   auto copy_b1 = [&](int m, int k0, uint16_t* buf) {   // copy m of 2 NJ: columns q = m/2, hi or lo
     const int q = m >> 1;
     __builtin_amdgcn_global_load_lds((const void*)((m & 1 ? a.Fl : a.Fh) + boff[q] + k0),
-                                     (lds_void*)(buf + (m & 1 ? T3_BL : T3_BH) + (wave * 16 * T3_NJ + q * 16) * T3_K),
+                                     (lds_void*)(buf + (m & 1 ? T3_BL : 0) + (wave * 16 * T3_NJ + q * 16) * T3_K),
                                      16, 0, 0);
   };
   auto copy_raw1 = [&](int k, int k0, float* rb) {    // raw copy instruction wave + 4 k
@@ -783,13 +784,8 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
     bf16_split2(x1.z * y1.z, x1.w * y1.w, hw[3], lw[3]);
     const v4u h = {hw[0], hw[1], hw[2], hw[3]};
     const v4u l = {lw[0], lw[1], lw[2], lw[3]};
-    // written in asm: the compiler cannot tell these stores from the copies into the same buffer
-    // and would otherwise wait for every copy in flight; they touch only the A region, and the
-    // wait at the end of the stage covers their completion
-    asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:%3"
-                 :
-                 : "v"(lds_addr(buf + T3_AH + fr * T3_K + swz(fr, pc) * 8)), "v"(h), "v"(l), "n"(2 * (T3_AL - T3_AH))
-                 : "memory");
+    *(v4u*)(buf + fr * T3_K + swz(fr, pc) * 8) = h;
+    *(v4u*)(buf + T3_AL + fr * T3_K + swz(fr, pc) * 8) = l;
   };
   auto form_piece = [&](int pc, const float* rb, uint16_t* buf) {
     form_read(pc, rb);
@@ -799,11 +795,11 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   // kind is reloaded for the next half stage as soon as its last MFMA of the current one has issued.
   bf16x8 fal[4], fah[4], fbh[T3_NJ], fbl[T3_NJ];
   // read kind w (0: A lo, 1: A hi, 2: B hi, 3: B lo) of tile i for half stage kk from buf
-  auto read1 = [&](int w, int i, const uint16_t* buf, int kk) {
-    if (w == 0) fal[i] = *(const bf16x8*)&buf[T3_AL + oa[kk][i]];
-    else if (w == 1) fah[i] = *(const bf16x8*)&buf[T3_AH + oa[kk][i]];
-    else if (w == 2) fbh[i] = *(const bf16x8*)&buf[T3_BH + ob[kk][i]];
-    else fbl[i] = *(const bf16x8*)&buf[T3_BL + ob[kk][i]];
+  auto read1 = [&](int w, int i, const uint16_t* abuf, const uint16_t* bbuf, int kk) {
+    if (w == 0) fal[i] = *(const bf16x8*)&abuf[T3_AL + oa[kk][i]];
+    else if (w == 1) fah[i] = *(const bf16x8*)&abuf[oa[kk][i]];
+    else if (w == 2) fbh[i] = *(const bf16x8*)&bbuf[ob[kk][i]];
+    else fbl[i] = *(const bf16x8*)&bbuf[T3_BL + ob[kk][i]];
   };
 
   f32x16 acc[4][T3_NJ];
@@ -856,7 +852,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   for (int j = 0; j < T3_NJ; ++j) fbl[j] = zf;
   // prologue: B of stage 0 and raw rows of stages 0 and 1 land, A of stage 0 is formed
 #pragma unroll
-  for (int m = 0; m < 2 * T3_NJ; ++m) copy_b1(m, kbeg, buf0);
+  for (int m = 0; m < 2 * T3_NJ; ++m) copy_b1(m, kbeg, bbuf0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) copy_raw1(k, kbeg, raw0);
 #pragma unroll
@@ -864,7 +860,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
 #pragma unroll
-  for (int pc = 0; pc < 4; ++pc) form_piece(pc, raw0, buf0);
+  for (int pc = 0; pc < 4; ++pc) form_piece(pc, raw0, abuf0);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
 
@@ -881,8 +877,10 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   // then the wait for this wave's memory operations and the barrier.
   auto stage = [&](int s, auto par) {
     constexpr int PAR = decltype(par)::value;
-    uint16_t* cur = PAR ? buf1 : buf0;
-    uint16_t* nxt = PAR ? buf0 : buf1;
+    const uint16_t* ac = PAR ? abuf1 : abuf0;   // A and B of stage s
+    const uint16_t* bc = PAR ? bbuf1 : bbuf0;
+    uint16_t* an = PAR ? abuf0 : abuf1;         // A and B of stage s+1
+    uint16_t* bn = PAR ? bbuf0 : bbuf1;
     const float* rawc = PAR ? raw0 : raw1;   // raw rows of stage s+1
     float* rawn = PAR ? raw1 : raw0;         // raw rows of stage s+2 land here
     const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 1) * T3_K, klast));
@@ -891,17 +889,17 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 #pragma unroll
     for (int m = 0; m < G; ++m) {   // G0
       mfma1(1, m);
-      if (m < 2 * T3_NJ) copy_b1(m, kb, nxt);
+      if (m < 2 * T3_NJ) copy_b1(m, kb, bn);
       else if (m < 2 * T3_NJ + 3) copy_raw1(m - 2 * T3_NJ, kr, rawn);
-      if (m < 4) read1(0, m, cur, 0);
-      else if (m < 4 + T3_NJ) read1(2, m - 4, cur, 0);
+      if (m < 4) read1(0, m, ac, bc, 0);
+      else if (m < 4 + T3_NJ) read1(2, m - 4, ac, bc, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int m = 0; m < G; ++m) {   // G1
       mfma1(0, m);
-      if (m < 4) read1(1, m, cur, 0);
-      else if (m < 4 + T3_NJ) read1(3, m - 4, cur, 0);
+      if (m < 4) read1(1, m, ac, bc, 0);
+      else if (m < 4 + T3_NJ) read1(3, m - 4, ac, bc, 0);
       else if (m == 8) form_read(0, rawc);
       else if (m == 10) form_read(1, rawc);
       __builtin_amdgcn_sched_barrier(0);
@@ -909,9 +907,9 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 #pragma unroll
     for (int m = 0; m < G; ++m) {   // G2
       mfma1(2, m);
-      if (m < 4) read1(0, m, cur, 1);
-      else if (m == 5) form_store(0, nxt);
-      else if (m == 7) form_store(1, nxt);
+      if (m < 4) read1(0, m, ac, bc, 1);
+      else if (m == 5) form_store(0, an);
+      else if (m == 7) form_store(1, an);
       else if (m == 8) form_read(2, rawc);
       else if (m == 10) form_read(3, rawc);
       __builtin_amdgcn_sched_barrier(0);
@@ -919,16 +917,16 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 #pragma unroll
     for (int m = 0; m < G; ++m) {   // G3
       mfma1(1, m);
-      if (m < T3_NJ) read1(2, m, cur, 1);
-      else if (m == 5) form_store(2, nxt);
-      else if (m == 8) form_store(3, nxt);
+      if (m < T3_NJ) read1(2, m, ac, bc, 1);
+      else if (m == 5) form_store(2, an);
+      else if (m == 8) form_store(3, an);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int m = 0; m < G; ++m) {   // G4
       mfma1(0, m);
-      if (m < 4) read1(1, m, cur, 1);
-      else if (m < 4 + T3_NJ) read1(3, m - 4, cur, 1);
+      if (m < 4) read1(1, m, ac, bc, 1);
+      else if (m < 4 + T3_NJ) read1(3, m - 4, ac, bc, 1);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -961,9 +959,9 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_split3(MabsGemmArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t buf0[T3_BUF], buf1[T3_BUF];
+  __shared__ __attribute__((aligned(16))) uint16_t abuf0[T3_ABUF], abuf1[T3_ABUF], bbuf0[T3_BBUF], bbuf1[T3_BBUF];
   __shared__ __attribute__((aligned(16))) float raw0[T3_RAW], raw1[T3_RAW];
-  split3_tile(a, blockIdx.x, buf0, buf1, raw0, raw1);
+  split3_tile(a, blockIdx.x, abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
 }
 
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
