@@ -390,6 +390,11 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(uintptr_t)(lds_cchar*)p; }
 
 __device__ __forceinline__ int swz(int r, int chunk) { return (chunk ^ ((r >> 2) & 3)); }
+// Chunk swizzle of 64-byte rows for 16-byte accesses of one chunk index by consecutive rows: any
+// eight consecutive rows (aligned) land in eight distinct 16-byte slots of a 128-byte bank line,
+// and any sixteen in sixteen distinct slots of a 256-byte line, so such accesses meet no bank
+// conflict (measured: none, against a fifth of the LDS cycles with the swizzle above)
+__device__ __forceinline__ int swz_rows(int r, int chunk) { return chunk ^ (((r >> 1) ^ (r >> 2)) & 3); }
 
 struct SplitFrags {
   bf16x8 ah[2], al[2], bh[4], bl[4];
@@ -735,7 +740,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   for (int q = 0; q < T3_NJ; ++q) {
     const int br = wave * 16 * T3_NJ + q * 16 + (lane >> 2);
     const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
-    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 8 * swz(br, lane & 3);
+    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 8 * swz_rows(br, lane & 3);
   }
   // A formation: thread r = tid owns tile row r = (i1, i2), i2 = r mod m2
   const int fr = tid, fi1 = fr >> lm2, fi2 = fr & (m2 - 1);
@@ -748,12 +753,12 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = wm * 128 + i * 32 + (lane & 31);
-      oa[kk][i] = r * T3_K + swz(r, chunk) * 8;
+      oa[kk][i] = r * T3_K + swz_rows(r, chunk) * 8;
     }
 #pragma unroll
     for (int j = 0; j < T3_NJ; ++j) {
       const int c = wn * 32 * T3_NJ + j * 32 + (lane & 31);
-      ob[kk][j] = c * T3_K + swz(c, chunk) * 8;
+      ob[kk][j] = c * T3_K + swz_rows(c, chunk) * 8;
     }
   }
 
@@ -766,30 +771,33 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   auto copy_raw1 = [&](int k, int k0, float* rb) {    // raw copy instruction wave + 4 k
     __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + (wave + 4 * k) * 256), 16, 0, 0);
   };
-  // A formation piece pc of 4 (pixels 8 pc .. 8 pc + 7 of row fr): the raw reads (into R[pc]) are
-  // issued several MFMA slots before the products, splits and stores that use them
+  // A formation piece pc of 4 (pixels 8 pc .. 8 pc + 7 of row fr) in six steps spread over the
+  // MFMA slots: the raw reads (into R[pc]), four pair products split into bf16 hi / lo words (one
+  // step of eight VALU operations, about the time of one MFMA), the two LDS stores
   float4 R[4][4];
+  uint32_t HW[4][4], LW[4][4];
   auto form_read = [&](int pc, const float* rb) {
     R[pc][0] = *(const float4*)&rb[rawf1 + 8 * pc];
     R[pc][1] = *(const float4*)&rb[rawf1 + 8 * pc + 4];
     R[pc][2] = *(const float4*)&rb[rawf2 + 8 * pc];
     R[pc][3] = *(const float4*)&rb[rawf2 + 8 * pc + 4];
   };
-  auto form_store = [&](int pc, uint16_t* buf) {
-    const float4 x0 = R[pc][0], x1 = R[pc][1], y0 = R[pc][2], y1 = R[pc][3];
-    uint32_t hw[4], lw[4];
-    bf16_split2(x0.x * y0.x, x0.y * y0.y, hw[0], lw[0]);
-    bf16_split2(x0.z * y0.z, x0.w * y0.w, hw[1], lw[1]);
-    bf16_split2(x1.x * y1.x, x1.y * y1.y, hw[2], lw[2]);
-    bf16_split2(x1.z * y1.z, x1.w * y1.w, hw[3], lw[3]);
-    const v4u h = {hw[0], hw[1], hw[2], hw[3]};
-    const v4u l = {lw[0], lw[1], lw[2], lw[3]};
-    *(v4u*)(buf + fr * T3_K + swz(fr, pc) * 8) = h;
-    *(v4u*)(buf + T3_AL + fr * T3_K + swz(fr, pc) * 8) = l;
+  auto form_pair = [&](int pc, int q) {   // pixels 8 pc + 2 q, 8 pc + 2 q + 1
+    const float4 x = R[pc][q >> 1], y = R[pc][2 + (q >> 1)];
+    if (q & 1) bf16_split2(x.z * y.z, x.w * y.w, HW[pc][q], LW[pc][q]);
+    else bf16_split2(x.x * y.x, x.y * y.y, HW[pc][q], LW[pc][q]);
+  };
+  auto form_write = [&](int pc, uint16_t* buf) {
+    const v4u h = {HW[pc][0], HW[pc][1], HW[pc][2], HW[pc][3]};
+    const v4u l = {LW[pc][0], LW[pc][1], LW[pc][2], LW[pc][3]};
+    *(v4u*)(buf + fr * T3_K + swz_rows(fr, pc) * 8) = h;
+    *(v4u*)(buf + T3_AL + fr * T3_K + swz_rows(fr, pc) * 8) = l;
   };
   auto form_piece = [&](int pc, const float* rb, uint16_t* buf) {
     form_read(pc, rb);
-    form_store(pc, buf);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) form_pair(pc, q);
+    form_write(pc, buf);
   };
   // One set of fragments (A lo / hi of four 32-row tiles, B hi / lo of NJ 32-column tiles): each
   // kind is reloaded for the next half stage as soon as its last MFMA of the current one has issued.
@@ -864,14 +872,15 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_s_barrier();
 
-  // Stage s (buffer s&1; raw rows of stage s+1 in raw buffer (s+1)&1), six product groups of G
-  // MFMA slots, sched_barrier keeping every slot in place; every LDS read is issued at least eight
-  // slots before its first use:
+  // Stage s (buffer s&1; raw rows of stage s+1 in raw buffer (s+1)&1): 72 MFMA slots in six
+  // product groups of G, sched_barrier keeping every slot in place; every LDS read is issued at
+  // least eight slots before its first use, and no slot holds more than about one MFMA's time of
+  // other work:
   //   G0  group (A hi, B lo) of half 1 of stage s-1 (deferred); B copies of stage s+1, raw copies
   //       of stage s+2; reads of A lo, B hi of half 0
   //   G1  (A lo, B hi) half 0; reads of A hi, B lo of half 0; raw reads of formation pieces 0, 1
-  //   G2  (A hi, B hi) half 0; reads of A lo of half 1; pieces 0, 1 formed; raw reads of 2, 3
-  //   G3  (A hi, B lo) half 0; reads of B hi of half 1; pieces 2, 3 formed
+  //   G2  (A hi, B hi) half 0; reads of A lo of half 1; piece 0 formed; raw reads of pieces 2, 3
+  //   G3  (A hi, B lo) half 0; reads of B hi of half 1; pieces 1, 2, 3 formed
   //   G4  (A lo, B hi) half 1; reads of A hi, B lo of half 1
   //   G5  (A hi, B hi) half 1
   // then the wait for this wave's memory operations and the barrier.
@@ -886,52 +895,35 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
     const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 1) * T3_K, klast));
     const int kr = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 2) * T3_K, klast));
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G0
-      mfma1(1, m);
-      if (m < 2 * T3_NJ) copy_b1(m, kb, bn);
-      else if (m < 2 * T3_NJ + 3) copy_raw1(m - 2 * T3_NJ, kr, rawn);
-      if (m < 4) read1(0, m, ac, bc, 0);
-      else if (m < 4 + T3_NJ) read1(2, m - 4, ac, bc, 0);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G1
-      mfma1(0, m);
-      if (m < 4) read1(1, m, ac, bc, 0);
-      else if (m < 4 + T3_NJ) read1(3, m - 4, ac, bc, 0);
-      else if (m == 8) form_read(0, rawc);
-      else if (m == 10) form_read(1, rawc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G2
-      mfma1(2, m);
-      if (m < 4) read1(0, m, ac, bc, 1);
-      else if (m == 5) form_store(0, an);
-      else if (m == 7) form_store(1, an);
-      else if (m == 8) form_read(2, rawc);
-      else if (m == 10) form_read(3, rawc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G3
-      mfma1(1, m);
-      if (m < T3_NJ) read1(2, m, ac, bc, 1);
-      else if (m == 5) form_store(2, an);
-      else if (m == 8) form_store(3, an);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G4
-      mfma1(0, m);
-      if (m < 4) read1(1, m, ac, bc, 1);
-      else if (m < 4 + T3_NJ) read1(3, m - 4, ac, bc, 1);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < G; ++m) {   // G5
-      mfma1(2, m);
+#pragma clang loop unroll(full)
+    for (int sl = 0; sl < 6 * G; ++sl) {
+      const int grp = sl / G, m = sl % G;
+      mfma1(grp % 3 == 0 ? 1 : (grp % 3 == 1 ? 0 : 2), m);
+      // copies of stage s+1 (B) and s+2 (raw rows)
+      if (sl < 2 * T3_NJ) copy_b1(sl, kb, bn);
+      else if (sl < 2 * T3_NJ + 3) copy_raw1(sl - 2 * T3_NJ, kr, rawn);
+      // fragments
+      if (sl < 4) read1(0, sl, ac, bc, 0);
+      else if (sl < 4 + T3_NJ) read1(2, sl - 4, ac, bc, 0);
+      else if (sl >= 12 && sl < 16) read1(1, sl - 12, ac, bc, 0);
+      else if (sl >= 16 && sl < 16 + T3_NJ) read1(3, sl - 16, ac, bc, 0);
+      else if (sl >= 24 && sl < 28) read1(0, sl - 24, ac, bc, 1);
+      else if (sl >= 36 && sl < 36 + T3_NJ) read1(2, sl - 36, ac, bc, 1);
+      else if (sl >= 48 && sl < 52) read1(1, sl - 48, ac, bc, 1);
+      else if (sl >= 52 && sl < 52 + T3_NJ) read1(3, sl - 52, ac, bc, 1);
+      // A of stage s+1
+      if (sl == 20) form_read(0, rawc);
+      if (sl == 22) form_read(1, rawc);
+      if (sl == 31) form_read(2, rawc);
+      if (sl == 33) form_read(3, rawc);
+      if (sl >= 28 && sl < 32) form_pair(0, sl - 28);
+      if (sl == 32) form_write(0, an);
+      if (sl >= 33 && sl < 37) form_pair(1, sl - 33);
+      if (sl == 37) form_write(1, an);
+      if (sl >= 39 && sl < 43) form_pair(2, sl - 39);
+      if (sl == 43) form_write(2, an);
+      if (sl >= 44 && sl < 48) form_pair(3, sl - 44);
+      if (sl == 48) form_write(3, an);
       __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_waitcnt(0);   // B of stage s+1, raw rows of stage s+2 landed; A of stage s+1 stored
