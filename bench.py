@@ -369,7 +369,8 @@ def mc_block(bs, ctx, bins, ncand, w, torch, R=64):
 def batch_block(bs, ctx, torch, ncubes=64, seed=4):
     """64 seeded cubes of uneven size (n in {128,192,256}, nc in {384,576,768}), 8 log rings, all
     candidate triangles, a seeded subset of 32 nu1 channels with all (nu2, nu3), split-BF16; one
-    hipGraph launch for the whole batch (one grouped contraction launch per wave)."""
+    hipGraph launch for the whole batch (per wave, one persistent contraction launch per tile shape
+    in use); tile shapes and pixel chunks per cube shape class from the library's autotuner."""
     rng = np.random.default_rng(seed)
     cubes = []
     for i in range(ncubes):
@@ -383,6 +384,10 @@ def batch_block(bs, ctx, torch, ncubes=64, seed=4):
     t_create = time.perf_counter() - t0
     try:
         info = [bs.bs_batch_info(h, i) for i in range(ncubes)]
+        tiles = {}
+        for i, c in enumerate(cubes):
+            tm, tn, m1, k = bs.bs_batch_tile(h, i)
+            tiles[f"n={c[0]} nc={c[1]}"] = f"{tm}x{tn}" + (f" rows {m1}x{256 // m1}" if m1 else "") + f", {k} chunk(s)"
         bs.bs_batch_run(h)          # warm-up launch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -398,8 +403,8 @@ def batch_block(bs, ctx, torch, ncubes=64, seed=4):
                         "x all (nu2, nu3), split-BF16, ergodic collapse over the nu1 subset",
             "seconds_per_launch": dt, "products": products, "products_per_s": products / dt,
             "mfma_tflops_incl_generation_and_fields": flops / dt / 1e12,
-            "waves": 1 + max(x[1] for x in info), "pixel_chunks": sorted({x[2] for x in info}),
-            "create_seconds": t_create}
+            "waves": 1 + max(x[1] for x in info), "tiles_per_class": dict(sorted(tiles.items())),
+            "create_seconds_incl_autotuning": t_create}
 
 
 def surrogate_block(bs, ctx, bins, ncand, w, torch):

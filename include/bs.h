@@ -324,9 +324,11 @@ void bs_mc_destroy(bs_mc* mc);
  * with nu1 - d1 and nu1 - d1 + d2 in the band of B(nu1, nu1 - d1 + d2, nu1 - d1) (NaN if none, or if
  * the triangle has no closed grid triangle), and N_nu[d1'][d2'] the number averaged.
  * bs_batch_create does every host-side step (bins, channel-independent counts, device tables) and
- * picks the pixel-chunk count of each cube shape by timing candidates on the device (cached in the
- * context); cubes are packed in order into waves whose workspaces fit budget_gib; every wave's
- * contraction is one grouped launch over all its cubes; the whole batch is captured into one hipGraph.
+ * picks the tile shape and pixel-chunk count of each cube shape class (n, nc, n_nu1, nrings) by
+ * timing candidates on the device (cached in the context; see bs_tune_set); cubes are packed in order
+ * into waves whose workspaces fit budget_gib; every wave's contraction is one persistent launch per
+ * tile shape in use (one block per CU pulls tiles of all the wave's cubes from per-XCD work queues,
+ * largest tiles first); the whole batch is captured into one hipGraph.
  * bs_batch_run: one graph launch (ordered after earlier work on the context's stream; later work on
  *   that stream waits for it).
  * bs_batch_info: candidate count, wave, pixel chunks and products (valid triangles x n_nu1 x nc^2 x n^2)
@@ -348,6 +350,20 @@ int bs_batch_info(const bs_batch* batch, int32_t cube, int32_t* n_cand, int32_t*
 int bs_batch_result(bs_batch* batch, int32_t cube, double* Bbar_host, int32_t* N_nu_host, int64_t* T_perp_host,
                     int32_t* tri3_host);
 void bs_batch_destroy(bs_batch* batch);
+/* Tile choice of the batch contraction (the paper fixes none; Sec. 3.2 only parallelises over ring
+ * and channel triples).  Shapes: tile_m x tile_n = 128 x 256 output rows (nu1, nu2) x columns nu3
+ * (m1 = 0), or 256 x 192 whose rows are an m1 x (256 / m1) block of (nu1, nu2), m1 in {4, 8, 16, 32}
+ * (needs n_nu1 >= 4 and m1 <= n_nu1 unless m1 = 4); kchunks in {1, 2, 4, 8} pixel chunks with n^2 /
+ * kchunks a multiple of 32 and at least 1024.  A class is (n, nc, n_nu1, nrings).
+ * bs_tune_set: store a choice for a class in the context's cache; bs_batch_create then uses it
+ *   instead of timing (BS_EINVAL if the choice cannot run the class).
+ * bs_tune_get: the cached choice of a class (all outputs 0 when it has none yet); outputs nullable.
+ * bs_batch_tile: the choice used for cube i of a batch; outputs nullable. */
+int bs_tune_set(bs_ctx* ctx, int32_t n, int32_t nc, int32_t n_nu1, int32_t nrings, int32_t tile_m, int32_t m1,
+                int32_t kchunks);
+int bs_tune_get(bs_ctx* ctx, int32_t n, int32_t nc, int32_t n_nu1, int32_t nrings, int32_t* tile_m, int32_t* tile_n,
+                int32_t* m1, int32_t* kchunks);
+int bs_batch_tile(const bs_batch* batch, int32_t cube, int32_t* tile_m, int32_t* tile_n, int32_t* m1, int32_t* kchunks);
 
 /* ---- learned variance surrogate ----
  * Not part of the paper, which takes error bars from the scatter of independent realizations

@@ -25,6 +25,7 @@ EXPORTED = [
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
     "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
+    "bs_batch_tile", "bs_tune_set", "bs_tune_get",
 ]
 BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
@@ -129,6 +130,9 @@ def lib() -> ctypes.CDLL:
     L.bs_batch_result.argtypes = [vp, i32, vp, vp, vp, vp]
     L.bs_batch_destroy.argtypes = [vp]
     L.bs_batch_destroy.restype = None
+    L.bs_batch_tile.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.bs_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
+    L.bs_tune_get.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("bs_destroy", "bs_last_error", "bs_free_bins", "bs_mc_destroy", "bs_mlp_destroy",
                         "bs_batch_destroy"):
@@ -478,6 +482,24 @@ def bs_batch_info(batch: int, cube: int):
     _check(_batch[batch][0], lib().bs_batch_info(batch, cube, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c_),
                                                  ctypes.byref(d)))
     return a.value, b.value, c_.value, d.value
+
+
+def bs_batch_tile(batch: int, cube: int):
+    """(tile_m, tile_n, m1, pixel_chunks) of the contraction of one cube."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(_batch[batch][0], lib().bs_batch_tile(batch, cube, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def bs_tune_set(ctx: int, n: int, nc: int, n_nu1: int, nrings: int, tile_m: int, m1: int, kchunks: int) -> None:
+    _check(ctx, lib().bs_tune_set(ctx, n, nc, n_nu1, nrings, tile_m, m1, kchunks))
+
+
+def bs_tune_get(ctx: int, n: int, nc: int, n_nu1: int, nrings: int):
+    """(tile_m, tile_n, m1, pixel_chunks) cached for a cube shape class; zeros when none."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(ctx, lib().bs_tune_get(ctx, n, nc, n_nu1, nrings, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def bs_batch_result(batch: int, cube: int):

@@ -6,9 +6,10 @@
 // ergodic collapse over the nu1 subset (mean over the selected nu1 of B(nu1, nu1 - d1 + d2, nu1 - d1),
 // Sec. 3.2 and Sec. 5), so that it stays O(nc^2) per triangle.
 // Cubes are packed into waves whose workspaces fit a memory budget; the contraction of a wave is
-// one grouped launch over all its cubes (one group per cube, blocks of all groups in one grid).
-// The pixel-chunk count (split K) of each cube shape is picked by timing the candidates on the
-// device the first time the shape is seen in a context.
+// one persistent launch per tile kind in use (one block per CU pulling the tiles of all its cubes
+// from per-XCD work queues, largest tiles first).  The tile shape and the pixel-chunk count (split
+// K) of each cube shape class are picked by timing the candidates on the device the first time the
+// class is seen in a context (or set beforehand with bs_tune_set), and cached in the context.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +43,7 @@ struct BCube {
   bs_bins* bins = nullptr;
   std::vector<int> nu1, tri, blocks;   // tri: candidate ring ids; blocks: rings in use
   int ntri = 0, nbu = 0, n_nu1 = 0, kchunks = 1, wave = 0, valid = 0;
+  int kind = 1, m1 = 16;   // tile: 0 = 128 x 256, 1 = 256 x 192 over m1 x 256/m1 (nu1, nu2) row blocks
   int *d_nu1 = nullptr, *d_tri = nullptr, *d_blocks = nullptr;
   int64_t* d_tperp = nullptr;
   std::vector<int64_t> tperp;
@@ -71,9 +73,12 @@ struct bs_batch {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   int nwaves = 0;
-  std::vector<MabsGemmArgs*> d_groups;   // per wave
-  std::vector<int*> d_offs;
-  std::vector<int> ngroups, nblocks;
+  struct PLaunch {
+    int wave, kind;
+    MabsPersistArgs args;
+  };
+  std::vector<PLaunch> launches;   // persistent contraction launches, by wave
+  int grid = 0;                    // blocks of a persistent launch (one per CU)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -106,7 +111,47 @@ MabsGemmArgs gemm_args(const BCube& q, char* arena, int kchunks) {
   g.kchunk = g.P / kchunks;
   g.bin_stride = (long long)q.nc * g.P;
   g.S = (double*)(arena + q.off_S);
+  g.tile_m1 = q.kind ? q.m1 : 0;
   return g;
+}
+
+int tiles_of(int kind, const MabsGemmArgs& g) { return kind ? mabs_split3_tiles(g) : mabs_split_blocks(g); }
+
+// Per-XCD queue prefixes [8][ngroups + 1] of the persistent launch over `gs` (in that order).
+std::vector<int> queue_offsets(int kind, const std::vector<MabsGemmArgs>& gs) {
+  const int ng = (int)gs.size();
+  std::vector<int> q(8 * (ng + 1), 0);
+  for (int g = 0; g < ng; ++g) {
+    const int nb = tiles_of(kind, gs[g]), per = nb / 8, rem = nb - 8 * per;
+    for (int x = 0; x < 8; ++x) q[x * (ng + 1) + g + 1] = q[x * (ng + 1) + g] + per + (x < rem ? 1 : 0);
+  }
+  return q;
+}
+
+int cu_count(int device) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    n = 256;
+  }
+  return std::max(8, n / 8 * 8);
+}
+
+std::string tile_key(int n, int nc, int n_nu1, int nrings) {
+  char key[96];
+  snprintf(key, sizeof key, "mabs_split_tile:%d:%d:%d:%d", n, nc, n_nu1, nrings);
+  return key;
+}
+int tile_code(int kind, int m1, int kchunks) { return kind | (m1 << 4) | (kchunks << 12); }
+void tile_decode(int code, int& kind, int& m1, int& kchunks) {
+  kind = code & 15; m1 = (code >> 4) & 255; kchunks = code >> 12;
+}
+// whether (kind, m1, kchunks) can run a GEMM of this class
+bool tile_ok(int kind, int m1, int kchunks, int n, int n_nu1) {
+  const int P = n * n;
+  if (kchunks < 1 || kchunks > 8 || (kchunks & (kchunks - 1)) || P % (32 * kchunks) || P / kchunks < 1024) return false;
+  if (kind == 0) return m1 == 0;
+  return kind == 1 && n_nu1 >= 4 && (m1 == 4 || m1 == 8 || m1 == 16 || m1 == 32) && (m1 == 4 || m1 <= n_nu1);
 }
 
 // Generator, ring fields and split of one cube into the arena slots (launches only).
@@ -124,23 +169,66 @@ void enqueue_front(const BCube& q, char* arena, hipStream_t s) {
                     (long long)q.bytes_fields(), s);
 }
 
-int pick_kchunks(bs_ctx* c, bs_batch* bt, BCube& q, hipStream_t s) {
-  const int P = q.n * q.n;
-  std::vector<int> cand;
-  for (int k = 1; k <= 8; k *= 2)
-    if (P % (32 * k) == 0 && P / k >= 1024) cand.push_back(k);
-  char key[96];
-  snprintf(key, sizeof key, "mabs_split_kchunks:%d:%d:%d:%d", q.n, q.nc, q.n_nu1, q.ntri);
-  auto it = c->tuned.find(key);
-  if (it != c->tuned.end()) { q.kchunks = it->second; return BS_OK; }
-  {
-    // a GEMM that already fills the chip many times over gains nothing from splitting K
-    MabsGemmArgs g1{};
-    g1.nc = q.nc; g1.n_nu1 = q.n_nu1; g1.ntri = q.ntri; g1.kchunks = 1;
-    if (mabs_split_blocks(g1) >= 4096) cand.resize(1);
+// Device-side tables of a one-GEMM persistent launch (autotuner timing runs).
+struct TuneLaunch {
+  MabsGemmArgs* dg = nullptr;
+  int* dq = nullptr;
+  int* dcnt = nullptr;
+  bool alloc() {
+    if (hipMalloc(&dg, sizeof(MabsGemmArgs)) != hipSuccess || hipMalloc(&dq, 16 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&dcnt, 8 * sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
   }
-  if (cand.size() == 1) { q.kchunks = cand[0]; c->tuned[key] = cand[0]; return BS_OK; }
-  // temporary slots for one cube at the largest candidate
+  void release() {
+    if (dg) (void)hipFree(dg);
+    if (dq) (void)hipFree(dq);
+    if (dcnt) (void)hipFree(dcnt);
+  }
+  // mean time of `reps` launches after one warm-up
+  float time(int kind, const MabsGemmArgs& g, int grid, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const std::vector<MabsGemmArgs> gs{g};
+    const std::vector<int> q = queue_offsets(kind, gs);
+    (void)hipMemcpyAsync(dg, &g, sizeof g, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(dq, q.data(), q.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    MabsPersistArgs pa{dg, dq, 1, dcnt};
+    float ms = 0.f, tot = 0.f;
+    for (int rep = 0; rep <= reps; ++rep) {
+      (void)hipEventRecord(e0, s);
+      launch_mabs_gemm_persist(kind, pa, grid, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep) tot += ms;
+    }
+    return tot / reps;
+  }
+};
+
+// Tile shape and pixel-chunk count of one cube shape class (n, nc, n_nu1, nrings): cached in the
+// context, else timed on this cube's own fields.  Tile shapes are compared on a leading subset of
+// the triangles with about eight tiles per CU (rate = products / time); the pixel-chunk count is
+// then timed on the whole GEMM when it has fewer than 4096 tiles unsplit (below that a split can
+// help to fill the chip).
+int pick_tile(bs_ctx* c, bs_batch* bt, BCube& q, int nrings, hipStream_t s) {
+  const std::string key = tile_key(q.n, q.nc, q.n_nu1, nrings);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    tile_decode(it->second, q.kind, q.m1, q.kchunks);
+    if (!tile_ok(q.kind, q.m1, q.kchunks, q.n, q.n_nu1))
+      return ctx_fail(c, BS_EINVAL, "the tile set for this cube shape cannot run it");
+    return BS_OK;
+  }
+  std::vector<std::pair<int, int>> tiles{{0, 0}};
+  for (int m1 : {4, 8, 16, 32})
+    if (tile_ok(1, m1, 1, q.n, q.n_nu1)) tiles.push_back({1, m1});
+  std::vector<int> ks;
+  for (int k = 1; k <= 8; k *= 2)
+    if (tile_ok(0, 0, k, q.n, q.n_nu1)) ks.push_back(k);
+  if (ks.empty()) return ctx_fail(c, BS_EINVAL, "batch cube too small for the split-BF16 contraction");
+  // temporary slots for one cube at the largest pixel-chunk count
   BCube t = q;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
@@ -149,49 +237,45 @@ int pick_kchunks(bs_ctx* c, bs_batch* bt, BCube& q, hipStream_t s) {
   t.off_F = take(q.bytes_fields() * 4);
   t.off_Fh = take(q.bytes_fields() * 2);
   t.off_Fl = take(q.bytes_fields() * 2);
-  t.off_S = take((size_t)cand.back() * q.ntri * q.n_nu1 * q.nc * (size_t)q.nc * 8);
+  t.off_S = take((size_t)ks.back() * q.ntri * q.n_nu1 * q.nc * (size_t)q.nc * 8);
   char* tmp = nullptr;
   if (hipMalloc(&tmp, off) != hipSuccess) { (void)hipGetLastError(); return ctx_fail(c, BS_ENOMEM, "autotuner workspace"); }
-  MabsGemmArgs* dg = nullptr;
-  int* doffs = nullptr;
-  if (hipMalloc(&dg, sizeof(MabsGemmArgs)) != hipSuccess || hipMalloc(&doffs, 2 * sizeof(int)) != hipSuccess) {
-    (void)hipGetLastError(); (void)hipFree(tmp); if (dg) (void)hipFree(dg);
-    return ctx_fail(c, BS_ENOMEM, "autotuner tables");
-  }
+  TuneLaunch tl;
+  if (!tl.alloc()) { tl.release(); (void)hipFree(tmp); return ctx_fail(c, BS_ENOMEM, "autotuner tables"); }
   enqueue_front(t, tmp, s);
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  double best = 1e30;
-  int bestk = cand[0];
-  for (int k : cand) {
-    MabsGemmArgs g = gemm_args(t, tmp, k);
-    const int nb = mabs_split_blocks(g);
-    int offs[2] = {0, (nb + 7) / 8 * 8};
-    (void)hipMemcpyAsync(dg, &g, sizeof g, hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(doffs, offs, sizeof offs, hipMemcpyHostToDevice, s);
-    float ms = 0.f, tot = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
-      (void)hipEventRecord(e0, s);
-      launch_mabs_gemm_split_grouped(dg, doffs, 1, offs[1], s);
-      (void)hipEventRecord(e1, s);
-      (void)hipEventSynchronize(e1);
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep) tot += ms;
+  // 1. tile shape
+  double best_rate = -1.0;
+  for (auto [kind, m1] : tiles) {
+    t.kind = kind; t.m1 = m1;
+    MabsGemmArgs g = gemm_args(t, tmp, 1);
+    g.ntri = 1;
+    const int per_tri = tiles_of(kind, g);
+    g.ntri = std::min(q.ntri, std::max(1, (8 * bt->grid + per_tri - 1) / per_tri));
+    const float ms = tl.time(kind, g, bt->grid, 2, s, e0, e1);
+    const double rate = (double)g.ntri * g.n_nu1 * (double)g.nc * g.nc * g.P / std::max(ms, 1e-6f);
+    if (rate > best_rate) { best_rate = rate; q.kind = kind; q.m1 = m1; }
+  }
+  // 2. pixel chunks for that tile
+  t.kind = q.kind; t.m1 = q.m1;   // m1 = 0 for 128 x 256 tiles
+  q.kchunks = 1;
+  if (tiles_of(q.kind, gemm_args(t, tmp, 1)) < 4096 && ks.size() > 1) {
+    float best = 1e30f;
+    for (int k : ks) {
+      const float ms = tl.time(q.kind, gemm_args(t, tmp, k), bt->grid, 2, s, e0, e1);
+      if (ms < best) { best = ms; q.kchunks = k; }
     }
-    if (tot < best) { best = tot; bestk = k; }
   }
   hipError_t err = hipGetLastError();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
   (void)hipFree(tmp);
-  (void)hipFree(dg);
-  (void)hipFree(doffs);
+  tl.release();
   if (err != hipSuccess) return ctx_fail(c, BS_EHIP, std::string("autotuner: ") + hipGetErrorString(err));
-  q.kchunks = bestk;
-  c->tuned[key] = bestk;
-  (void)bt;
+  c->tuned[key] = tile_code(q.kind, q.m1, q.kchunks);
   return BS_OK;
 }
 
@@ -230,6 +314,7 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
     (void)hipGetLastError();
     return fail(ctx_fail(c, BS_EHIP, "stream/event creation"));
   }
+  b->grid = cu_count(c->device);
   hipStream_t saved = c->stream;
   c->stream = b->s;   // eager set-up work (counts, tuning) runs on the batch stream
   auto restore_fail = [&](int rc) { c->stream = saved; return fail(rc); };
@@ -323,7 +408,7 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
     q.Bbar = (double*)balloc(b, (size_t)q.ntri * D * D * 8);
     q.Nnu = (int32_t*)balloc(b, (size_t)D * D * 4);
     if (!q.Bbar || !q.Nnu) return restore_fail(ctx_fail(c, BS_ENOMEM, "batch outputs"));
-    int rc2 = pick_kchunks(c, b, q, c->stream);
+    int rc2 = pick_tile(c, b, q, nrings, c->stream);
     if (rc2) return restore_fail(rc2);
   }
   // ---- waves under the memory budget ----
@@ -349,22 +434,29 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
   b->arena = (char*)balloc(b, maxw);
   b->arena_bytes = maxw;
   if (!b->arena) return restore_fail(ctx_fail(c, BS_ENOMEM, "batch arena (lower the budget)"));
-  // ---- group tables: one per wave ----
+  // ---- persistent launch tables: per wave and tile kind, cubes by tile cost (largest first) ----
   for (int wv = 0; wv < b->nwaves; ++wv) {
-    std::vector<MabsGemmArgs> gs;
-    std::vector<int> offs{0};
-    for (auto& q : b->cubes) {
-      if (q.wave != wv) continue;
-      MabsGemmArgs g = gemm_args(q, b->arena, q.kchunks);
-      gs.push_back(g);
-      offs.push_back(offs.back() + (mabs_split_blocks(g) + 7) / 8 * 8);
+    for (int kind = 1; kind >= 0; --kind) {
+      std::vector<const BCube*> cs;
+      for (auto& q : b->cubes)
+        if (q.wave == wv && q.kind == kind) cs.push_back(&q);
+      if (cs.empty()) continue;
+      // tile cost: MACs of one tile = tile area x pixels of one chunk (the area is the same for all
+      // cubes of one kind)
+      std::stable_sort(cs.begin(), cs.end(), [](const BCube* x, const BCube* y) {
+        return (long long)x->n * x->n / x->kchunks > (long long)y->n * y->n / y->kchunks;
+      });
+      std::vector<MabsGemmArgs> gs;
+      for (const BCube* q : cs) gs.push_back(gemm_args(*q, b->arena, q->kchunks));
+      const std::vector<int> qo = queue_offsets(kind, gs);
+      bs_batch::PLaunch L{wv, kind, {}};
+      L.args.groups = upload(b, gs);
+      L.args.qoff = upload(b, qo);
+      L.args.ngroups = (int)gs.size();
+      L.args.counters = (int*)balloc(b, 8 * sizeof(int));
+      if (!L.args.groups || !L.args.qoff || !L.args.counters) return restore_fail(ctx_fail(c, BS_ENOMEM, "queue tables"));
+      b->launches.push_back(L);
     }
-    b->ngroups.push_back((int)gs.size());
-    b->nblocks.push_back(offs.back());
-    b->d_groups.push_back(gs.empty() ? nullptr : upload(b, gs));
-    b->d_offs.push_back(gs.empty() ? nullptr : upload(b, offs));
-    if (!gs.empty() && (!b->d_groups.back() || !b->d_offs.back()))
-      return restore_fail(ctx_fail(c, BS_ENOMEM, "group tables"));
   }
   HIPCHK(c, hipStreamSynchronize(b->s));
   // ---- capture the whole batch ----
@@ -373,8 +465,8 @@ extern "C" int bs_batch_create(bs_ctx* c, const bs_batch_cube* cubes, int32_t nc
   for (int wv = 0; wv < b->nwaves; ++wv) {
     for (auto& q : b->cubes)
       if (q.wave == wv) enqueue_front(q, b->arena, b->s);
-    if (b->ngroups[wv])
-      launch_mabs_gemm_split_grouped(b->d_groups[wv], b->d_offs[wv], b->ngroups[wv], b->nblocks[wv], b->s);
+    for (const auto& L : b->launches)
+      if (L.wave == wv) launch_mabs_gemm_persist(L.kind, L.args, b->grid, b->s);
     for (auto& q : b->cubes) {
       if (q.wave != wv) continue;
       MabsSubsetArgs a{};
@@ -425,6 +517,41 @@ extern "C" int bs_batch_info(const bs_batch* b, int32_t cube, int32_t* n_cand, i
   if (wave) *wave = q.wave;
   if (kchunks) *kchunks = q.kchunks;
   if (products) *products = q.products;
+  return BS_OK;
+}
+
+extern "C" int bs_batch_tile(const bs_batch* b, int32_t cube, int32_t* tile_m, int32_t* tile_n, int32_t* m1,
+                             int32_t* kchunks) {
+  if (!b || cube < 0 || cube >= (int)b->cubes.size()) return BS_EINVAL;
+  const BCube& q = b->cubes[cube];
+  if (tile_m) *tile_m = q.kind ? 256 : 128;
+  if (tile_n) *tile_n = q.kind ? 192 : 256;
+  if (m1) *m1 = q.kind ? q.m1 : 0;
+  if (kchunks) *kchunks = q.kchunks;
+  return BS_OK;
+}
+
+extern "C" int bs_tune_set(bs_ctx* c, int32_t n, int32_t nc, int32_t n_nu1, int32_t nrings, int32_t tile_m, int32_t m1,
+                           int32_t kchunks) {
+  if (!c) return BS_EINVAL;
+  const int kind = tile_m == 256 ? 1 : (tile_m == 128 ? 0 : -1);
+  if (kind < 0 || n < 16 || n % 8 || nc < 1 || n_nu1 < 1 || n_nu1 > nc || nrings < 1 || nrings > 64 ||
+      !tile_ok(kind, kind ? m1 : 0, kchunks, n, n_nu1))
+    return ctx_fail(c, BS_EINVAL, "bs_tune_set: this tile cannot run the cube shape");
+  c->tuned[tile_key(n, nc, n_nu1, nrings)] = tile_code(kind, kind ? m1 : 0, kchunks);
+  return BS_OK;
+}
+
+extern "C" int bs_tune_get(bs_ctx* c, int32_t n, int32_t nc, int32_t n_nu1, int32_t nrings, int32_t* tile_m,
+                           int32_t* tile_n, int32_t* m1, int32_t* kchunks) {
+  if (!c) return BS_EINVAL;
+  int kind = -1, mm = 0, k = 0;
+  auto it = c->tuned.find(tile_key(n, nc, n_nu1, nrings));
+  if (it != c->tuned.end()) tile_decode(it->second, kind, mm, k);
+  if (tile_m) *tile_m = kind < 0 ? 0 : (kind ? 256 : 128);
+  if (tile_n) *tile_n = kind < 0 ? 0 : (kind ? 192 : 256);
+  if (m1) *m1 = kind == 1 ? mm : 0;
+  if (kchunks) *kchunks = kind < 0 ? 0 : k;
   return BS_OK;
 }
 

@@ -44,6 +44,7 @@ struct MabsGemmArgs {
   int kchunk, kchunks;      // pixels per chunk, number of chunks
   long long bin_stride;     // nc * P
   double* S;                // [kchunks][ntri][n_nu1*nc][nc]
+  int tile_m1;              // 256 x 192 split tiles: nu1 rows per tile (4, 8, 16 or 32); 0 picks by n_nu1
 };
 
 struct MabsFinalArgs {
@@ -93,6 +94,18 @@ int mabs_split_blocks(const MabsGemmArgs& a);
 void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* offs_dev, int ngroups, int nblocks,
                                     hipStream_t s);
 void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s);
+// Persistent split-BF16 contraction over ngroups GEMMs of one tile kind (0: 128 x 256 tiles,
+// 1: 256 x 192 tiles over nu1 x nu2 row blocks of tile_m1 x 256/tile_m1).  qoff[x][g] (x < 8, g <=
+// ngroups) is the prefix over groups of the tiles that queue x holds: per = tiles/8 of group g,
+// plus one when x < tiles mod 8.  counters: 8 ints of device memory, zeroed by the launch itself.
+struct MabsPersistArgs {
+  const MabsGemmArgs* groups;   // device [ngroups], largest tile cost first
+  const int* qoff;              // device [8][ngroups + 1]
+  int ngroups;
+  int* counters;                // device [8]
+};
+int mabs_split3_tiles(const MabsGemmArgs& a);
+void launch_mabs_gemm_persist(int kind, const MabsPersistArgs& p, int nblocks, hipStream_t s);
 // Tsum[t] = npix^2 * sum_p I_b1 I_b2 I_b3 over channel-independent FP64 count fields [nb][P].
 void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s);
 void launch_round_counts(const double* x, int n, int64_t* out, unsigned long long* maxdev, hipStream_t s);

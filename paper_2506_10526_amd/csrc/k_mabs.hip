@@ -400,19 +400,23 @@ struct SplitFrags {
   bf16x8 ah[2], al[2], bh[4], bl[4];
 };
 
-// One block tile of GEMM `a`; b0 is the block's index within this GEMM's nb = rtiles ctiles ntri
-// kchunks blocks.
-__device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsigned char* smem_raw) {
+// XCD-aware order of the tiles of one GEMM: blocks are dealt to the eight XCDs round-robin, so
+// block b0 runs on XCD b0 mod 8; it takes tile (b0 mod 8) (nb/8) + b0/8, which gives each XCD a
+// contiguous run of tiles (the row tiles of one column tile and pixel chunk share their B operand
+// in that XCD's L2).  The last nb mod 8 tiles keep their index.
+__device__ __forceinline__ int xcd_tile(int b0, int nb) {
+  const int full = (nb / 8) * 8;
+  return b0 < full ? (b0 & 7) * (full / 8) + (b0 >> 3) : b0;
+}
+
+// One block tile of GEMM `a`; b is the tile's index within this GEMM's nb = rtiles ctiles ntri
+// kchunks tiles, row tile fastest.
+__device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b, unsigned char* smem_raw) {
   uint16_t* lds = (uint16_t*)smem_raw;   // [S_NBUF][S_BUF]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int nrows = a.n_nu1 * a.nc;
   const int rtiles = (nrows + S_TM - 1) / S_TM, ctiles = (a.nc + S_TN - 1) / S_TN;
-  const int nb = rtiles * ctiles * a.ntri * a.kchunks;
-  // XCD-aware remap of the linear block id (blocks are dealt to the eight XCDs round-robin)
-  int b = b0;
-  const int full = (nb / 8) * 8;
-  if (b < full) b = (b & 7) * (full / 8) + (b >> 3);
   const int rt = b % rtiles;
   int rest = b / rtiles;
   const int ct = rest % ctiles;
@@ -653,9 +657,13 @@ __device__ __forceinline__ void split2_tile(const MabsGemmArgs& a, int b0, unsig
   __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS may outlive the block
 }
 
+__device__ __forceinline__ int split2_tiles(const MabsGemmArgs& a) {
+  return ((a.n_nu1 * a.nc + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
+}
+
 __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  split2_tile(a, blockIdx.x, smem_raw);
+  split2_tile(a, xcd_tile(blockIdx.x, split2_tiles(a)), smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,25 +695,25 @@ static_assert(T3_RAW >= T3_RAWMAX * T3_RAWLD, "raw buffer holds every raw row");
 static_assert(2 * (size_t)(T3_ABUF + T3_BBUF) * 2 + 2 * (size_t)T3_RAW * 4 <= 160 * 1024, "stage and raw buffers fit in LDS");
 
 
-__device__ __forceinline__ int t3_m1(int n_nu1) { return n_nu1 >= 16 ? 16 : (n_nu1 >= 8 ? 8 : 4); }
+__device__ __forceinline__ int t3_m1(const MabsGemmArgs& a) {
+  return a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4));
+}
+__device__ __forceinline__ int split3_tiles(const MabsGemmArgs& a) {
+  const int m1 = t3_m1(a), m2 = T3_M / m1;
+  return ((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) * a.ntri * a.kchunks;
+}
 
 // The six LDS buffers (A, B and raw rows, two of each) are separate variables, so that the compiler
 // can tell the copies into one from the reads and stores of another and does not wait for every
 // copy in flight before them.
-__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint16_t* abuf0, uint16_t* abuf1,
+__device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b, uint16_t* abuf0, uint16_t* abuf1,
                                             uint16_t* bbuf0, uint16_t* bbuf1, float* raw0, float* raw1) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
-  const int m1 = t3_m1(a.n_nu1), m2 = T3_M / m1, lm2 = __builtin_ctz(m2);
+  const int m1 = t3_m1(a), m2 = T3_M / m1, lm2 = __builtin_ctz(m2);
   const int r1t = (a.n_nu1 + m1 - 1) / m1, r2t = (a.nc + m2 - 1) / m2, rtiles = r1t * r2t;
   const int ctiles = (a.nc + T3_N - 1) / T3_N;
-  const int nb = rtiles * ctiles * a.ntri * a.kchunks;
-  // XCD-aware remap of the linear block id (blocks are dealt to the eight XCDs round-robin): the
-  // row tiles of one (column tile, triangle, pixel chunk), which share B, run on one XCD
-  int b = b0;
-  const int full = (nb / 8) * 8;
-  if (b < full) b = (b & 7) * (full / 8) + (b >> 3);
   const int rt = b % rtiles;
   int rest = b / rtiles;
   const int ct = rest % ctiles;
@@ -953,7 +961,7 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b0, uint1
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_split3(MabsGemmArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t abuf0[T3_ABUF], abuf1[T3_ABUF], bbuf0[T3_BBUF], bbuf1[T3_BBUF];
   __shared__ __attribute__((aligned(16))) float raw0[T3_RAW], raw1[T3_RAW];
-  split3_tile(a, blockIdx.x, abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
+  split3_tile(a, xcd_tile(blockIdx.x, split3_tiles(a)), abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
 }
 
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
@@ -965,11 +973,67 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemm
   int g = 0;
   while (g + 1 < ngroups && offs[g + 1] <= b) ++g;
   const MabsGemmArgs a = groups[g];
-  const int nrows = a.n_nu1 * a.nc;
-  const int nb = ((nrows + S_TM - 1) / S_TM) * ((a.nc + S_TN - 1) / S_TN) * a.ntri * a.kchunks;
+  const int nb = split2_tiles(a);
   const int lb = b - offs[g];
   if (lb >= nb) return;   // alignment padding
-  split2_tile(a, lb, smem_raw);
+  split2_tile(a, xcd_tile(lb, nb), smem_raw);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent split-BF16 contraction over many GEMMs (cubes of uneven sizes, each with its own tile
+// choice): a grid of one block per CU (both tile kinds take more than half of a CU's LDS) pulls
+// tiles from eight work queues, one per XCD, until every queue is empty.  Queue x holds, for each
+// GEMM in the order given (largest tile cost first), the run of that GEMM's tiles that the
+// XCD-aware order gives to XCD x.  A block drains the queue of its own XCD first (block b runs on
+// XCD b mod 8), so tiles that share an operand mostly meet in one L2, and then takes tiles from
+// the other queues, so that no CU idles while work remains.  A pull is one atomic add on the
+// queue's counter (zero at launch); a block leaves after one failed pull on each of the eight
+// queues, so every block exits.  Tiles write disjoint outputs, so the result does not depend on
+// which block takes which tile.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ int persist_pull(const MabsPersistArgs& p, int& x, int& q, int* pull_sh, MabsGemmArgs& a) {
+  // returns the tile index inside GEMM a, or -1 when every queue is empty
+  while (q < 8) {
+    x = ((int)blockIdx.x + q) & 7;
+    __syncthreads();   // every wave is done with the previous tile's LDS and with pull_sh
+    if (threadIdx.x == 0) *pull_sh = atomicAdd(&p.counters[x], 1);
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(*pull_sh);
+    const int* qo = p.qoff + x * (p.ngroups + 1);
+    if (j >= qo[p.ngroups]) { ++q; continue; }
+    int g = 0;
+    while (qo[g + 1] <= j) ++g;
+    g = __builtin_amdgcn_readfirstlane(g);
+    a = p.groups[g];
+    const int nb = KIND ? split3_tiles(a) : split2_tiles(a);
+    const int per = nb / 8, lj = j - qo[g];
+    return lj < per ? x * per + lj : 8 * per + x;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_persist3(MabsPersistArgs p) {
+  __shared__ __attribute__((aligned(16))) uint16_t abuf0[T3_ABUF], abuf1[T3_ABUF], bbuf0[T3_BBUF], bbuf1[T3_BBUF];
+  __shared__ __attribute__((aligned(16))) float raw0[T3_RAW], raw1[T3_RAW];
+  __shared__ int pull_sh;
+  int x = 0, q = 0;
+  MabsGemmArgs a;
+  for (int t; (t = persist_pull<1>(p, x, q, &pull_sh, a)) >= 0;)
+    split3_tile(a, t, abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_persist2(MabsPersistArgs p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  __shared__ int pull_sh;
+  int x = 0, q = 0;
+  MabsGemmArgs a;
+  for (int t; (t = persist_pull<0>(p, x, q, &pull_sh, a)) >= 0;) split2_tile(a, t, smem_raw);
+}
+
+__global__ void k_zero_i32(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1202,7 +1266,7 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
   }
   if (a.n_nu1 >= 4 && !getenv("BS_MABS_TILE128")) {
     // 256 x 256 tiles over (nu1 block x nu2 block) rows
-    const int m1 = a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4), m2 = T3_M / m1;
+    const int m1 = a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4)), m2 = T3_M / m1;
     const long long nb = (long long)((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) *
                          a.ntri * a.kchunks;
     hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), 0, s, a);
@@ -1224,6 +1288,21 @@ void launch_mabs_gemm_split_grouped(const MabsGemmArgs* groups_dev, const int* o
   const size_t lds = S_NBUF * (size_t)S_BUF * 2;
   (void)hipFuncSetAttribute((const void*)k_mabs_gemm_split2_grouped, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_mabs_gemm_split2_grouped, dim3((unsigned)nblocks), dim3(256), lds, s, groups_dev, offs_dev, ngroups);
+}
+int mabs_split3_tiles(const MabsGemmArgs& a) {
+  const int m1 = a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4)), m2 = T3_M / m1;
+  return ((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) * a.ntri * a.kchunks;
+}
+void launch_mabs_gemm_persist(int kind, const MabsPersistArgs& p, int nblocks, hipStream_t s) {
+  if (nblocks <= 0 || p.ngroups <= 0) return;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, p.counters, 8);
+  if (kind) {
+    hipLaunchKernelGGL(k_mabs_gemm_persist3, dim3(nblocks), dim3(256), 0, s, p);
+  } else {
+    const size_t lds = S_NBUF * (size_t)S_BUF * 2;
+    (void)hipFuncSetAttribute((const void*)k_mabs_gemm_persist2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_mabs_gemm_persist2, dim3(nblocks), dim3(256), lds, s, p);
+  }
 }
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
