@@ -964,6 +964,242 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   split3_tile(a, xcd_tile(blockIdx.x, split3_tiles(a)), abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 contraction on FP32 MFMA (v_mfma_f32_32x32x2_f32), 128 x 128 tiles laid out like the split
+// kernel above: rows are an m1 x (128 / m1) block of (nu1, nu2), the A tile is formed in LDS from
+// the m1 + m2 raw FP32 rows (one FP32 product per element), B is the F_b3 rows copied straight into
+// LDS.  Each wave owns 64 x 64 outputs (2 x 2 MFMA tiles); 80 KB of LDS and at most 256 registers
+// a lane let two blocks share a CU.  LDS rows hold 32 floats as eight
+// 16-byte chunks, chunk c of row r stored at slot c ^ (r ^ r >> 3) & 7, so that 16-byte accesses
+// of one chunk by 8, 16 or 32 consecutive rows meet distinct slots of a 128-, 256- or 512-byte bank
+// line.  A lane's 16-byte fragment read serves four MFMA steps: step e pairs pixels 8q + e and
+// 8q + 4 + e of an 8-pixel group q (lanes 0-31 and 32-63), the same pairing on both operands.
+// Per 32-pixel stage a wave issues 64 MFMAs (64 cycles each); the B copies of stage s+1 and the raw
+// copies of stage s+2 go out first, the A formation of stage s+1 runs between the MFMAs, and the
+// next 8-pixel group's fragments are read while the current group's MFMAs run; one wait and one
+// barrier per stage.  Accumulation: FP32 MFMA sums over runs of 256 pixels are added into a second
+// FP32 accumulator, which goes into the FP64 output every 8192 pixels (the first time a store,
+// later FP64 atomics), so no FP32 sum takes more than 256 products before it joins a larger sum.
+// ---------------------------------------------------------------------------
+constexpr int F4_M = 128, F4_N = 128, F4_RUN = 256, F4_FLUSH = 8192;
+constexpr int F4_AB = F4_M * T3_K, F4_BB = F4_N * T3_K;   // floats per A / B stage buffer (16 KB each)
+constexpr int F4_RAW = 8 * 64 * 4;                        // floats per raw buffer: 8 copy instructions
+static_assert(F4_RAW >= 36 * T3_RAWLD, "raw buffer holds the m1 + m2 <= 36 raw rows");
+__device__ __forceinline__ int f4_swz(int r, int c) { return c ^ ((r ^ (r >> 3)) & 7); }
+__device__ __forceinline__ int f4_m1(const MabsGemmArgs& a) {
+  return a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4));
+}
+__device__ __forceinline__ int f32t_tiles(const MabsGemmArgs& a) {
+  const int m1 = f4_m1(a), m2 = F4_M / m1;
+  return ((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + F4_N - 1) / F4_N) * a.ntri * a.kchunks;
+}
+
+__device__ __forceinline__ void f32t_tile(const MabsGemmArgs& a, int b, float* abuf0, float* abuf1, float* bbuf0,
+                                          float* bbuf1, float* raw0, float* raw1) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m1 = f4_m1(a), m2 = F4_M / m1, lm2 = __builtin_ctz(m2);
+  const int r1t = (a.n_nu1 + m1 - 1) / m1, r2t = (a.nc + m2 - 1) / m2, rtiles = r1t * r2t;
+  const int ctiles = (a.nc + F4_N - 1) / F4_N;
+  const int rt = b % rtiles;
+  int rest = b / rtiles;
+  const int ct = rest % ctiles;
+  rest /= ctiles;
+  const int kc = rest % a.kchunks;
+  const int t = rest / a.kchunks;
+  const int i0 = (rt / r2t) * m1, n20 = (rt % r2t) * m2, col0 = ct * F4_N;
+  const int b1 = a.tri[3 * t], b2 = a.tri[3 * t + 1], b3 = a.tri[3 * t + 2];
+  const int kbeg = __builtin_amdgcn_readfirstlane(kc * a.kchunk);
+  const int kend = __builtin_amdgcn_readfirstlane(min(a.P, kbeg + a.kchunk));
+  const int nst = (kend - kbeg) / T3_K;   // >= 1; pixel ranges are multiples of T3_K
+  const int klast = kend - T3_K;          // copies past the range re-read the last stage
+
+  // raw copies: chunk g of (m1 + m2) x 9 (row q = g / 9, chunk c = g % 9, the ninth a pad that
+  // re-reads chunk 0), rows q < m1 F_b1 at nu1[i0 + q], the rest F_b2 at nu2 = n20 + q - m1 (both
+  // clamped to a valid row; such products are never stored); two copy instructions a wave, chunks
+  // past the row set re-read the last row into the unused tail of the buffer
+  const float* rsrc[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int g = (wave + 4 * k) * 64 + lane;
+    const int q = min(g / 9, m1 + m2 - 1), c = g % 9 == 8 ? 0 : g % 9;
+    const float* row = q < m1 ? a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[min(i0 + q, a.n_nu1 - 1)] * a.P
+                              : a.F + (size_t)b2 * a.bin_stride + (size_t)min(n20 + q - m1, a.nc - 1) * a.P;
+    rsrc[k] = row + 4 * c;
+  }
+  // B copies: this wave's columns w*32 .. w*32+31, eight a copy instruction (lane l: column l / 8,
+  // LDS slot l % 8, which holds global chunk (l % 8) ^ swizzle)
+  size_t boff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int br = wave * 32 + q * 8 + (lane >> 3);
+    const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
+    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 4 * f4_swz(br, lane & 7);
+  }
+  // A formation: threads 2r, 2r + 1 own tile row r = (i1, i2), i2 = r mod m2, chunks 4h .. 4h + 3
+  const int fr = tid >> 1, fh = tid & 1, fi1 = fr >> lm2, fi2 = fr & (m2 - 1);
+  const int rawf1 = fi1 * T3_RAWLD, rawf2 = (m1 + fi2) * T3_RAWLD;
+  // fragment offsets (floats, inside a stage buffer) per 8-pixel group q
+  int oa[4][2], ob[4][2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int chunk = 2 * q + (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 64 + i * 32 + (lane & 31);
+      oa[q][i] = r * T3_K + 4 * f4_swz(r, chunk);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wn * 64 + j * 32 + (lane & 31);
+      ob[q][j] = c * T3_K + 4 * f4_swz(c, chunk);
+    }
+  }
+  auto copy_b1 = [&](int q, int k0, float* buf) {
+    __builtin_amdgcn_global_load_lds((const void*)(a.F + boff[q] + k0), (lds_void*)(buf + (wave * 32 + q * 8) * T3_K),
+                                     16, 0, 0);
+  };
+  auto copy_raw1 = [&](int k, int k0, float* rb) {
+    __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + (wave + 4 * k) * 256), 16, 0, 0);
+  };
+  float4 R1, R2;
+  auto form_read = [&](int c, const float* rb) {   // chunk 4 fh + c of this thread's row
+    R1 = *(const float4*)&rb[rawf1 + 4 * (4 * fh + c)];
+    R2 = *(const float4*)&rb[rawf2 + 4 * (4 * fh + c)];
+  };
+  auto form_write = [&](int c, float* buf) {
+    const float4 v = {R1.x * R2.x, R1.y * R2.y, R1.z * R2.z, R1.w * R2.w};
+    *(float4*)(buf + fr * T3_K + 4 * f4_swz(fr, 4 * fh + c)) = v;
+  };
+  float4 fa[2][2], fb[2][2];
+  auto read_frags = [&](int par, int q, const float* ab, const float* bb) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fa[par][i] = *(const float4*)&ab[oa[q][i]];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) fb[par][j] = *(const float4*)&bb[ob[q][j]];
+  };
+
+  f32x16 acc[2][2], acc2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = acc2[i][j][e] = 0.f;
+  auto mfma1 = [&](int par, int m) {   // MFMA m of 16 of an 8-pixel group: step m / 4, tile m % 4
+    const int e = m / 4, i = (m % 4) / 2, j = m % 2;
+    const float x = e == 0 ? fa[par][i].x : (e == 1 ? fa[par][i].y : (e == 2 ? fa[par][i].z : fa[par][i].w));
+    const float y = e == 0 ? fb[par][j].x : (e == 1 ? fb[par][j].y : (e == 2 ? fb[par][j].z : fb[par][j].w));
+    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc[i][j], 0, 0, 0);
+  };
+
+  const int nrows = a.n_nu1 * a.nc;
+  double* S = a.S + ((size_t)kc * a.ntri + t) * (size_t)nrows * a.nc;
+  bool first_flush = true;
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) { acc2[i][j][e] += acc[i][j][e]; acc[i][j][e] = 0.f; }
+  };
+  auto flush = [&]() {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = col0 + wn * 64 + j * 32 + (ln & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int r = wm * 64 + i * 32 + (e >> 2) * 8 + (ln >> 5) * 4 + (e & 3);
+          const int ii = i0 + (r >> lm2), nu2 = n20 + (r & (m2 - 1));
+          if (ii < a.n_nu1 && nu2 < a.nc && col < a.nc) {
+            double* d = &S[((size_t)ii * a.nc + nu2) * a.nc + col];
+            const double v = (double)acc2[i][j][e];
+            if (first_flush) *d = v;
+            else unsafeAtomicAdd(d, v);
+          }
+          acc2[i][j][e] = 0.f;
+        }
+      }
+    first_flush = false;
+  };
+
+  // prologue: B of stage 0 and raw rows of stages 0 and 1 land, A of stage 0 is formed
+#pragma unroll
+  for (int q = 0; q < 4; ++q) copy_b1(q, kbeg, bbuf0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) copy_raw1(k, kbeg, raw0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) copy_raw1(k, min(kbeg + T3_K, klast), raw1);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    form_read(c, raw0);
+    form_write(c, abuf0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+
+  // Stage s: four 8-pixel groups of 16 MFMA slots; copies in the first six slots, the A formation
+  // of stage s+1 (four chunks: a raw read, six slots later the product and its store) from slot 10
+  // on, the next group's fragments read in slot 2 of each group.
+  auto stage = [&](int s, auto par) {
+    constexpr int PAR = decltype(par)::value;
+    const float* ac = PAR ? abuf1 : abuf0;   // A and B of stage s
+    const float* bc = PAR ? bbuf1 : bbuf0;
+    float* an = PAR ? abuf0 : abuf1;         // A and B of stage s+1
+    float* bn = PAR ? bbuf0 : bbuf1;
+    const float* rawc = PAR ? raw0 : raw1;   // raw rows of stage s+1
+    float* rawn = PAR ? raw1 : raw0;         // raw rows of stage s+2 land here
+    const int kb = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 1) * T3_K, klast));
+    const int kr = __builtin_amdgcn_readfirstlane(min(kbeg + (s + 2) * T3_K, klast));
+    read_frags(0, 0, ac, bc);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma clang loop unroll(full)
+    for (int sl = 0; sl < 64; ++sl) {
+      const int q = sl / 16, m = sl % 16;
+      mfma1(q & 1, m);
+      if (sl < 4) copy_b1(sl, kb, bn);
+      else if (sl < 6) copy_raw1(sl - 4, kr, rawn);
+      if (q < 3 && m == 2) read_frags((q + 1) & 1, q + 1, ac, bc);
+      if (sl >= 10 && sl < 10 + 4 * 12 && (sl - 10) % 12 == 0) form_read((sl - 10) / 12, rawc);
+      if (sl >= 16 && sl < 16 + 4 * 12 && (sl - 16) % 12 == 0) form_write((sl - 16) / 12, an);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // B of stage s+1, raw rows of stage s+2 landed; A of stage s+1 stored
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  for (int s = 0; s < nst;) {
+    const int se = min(nst, s + F4_FLUSH / T3_K);   // s is a multiple of F4_RUN / T3_K here
+    while (s < se) {
+      const int re = min(se, s + F4_RUN / T3_K);    // s is even here
+      while (true) {
+        stage(s, std::integral_constant<int, 0>{});
+        if (++s >= re) break;
+        stage(s, std::integral_constant<int, 1>{});
+        if (++s >= re) break;
+      }
+      fold();
+    }
+    flush();
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS may outlive the block
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mabs_gemm_f32t(MabsGemmArgs a) {
+  __shared__ __attribute__((aligned(16))) float abuf0[F4_AB], abuf1[F4_AB], bbuf0[F4_BB], bbuf1[F4_BB];
+  __shared__ __attribute__((aligned(16))) float raw0[F4_RAW], raw1[F4_RAW];
+  f32t_tile(a, xcd_tile(blockIdx.x, f32t_tiles(a)), abuf0, abuf1, bbuf0, bbuf1, raw0, raw1);
+}
+
 // Several independent GEMMs (e.g. cubes of different sizes) in one launch: group g owns blocks
 // [offs[g], offs[g+1]); offsets are multiples of 8 so that the XCD remap of each group holds.
 __global__ __launch_bounds__(256) void k_mabs_gemm_split2_grouped(const MabsGemmArgs* __restrict__ groups,
@@ -1265,11 +1501,13 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
     return;
   }
   if (a.n_nu1 >= 4 && !getenv("BS_MABS_TILE128")) {
-    // 256 x 256 tiles over (nu1 block x nu2 block) rows
-    const int m1 = a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4)), m2 = T3_M / m1;
+    // 256 x 192 tiles over (nu1 block x nu2 block) rows
+    MabsGemmArgs b = a;
+    if (const char* e = getenv("BS_MABS_M1")) b.tile_m1 = atoi(e);   // tuning switch: 4, 8, 16 or 32
+    const int m1 = b.tile_m1 ? b.tile_m1 : (b.n_nu1 >= 16 ? 16 : (b.n_nu1 >= 8 ? 8 : 4)), m2 = T3_M / m1;
     const long long nb = (long long)((a.n_nu1 + m1 - 1) / m1) * ((a.nc + m2 - 1) / m2) * ((a.nc + T3_N - 1) / T3_N) *
                          a.ntri * a.kchunks;
-    hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_mabs_gemm_split3, dim3((unsigned)nb), dim3(256), 0, s, b);
     return;
   }
   const int nrows = a.n_nu1 * a.nc;
@@ -1305,6 +1543,15 @@ void launch_mabs_gemm_persist(int kind, const MabsPersistArgs& p, int nblocks, h
   }
 }
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
+  if (a.n_nu1 >= 4 && !getenv("BS_MABS_F32_TILE128")) {
+    MabsGemmArgs b = a;
+    if (const char* e = getenv("BS_MABS_M1")) b.tile_m1 = atoi(e);   // tuning switch: 4, 8, 16 or 32
+    const int m1 = b.tile_m1 ? b.tile_m1 : (b.n_nu1 >= 16 ? 16 : (b.n_nu1 >= 8 ? 8 : 4)), m2 = 128 / m1;
+    const long long nb = (long long)((b.n_nu1 + m1 - 1) / m1) * ((b.nc + m2 - 1) / m2) * ((b.nc + 127) / 128) *
+                         b.ntri * b.kchunks;
+    hipLaunchKernelGGL(k_mabs_gemm_f32t, dim3((unsigned)nb), dim3(256), 0, s, b);
+    return;
+  }
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
 }
 void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s) {
