@@ -148,6 +148,73 @@ def baseline_log_var(edges: np.ndarray, tri: np.ndarray, T3D: np.ndarray, nvox: 
     return np.where(T > 0, out, -np.inf)
 
 
+# ------------------------------------------------------------------------------------------------
+# Flag-aware inputs.  Flags multiply the cube by w(nu) along frequency; the delay transform of the
+# product is the circular convolution of each line's transform with w~ / nc (Sec. 2.2 delay
+# transform, Sec. 4 flagging), so a Gaussian field of power P is seen with the power
+#     P_w(k_perp, eta) = sum_q c_q P(k_perp, eta - q),   c_q = |w~(q)|^2 / nc^2,
+# w~ the unnormalised DFT of w.  The Gaussian variance of a triangle average is proportional to the
+# mean over its closed triangles of P_w(k1) P_w(k2) P_w(k3) (times N_vox / T3D, divided by rho3^2
+# for the N_eff normalisation); G below is that mean.
+def window_power_weights(chan_w: np.ndarray) -> np.ndarray:
+    """c_q = |sum_nu w(nu) e^(-2 pi i q nu / nc)|^2 / nc^2 for q = 0 .. nc-1."""
+    w = np.asarray(chan_w, dtype=np.float64)
+    nc = len(w)
+    nu = np.arange(nc)
+    wt = np.array([np.sum(w * np.exp(-2j * np.pi * q * nu / nc)) for q in range(nc)])
+    return np.abs(wt) ** 2 / nc ** 2
+
+
+def windowed_power(n: int, nc: int, du: float, r_mpc: float, rprime: float, dnu: float, chan_w,
+                   pk_index: float, rel_cut: float = 1e-13) -> np.ndarray:
+    """P_w on the [nc][n][n//2+1] delay grid (delay axis first, signed index order of the FFT):
+    P(k) = |k|^pk_index with P(0) = 0, |k| as for the shell bins; the sum over q skips the c_q
+    below rel_cut * c_0 (exactly zero for periodic masks up to rounding)."""
+    from .bins import shell_kmag
+    k = shell_kmag(n, nc, du, r_mpc, rprime, dnu)
+    with np.errstate(divide="ignore"):
+        P = np.where(k > 0, k ** pk_index, 0.0)
+    c = window_power_weights(np.ones(nc) if chan_w is None else chan_w)
+    out = np.zeros_like(P)
+    for q in range(nc):
+        if c[q] > rel_cut * c[0]:
+            out += c[q] * np.roll(P, q, axis=0)     # out[i] += c_q P[i - q mod nc]
+    return out
+
+
+def flag_proxy(bins, du: float, r_mpc: float, rprime: float, dnu: float, chan_w, pk_index: float,
+               counts=None) -> np.ndarray:
+    """G_t = mean over the closed triangles of candidate t of P_w(k1) P_w(k2) P_w(k3), by the 3D
+    estimator's FFT route on a cube whose delay transform is P_w (NaN where T3D = 0)."""
+    from .estimator import estimate_3d
+    Pw = windowed_power(bins.n, bins.nc, du, r_mpc, rprime, dnu, chan_w, pk_index)
+    V = np.fft.ifft(Pw, axis=0)
+    B, T, _, _, _ = estimate_3d(bins, V, None, counts=counts)
+    return B * float(bins.nc * bins.n * bins.n)
+
+
+def features_flag(edges: np.ndarray, tri: np.ndarray, G: np.ndarray, G1: np.ndarray, rho3: float) -> np.ndarray:
+    """(log k1, log k2, log k3, log(G / G1) - 2 log rho3) per triangle (NaN where G or G1 <= 0)."""
+    c = np.log(np.sqrt(edges[:-1] * edges[1:]))
+    tri = np.asarray(tri)
+    G = np.asarray(G, dtype=np.float64)
+    G1 = np.asarray(G1, dtype=np.float64)
+    ok = (G > 0) & (G1 > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(ok, np.log(np.where(ok, G, 1.0) / np.where(ok, G1, 1.0)) - 2.0 * np.log(rho3), np.nan)
+    return np.column_stack([c[tri[:, 0]], c[tri[:, 1]], c[tri[:, 2]], f])
+
+
+def baseline_flag(T3D: np.ndarray, nvox: int, G: np.ndarray, rho3: float) -> np.ndarray:
+    """log(N_vox / T3D) + log G - 2 log rho3 per triangle (-inf where T3D = 0 or G <= 0)."""
+    T = np.asarray(T3D, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    ok = (T > 0) & (G > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.log(nvox / np.where(ok, T, 1.0)) + np.log(np.where(ok, G, 1.0)) - 2.0 * np.log(rho3)
+    return np.where(ok, out, -np.inf)
+
+
 def train(theta: np.ndarray, x: np.ndarray, t: np.ndarray, steps: int, lr: float = 1e-3, cosine: bool = False):
     """Full-batch Adam on normalised data; returns (theta, losses)."""
     opt = Adam(theta.size, lr=lr)
