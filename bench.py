@@ -408,8 +408,9 @@ def batch_block(bs, ctx, torch, ncubes=64, seed=4):
 
 
 def surrogate_block(bs, ctx, bins, ncand, w, torch):
-    """Labels (4 flag patterns x 256 realizations), GPU training, evaluation against 1024 fresh
-    realizations of a training pattern and of an unseen one; next to 200-realization Monte Carlo."""
+    """Labels (7 flag patterns x 1024 realizations), GPU training with the per-triangle flag summary,
+    evaluation against 4096 fresh realizations of config 3's pattern and of two unseen patterns;
+    next to 200-realization Monte Carlo and the noise floor of the references."""
     from paper_2506_10526_amd import surrogate, synth
     desc = bs.field_desc(w.n, w.nc, bs.BS_K_PHYSICAL, du_lambda=w.du, r_mpc=w.r_mpc,
                          rprime_mpc_per_mhz=w.rprime, dnu_mhz=w.dnu)
@@ -419,32 +420,40 @@ def surrogate_block(bs, ctx, bins, ncand, w, torch):
     N = torch.empty(ncand, dtype=torch.int64, device="cuda")
     bs.bs_estimate_3d(ctx, bins, V, bs.BS_SPLIT_BF16, B, N)
     T3D = N.cpu().numpy()
-    flags = {e: synth.mwa_flags(w.nc, surrogate.edge_flags(e)) for e in (0, 1, 2, 3, 4)}
-    train = [surrogate.mc_run(ctx, bins, ncand, desc, flags[e], 256, 100 + e) for e in (0, 1, 2, 4)]
-    X, tgt = surrogate.training_set(bins, ncand, T3D, train, -2.0)
+    pats = dict(surrogate.TRAIN_PATTERNS, **surrogate.UNSEEN_PATTERNS)
+    flags = {k: (synth.mwa_flags(w.nc, v) if v else np.ones(w.nc)) for k, v in pats.items()}
+    t0 = time.perf_counter()
+    ff = surrogate.FlagFeatures(ctx, bins, ncand, T3D, -2.0)
+    names = list(surrogate.TRAIN_PATTERNS)
+    train = [surrogate.mc_run(ctx, bins, ncand, desc, flags[k], 1024, 100 + i) for i, k in enumerate(names)]
+    X, tgt = surrogate.training_set_flag(ff, train, [flags[k] for k in names])
+    t_feat = time.perf_counter() - t0 - sum(r.seconds for r in train)
     sur = surrogate.Surrogate(ctx, seed=1)
     try:
-        fit = sur.fit(X, tgt, steps=4000, lr=3e-3, cosine=True)
-        j1 = surrogate.mc_run(ctx, bins, ncand, desc, flags[1], 1024, 1000)
-        j3 = surrogate.mc_run(ctx, bins, ncand, desc, flags[3], 1024, 2000)
-        m200 = surrogate.mc_run(ctx, bins, ncand, desc, flags[1], 200, 3200)
+        fit = sur.fit(X, tgt, steps=16000, lr=3e-3, cosine=True)
+        ref = {k: surrogate.mc_run(ctx, bins, ncand, desc, flags[k], 4096, 5000 + i)
+               for i, k in enumerate(("e1", "spread4", "e3"))}
+        ref1b = surrogate.mc_run(ctx, bins, ncand, desc, flags["e1"], 4096, 7777)
+        m200 = surrogate.mc_run(ctx, bins, ncand, desc, flags["e1"], 200, 3200)
         t0 = time.perf_counter()
-        p1 = surrogate.predict_var(sur, bins, ncand, T3D, j1.rho, -2.0, bf16=True)
-        t_pred = time.perf_counter() - t0
-        p3 = surrogate.predict_var(sur, bins, ncand, T3D, j3.rho, -2.0, bf16=True)
+        p = {k: surrogate.predict_var_flag(sur, ff, flags[k], bf16=True) for k in ref}
+        t_pred = (time.perf_counter() - t0) / len(ref)
     finally:
         sur.close()
 
-    def err(p, ref):
-        ok = np.isfinite(ref) & (ref > 0)
-        e = np.abs(p[ok] - ref[ok]) / ref[ok]
+    def err(pv, rv):
+        ok = np.isfinite(rv) & (rv > 0) & np.isfinite(pv)
+        e = np.abs(pv[ok] - rv[ok]) / rv[ok]
         return {"median": float(np.median(e)), "p90": float(np.percentile(e, 90))}
-    return {"labels": "4 flag patterns (e = 0, 1, 2, 4 edge channels + centre) x 256 realizations",
-            "label_seconds": sum(r.seconds for r in train), "train_steps": fit["steps"],
-            "train_seconds": fit["seconds"], "predict_ms_bf16": t_pred * 1e3,
-            "rel_err_vs_mc1024_training_pattern": err(p1, j1.var),
-            "rel_err_vs_mc1024_unseen_pattern": err(p3, j3.var),
-            "rel_err_mc200_vs_mc1024": err(m200.var, j1.var), "mc200_seconds": m200.seconds}
+    return {"labels": f"{len(names)} flag patterns ({', '.join(names)}) x 1024 realizations",
+            "label_seconds": sum(r.seconds for r in train), "flag_features_seconds": t_feat,
+            "train_steps": fit["steps"], "train_seconds": fit["seconds"],
+            "predict_ms_bf16_incl_flag_features": t_pred * 1e3,
+            "rel_err_vs_mc4096_config3_pattern": err(p["e1"], ref["e1"].var),
+            "rel_err_vs_mc4096_unseen_spread4": err(p["spread4"], ref["spread4"].var),
+            "rel_err_vs_mc4096_unseen_e3": err(p["e3"], ref["e3"].var),
+            "rel_err_mc200_vs_mc4096": err(m200.var, ref["e1"].var), "mc200_seconds": m200.seconds,
+            "reference_noise_floor_mc4096_vs_mc4096": err(ref1b.var, ref["e1"].var)}
 
 
 def full_mabs(bs, ctx, w, Vd, torch):
@@ -646,7 +655,8 @@ def main():
     if not args.no_surrogate:
         log("[bench] variance surrogate: labels, training, evaluation against Monte Carlo")
         sur = surrogate_block(bs, ctx, bins, ncand, w, torch)
-        log(f"[bench] surrogate: {sur['rel_err_vs_mc1024_training_pattern']}, unseen {sur['rel_err_vs_mc1024_unseen_pattern']}")
+        log(f"[bench] surrogate: config-3 pattern {sur['rel_err_vs_mc4096_config3_pattern']}, unseen "
+            f"{sur['rel_err_vs_mc4096_unseen_spread4']} / {sur['rel_err_vs_mc4096_unseen_e3']}")
     cpu = None
     if not args.no_cpu_baseline:
         Vh = Vd.cpu().numpy()

@@ -404,6 +404,29 @@ int bs_mlp_predict(bs_mlp* mlp, const float* X, int32_t n, int32_t bf16, float* 
 void bs_mlp_destroy(bs_mlp* mlp);
 int bs_var_features(const bs_bins* bins, const int64_t* T3D_host, double pk_index, double rho, float* X_host,
                     double* base_host);
+/* Flag-aware surrogate inputs (the flag summary per triangle instead of the scalar rho).
+ * Flags multiply the cube by w(nu) along frequency, which convolves every line of the delay
+ * transform with the window's spectrum (Sec. 2.2 delay transform; Sec. 4 flagging): the Gaussian
+ * power seen by the estimator is P_w(k_perp, eta) = sum_q |w~(q)|^2 / nc^2 P(k_perp, eta - q), with
+ * P(k) = |k|^pk_index (P(0) = 0) on the bins' physical grid.  Power leaks from low |k| into shells of
+ * high k_par, which for steep spectra raises the variance of some triangles by orders of magnitude.
+ * bs_var_flag_proxy: G_host [n_cand] (host float64) = mean over the closed triangles of each
+ *   candidate of P_w(k1) P_w(k2) P_w(k3) (the Gaussian variance of B up to N_vox / T3D and the
+ *   N_eff normalisation), NaN where the triangle has no closed triangle.  chan_w_host: host float32
+ *   [nc] weights (NULL = all ones).  Computed on the device: a cube whose delay transform is P_w
+ *   (its channel form a(nu) xi(nu), a the window's autocorrelation, xi the inverse DFT of P along
+ *   eta) goes through bs_estimate_3d in BS_FP64 with unit weights.  Needs 3D shell bins made with a
+ *   context.  Synchronises the context's stream; about nc n (n/2+1) 16 bytes of context workspace.
+ *   Errors: BS_EINVAL (not shell bins, a weight < 0 or not finite, all channels flagged), BS_ENOMEM,
+ *   BS_EHIP and those of bs_estimate_3d.
+ * bs_var_features_flag (host only): X_host [n_cand][4] = (log k1, log k2, log k3, log(G / G1) -
+ *   2 log rho3), G from the flags and G1 from all ones (bs_var_flag_proxy), rho3 = (1/nc) sum w^3;
+ *   base_host [n_cand] (nullable) = log(N_vox / T3D) + log G - 2 log rho3, the Gaussian log variance
+ *   with flags up to a constant (-inf where T3D = 0 or G is not positive; X's last column NaN where
+ *   G or G1 is not positive).  BS_EINVAL for NULL arrays or rho3 <= 0. */
+int bs_var_flag_proxy(bs_ctx* ctx, const bs_bins* bins, double pk_index, const float* chan_w_host, double* G_host);
+int bs_var_features_flag(const bs_bins* bins, const int64_t* T3D_host, const double* G_host, const double* G1_host,
+                         double rho3, float* X_host, double* base_host);
 
 /* ---- diagnostics ----
  * Time, in milliseconds, of the kernels of the last estimate call on this context, measured with HIP

@@ -25,7 +25,7 @@ EXPORTED = [
     "bs_mc_stats", "bs_mc_last", "bs_mc_reset", "bs_mc_destroy", "bs_mlp_create", "bs_mlp_read_state", "bs_mlp_write_state",
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
     "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
-    "bs_batch_tile", "bs_tune_set", "bs_tune_get",
+    "bs_batch_tile", "bs_tune_set", "bs_tune_get", "bs_var_flag_proxy", "bs_var_features_flag",
 ]
 BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.bs_mlp_destroy.argtypes = [vp]
     L.bs_mlp_destroy.restype = None
     L.bs_var_features.argtypes = [vp, vp, dbl, dbl, vp, vp]
+    L.bs_var_flag_proxy.argtypes = [vp, vp, dbl, vp, vp]
+    L.bs_var_features_flag.argtypes = [vp, vp, vp, vp, dbl, vp, vp]
     L.bs_batch_create.argtypes = [vp, ctypes.POINTER(bs_batch_cube), i32, i32, ctypes.POINTER(bs_field_desc), dbl,
                                   ctypes.POINTER(vp)]
     L.bs_batch_run.argtypes = [vp]
@@ -449,6 +451,30 @@ def bs_var_features(bins: int, n_cand: int, T3D=None, pk_index: float = -2.0, rh
                                None if base is None else base.ctypes.data)
     if rc != BS_OK:
         raise BsError(rc, "bs_var_features failed")
+    return X, base
+
+
+def bs_var_flag_proxy(ctx: int, bins: int, n_cand: int, pk_index: float = -2.0, chan_w=None):
+    """G float64 [n_cand]: mean over closed triangles of P_w P_w P_w (chan_w: host array or None)."""
+    import numpy as np
+    G = np.zeros(n_cand, dtype=np.float64)
+    w = None if chan_w is None else np.ascontiguousarray(chan_w, dtype=np.float32)
+    _check(ctx, lib().bs_var_flag_proxy(ctx, bins, pk_index, None if w is None else w.ctypes.data, G.ctypes.data))
+    return G
+
+
+def bs_var_features_flag(bins: int, n_cand: int, T3D, G, G1, rho3: float):
+    """(X float32 [n_cand][4], baseline float64 [n_cand]) with the per-triangle flag summary."""
+    import numpy as np
+    X = np.zeros((n_cand, 4), dtype=np.float32)
+    base = np.zeros(n_cand, dtype=np.float64)
+    T = np.ascontiguousarray(T3D, dtype=np.int64)
+    Gc = np.ascontiguousarray(G, dtype=np.float64)
+    G1c = np.ascontiguousarray(G1, dtype=np.float64)
+    rc = lib().bs_var_features_flag(bins, T.ctypes.data, Gc.ctypes.data, G1c.ctypes.data, rho3, X.ctypes.data,
+                                    base.ctypes.data)
+    if rc != BS_OK:
+        raise BsError(rc, "bs_var_features_flag failed")
     return X, base
 
 

@@ -344,3 +344,68 @@ extern "C" int bs_var_features(const bs_bins* b, const int64_t* T3D_host, double
   }
   return BS_OK;
 }
+
+// ---- Gaussian flag proxy and flag-aware features (Sec. 4 error bars; Sec. 2.2 shells) ----
+extern "C" int bs_var_flag_proxy(bs_ctx* c, const bs_bins* b, double pk_index, const float* chan_w_host,
+                                 double* G_host) {
+  if (!c || !b || !G_host) return BS_EINVAL;
+  const auto& P = b->P;
+  if (P.kind != BS_SHELL_K || !b->d_lut) return ctx_fail(c, BS_EINVAL, "bs_var_flag_proxy needs device 3D shell bins");
+  if (!std::isfinite(pk_index)) return ctx_fail(c, BS_EINVAL, "bad power-law index");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  const int n = P.n, nc = P.nc, nh = n / 2 + 1;
+  // window autocorrelation a(nu) = (1/nc) sum_mu w(mu) w(mu + nu mod nc)
+  std::vector<double> w(nc, 1.0), a(nc, 0.0);
+  if (chan_w_host)
+    for (int i = 0; i < nc; ++i) {
+      if (!std::isfinite(chan_w_host[i]) || chan_w_host[i] < 0.f) return ctx_fail(c, BS_EINVAL, "channel weights must be finite and >= 0");
+      w[i] = chan_w_host[i];
+    }
+  for (int nu = 0; nu < nc; ++nu) {
+    double acc = 0.0;
+    for (int mu = 0; mu < nc; ++mu) acc += w[mu] * w[(mu + nu) % nc];
+    a[nu] = acc / nc;
+  }
+  if (!(a[0] > 0.0)) return ctx_fail(c, BS_EINVAL, "every channel is flagged");
+  const int ncand = (int)(P.tri.size() / 3);
+  double* d_a = (double*)ctx_ws(c, "varp_a", (size_t)nc * 8);
+  double* d_xi = (double*)ctx_ws(c, "varp_xi", (size_t)(P.smax + 1) * nc * 8);
+  void* d_V = ctx_ws(c, "varp_V", (size_t)nc * n * nh * 16);
+  double* d_B = (double*)ctx_ws(c, "varp_B", (size_t)std::max(ncand, 1) * 8);
+  int64_t* d_N = (int64_t*)ctx_ws(c, "varp_N", (size_t)std::max(ncand, 1) * 8);
+  if (!d_a || !d_xi || !d_V || !d_B || !d_N) return ctx_fail(c, BS_ENOMEM, "flag proxy workspace");
+  HIPCHK(c, hipMemcpyAsync(d_a, a.data(), (size_t)nc * 8, hipMemcpyHostToDevice, c->stream));
+  launch_var_xi(nc, P.smax, P.cperp * P.cperp, P.cpar * P.cpar, pk_index, d_xi, c->stream);
+  launch_var_cube(n, nh, nc, P.smax, d_a, d_xi, d_V, c->stream);
+  LAUNCHCHK(c, "flag proxy cube");
+  // the FP64 estimator with unit weights: B = N_vox S_D / T3D = mean over closed triangles of
+  // P_w1 P_w2 P_w3 / N_vox
+  const int rc = bs_estimate_3d(c, b, d_V, nullptr, BS_FP64, 1.0, d_B, d_N, nullptr);
+  if (rc) return rc;
+  std::vector<double> hb(ncand);
+  HIPCHK(c, hipMemcpyAsync(hb.data(), d_B, (size_t)ncand * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double nvox = (double)nc * n * n;
+  for (int t = 0; t < ncand; ++t) G_host[t] = hb[t] * nvox;   // NaN where N_tri = 0 stays NaN
+  return BS_OK;
+}
+
+extern "C" int bs_var_features_flag(const bs_bins* b, const int64_t* T3D_host, const double* G_host,
+                                    const double* G1_host, double rho3, float* X_host, double* base_host) {
+  if (!b || !X_host || !G_host || !G1_host || !(rho3 > 0.0)) return BS_EINVAL;
+  const auto& P = b->P;
+  const int nt = (int)(P.tri.size() / 3);
+  const double nvox = (double)P.nc * P.n * P.n;
+  std::vector<double> lc(P.nbins);
+  for (int j = 0; j < P.nbins; ++j) lc[j] = 0.5 * (std::log(P.edges[j]) + std::log(P.edges[j + 1]));
+  for (int t = 0; t < nt; ++t) {
+    for (int i = 0; i < 3; ++i) X_host[4 * t + i] = (float)lc[P.tri[3 * t + i]];
+    const bool ok = G_host[t] > 0.0 && G1_host[t] > 0.0;
+    X_host[4 * t + 3] = ok ? (float)(std::log(G_host[t] / G1_host[t]) - 2.0 * std::log(rho3)) : NAN;
+    if (base_host) {
+      const double T = T3D_host ? (double)T3D_host[t] : 0.0;
+      base_host[t] = (T > 0 && ok) ? std::log(nvox / T) + std::log(G_host[t]) - 2.0 * std::log(rho3) : -INFINITY;
+    }
+  }
+  return BS_OK;
+}

@@ -49,3 +49,7 @@ void launch_mlp_init(float* p, unsigned long long seed, hipStream_t s);
 void launch_to_bf16(const float* x, void* y, int n, hipStream_t s);
 void launch_bf16_forward(const float* Xn, int n, const float* p, const float* norm, const void* W2b, const void* W3b,
                          const void* w4b, void* H1, void* H2, float* y, hipStream_t s);
+// Gaussian flag proxy: xi[s][nu] for s = 0..nsmax (device float64 [nsmax+1][nc]) and the cube
+// V[nu][u][v] = a(nu) xi[q_u^2 + q_v^2][nu] on support cells (complex128 [nc][n][n/2+1]).
+void launch_var_xi(int nc, int nsmax, double cperp2, double cpar2, double pk_index, double* xi, hipStream_t s);
+void launch_var_cube(int n, int nh, int nc, int smax, const double* a, const double* xi, void* V, hipStream_t s);

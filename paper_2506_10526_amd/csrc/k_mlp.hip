@@ -312,6 +312,56 @@ __global__ __launch_bounds__(256) void k_bf16_out(const __bf16* __restrict__ H, 
   y[r] = norm[8] + norm[9] * (s + p[MLP_OFF_B4]);
 }
 
+
+// ---------------------------------------------------------------------------
+// Gaussian flag proxy of the variance surrogate: the channel-domain cube whose delay transform is
+// the window-convolved power P_w(k_perp, eta) = sum_q |w~(q)|^2 / nc^2 P(k_perp, eta - q).  By the
+// convolution theorem its inverse DFT along eta is a(nu) xi_s(nu), with xi_s = IDFT_eta P (real:
+// P is even in eta) and a(nu) = (1/nc) sum_mu w(mu) w(mu + nu) the window's autocorrelation.
+// xi depends on the cell only through s = q_u^2 + q_v^2, so it is tabulated once per s.
+// ---------------------------------------------------------------------------
+// xi[s][nu] = (1/nc) sum_i P(s, i) cos(2 pi i nu / nc), P(s, i) = (cperp2 s + cpar2 eta_i^2)^(pk/2),
+// eta_i the signed index of i; one block per s, threads over nu, P(s, .) and cos(2 pi m / nc) in LDS.
+__global__ __launch_bounds__(256) void k_var_xi(int nc, double cperp2, double cpar2, double half_pk, double* xi) {
+  extern __shared__ double sh[];   // [nc] P then [nc] cos table
+  double* Ps = sh;
+  double* ct = sh + nc;
+  const int sidx = blockIdx.x;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const int e = i < (nc + 1) / 2 ? i : i - nc;
+    const double k2 = cperp2 * sidx + cpar2 * (double)e * e;
+    Ps[i] = k2 > 0.0 ? pow(k2, half_pk) : 0.0;
+    ct[i] = cos(2.0 * M_PI * (double)i / nc);
+  }
+  __syncthreads();
+  for (int nu = threadIdx.x; nu < nc; nu += blockDim.x) {
+    double acc = 0.0;
+    int m = 0;   // i * nu mod nc
+    for (int i = 0; i < nc; ++i) {
+      acc = fma(Ps[i], ct[m], acc);
+      m += nu;
+      if (m >= nc) m -= nc;
+    }
+    xi[(size_t)sidx * nc + nu] = acc / nc;
+  }
+}
+
+// V[nu][u][v] = a(nu) xi[s][nu] (complex128, imaginary part 0) on support cells 1 <= s <= smax.
+__global__ __launch_bounds__(256) void k_var_cube(int n, int nh, int nc, int smax, const double* a, const double* xi,
+                                                  double2* V) {
+  const size_t total = (size_t)nc * n * nh;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int v = (int)(e % nh);
+    const size_t r = e / nh;
+    const int u = (int)(r % n);
+    const int nu = (int)(r / n);
+    const int qu = u < (n + 1) / 2 ? u : u - n;
+    const int s = qu * qu + v * v;
+    double x = 0.0;
+    if (s >= 1 && s <= smax) x = a[nu] * xi[(size_t)s * nc + nu];
+    V[e] = make_double2(x, 0.0);
+  }
+}
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -376,4 +426,15 @@ void launch_bf16_forward(const float* Xn, int n, const float* p, const float* no
                      (__bf16*)H1);
   hipLaunchKernelGGL(k_bf16_out, dim3((n + 255) / 256), dim3(256), 0, s, (const __bf16*)H1, n, (const __bf16*)w4b, p,
                      norm, y);
+}
+
+void launch_var_xi(int nc, int nsmax, double cperp2, double cpar2, double pk_index, double* xi, hipStream_t s) {
+  const size_t lds = 2 * (size_t)nc * sizeof(double);
+  hipLaunchKernelGGL(k_var_xi, dim3(nsmax + 1), dim3(256), lds, s, nc, cperp2, cpar2, 0.5 * pk_index, xi);
+}
+void launch_var_cube(int n, int nh, int nc, int smax, const double* a, const double* xi, void* V, hipStream_t s) {
+  const size_t total = (size_t)nc * n * nh;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_var_cube, dim3((unsigned)blocks), dim3(256), 0, s, n, nh, nc, smax, a, xi, (double2*)V);
 }

@@ -167,8 +167,11 @@ def rel_err(pred, ref):
 
 
 def test_surrogate_gain_on_flagged_mwa_cube(ctx):
-    """Train on 4 flag patterns x 256 realizations of the 256 x 256 x 768 cube; checked against 1024
-    fresh realizations of a training pattern (e = 1) and of an unseen one (e = 3)."""
+    """Train on 7 flag patterns x 1024 realizations of the 256 x 256 x 768 cube with the per-triangle
+    flag summary; judged against 4096 fresh realizations of config 3's pattern (e1, held-out
+    realizations) and of two patterns kept out of training (spread4 near a training pattern, e3 between
+    two of them).  References of 4096 realizations have a noise floor of about 2.3 % (median) and
+    5.5 % (p90) of their own."""
     w = synth.config2()
     edges = w.shell_edges(20)
     h, ncand = bs.bs_make_bins(ctx, bs.BS_SHELL_K, w.n, w.nc, edges, du_lambda=w.du, r_mpc=w.r_mpc,
@@ -183,40 +186,46 @@ def test_surrogate_gain_on_flagged_mwa_cube(ctx):
         N = torch.empty(ncand, dtype=torch.int64, device="cuda")
         bs.bs_estimate_3d(ctx, h, V, bs.BS_SPLIT_BF16, B, N)
         T3D = N.cpu().numpy()
-        flags = {e: synth.mwa_flags(w.nc, surrogate.edge_flags(e)) for e in (0, 1, 2, 3, 4)}
-        train = [surrogate.mc_run(ctx, h, ncand, desc, flags[e], 256, 100 + e) for e in (0, 1, 2, 4)]
+        pats = dict(surrogate.TRAIN_PATTERNS, **surrogate.UNSEEN_PATTERNS)
+        flags = {k: (synth.mwa_flags(w.nc, v) if v else np.ones(w.nc)) for k, v in pats.items()}
+        ff = surrogate.FlagFeatures(ctx, h, ncand, T3D, -2.0)
+        names = list(surrogate.TRAIN_PATTERNS)
+        train = [surrogate.mc_run(ctx, h, ncand, desc, flags[k], 1024, 100 + i) for i, k in enumerate(names)]
         t_labels = sum(r.seconds for r in train)
-        X, tgt = surrogate.training_set(h, ncand, T3D, train, -2.0)
+        X, tgt = surrogate.training_set_flag(ff, train, [flags[k] for k in names])
         sur = surrogate.Surrogate(ctx, seed=1)
-        fit = sur.fit(X, tgt, steps=4000, lr=3e-3, cosine=True)
-        ref1 = surrogate.mc_run(ctx, h, ncand, desc, flags[1], 1024, 1000)
-        ref3 = surrogate.mc_run(ctx, h, ncand, desc, flags[3], 1024, 2000)
-        small = {R: surrogate.mc_run(ctx, h, ncand, desc, flags[1], R, 3000 + R) for R in (50, 200)}
+        fit = sur.fit(X, tgt, steps=16000, lr=3e-3, cosine=True)
+        ref = {k: surrogate.mc_run(ctx, h, ncand, desc, flags[k], 4096, 5000 + i)
+               for i, k in enumerate(("e1", "spread4", "e3"))}
+        small = {R: surrogate.mc_run(ctx, h, ncand, desc, flags["e1"], R, 3000 + R) for R in (50, 200)}
         t0 = time.perf_counter()
-        p1 = surrogate.predict_var(sur, h, ncand, T3D, ref1.rho, -2.0)
+        p1 = surrogate.predict_var_flag(sur, ff, flags["e1"])
         t_pred = time.perf_counter() - t0
-        p3 = surrogate.predict_var(sur, h, ncand, T3D, ref3.rho, -2.0)
-        p1b = surrogate.predict_var(sur, h, ncand, T3D, ref1.rho, -2.0, bf16=True)
-        # the Gaussian-shaped baseline alone, its constant fitted on the training labels
-        _, base = bs.bs_var_features(h, ncand, T3D, -2.0, ref1.rho)
+        pu = surrogate.predict_var_flag(sur, ff, flags["spread4"])
+        p3 = surrogate.predict_var_flag(sur, ff, flags["e3"])
+        p1b = surrogate.predict_var_flag(sur, ff, flags["e1"], bf16=True)
+        # the Gaussian log variance with flags alone, its constant fitted on the training labels
+        _, base = ff(flags["e1"])
         g1 = np.where(T3D > 0, np.exp(base + np.mean(tgt)), np.nan)
     finally:
         if sur:
             sur.close()
         bs.bs_free_bins(h)
-    e_s1, e_s3, e_b = rel_err(p1, ref1.var), rel_err(p3, ref3.var), rel_err(p1b, ref1.var)
-    e_g = rel_err(g1, ref1.var)
-    e50, e200 = rel_err(small[50].var, ref1.var), rel_err(small[200].var, ref1.var)
-    print(f"labels: 4 x 256 realizations in {t_labels:.2f} s; training {fit['steps']} steps in {fit['seconds']:.2f} s "
-          f"(loss {fit['final_loss']:.3e}); prediction of {ncand} triangles in {t_pred * 1e3:.2f} ms")
-    print(f"median / p90 relative error vs 1024-realization Monte Carlo:")
-    print(f"  surrogate, training pattern e=1 : {e_s1[0]:.3f} / {e_s1[1]:.3f}  (bf16 {e_b[0]:.3f} / {e_b[1]:.3f})")
-    print(f"  surrogate, unseen pattern e=3   : {e_s3[0]:.3f} / {e_s3[1]:.3f}")
-    print(f"  Gaussian-shaped baseline alone  : {e_g[0]:.3f} / {e_g[1]:.3f}")
-    print(f"  Monte Carlo, 50 realizations    : {e50[0]:.3f} / {e50[1]:.3f} ({small[50].seconds:.2f} s)")
-    print(f"  Monte Carlo, 200 realizations   : {e200[0]:.3f} / {e200[1]:.3f} ({small[200].seconds:.2f} s)")
-    assert e_s1[0] <= 0.10                  # within 10 % of Monte Carlo (median) on held-out realizations
-    assert e_s3[0] <= 0.15                  # and close on a flag pattern it never saw
-    assert e_s1[0] < e50[0] and e_s1[1] < e50[1]   # better than 50 fresh realizations, at no new realization
-    assert e_s1[0] < 0.5 * e_g[0]           # the network adds to the Gaussian-shaped scaling
-    assert abs(e_b[0] - e_s1[0]) <= 0.02    # BF16 inference keeps the accuracy
+    e_s1, e_su, e_s3 = rel_err(p1, ref["e1"].var), rel_err(pu, ref["spread4"].var), rel_err(p3, ref["e3"].var)
+    e_b, e_g = rel_err(p1b, ref["e1"].var), rel_err(g1, ref["e1"].var)
+    e50, e200 = rel_err(small[50].var, ref["e1"].var), rel_err(small[200].var, ref["e1"].var)
+    print(f"labels: {len(names)} patterns x 1024 realizations in {t_labels:.2f} s; training {fit['steps']} steps in "
+          f"{fit['seconds']:.2f} s (loss {fit['final_loss']:.3e}); prediction of {ncand} triangles in {t_pred * 1e3:.2f} ms")
+    print(f"median / p90 relative error vs 4096-realization Monte Carlo:")
+    print(f"  surrogate, config-3 pattern e1 : {e_s1[0]:.3f} / {e_s1[1]:.3f}  (bf16 {e_b[0]:.3f} / {e_b[1]:.3f})")
+    print(f"  surrogate, unseen spread4      : {e_su[0]:.3f} / {e_su[1]:.3f}")
+    print(f"  surrogate, unseen e3           : {e_s3[0]:.3f} / {e_s3[1]:.3f}")
+    print(f"  Gaussian log variance alone    : {e_g[0]:.3f} / {e_g[1]:.3f}")
+    print(f"  Monte Carlo, 50 realizations   : {e50[0]:.3f} / {e50[1]:.3f} ({small[50].seconds:.2f} s)")
+    print(f"  Monte Carlo, 200 realizations  : {e200[0]:.3f} / {e200[1]:.3f} ({small[200].seconds:.2f} s)")
+    assert e_s1[0] <= 0.10 and e_s1[1] <= 0.10    # within 10 % of Monte Carlo, median and p90
+    assert e_b[0] <= 0.10 and e_b[1] <= 0.10      # also with BF16 inference
+    assert e_su[0] <= 0.10 and e_su[1] <= 0.12    # a pattern it never saw, near the training set
+    assert e_s3[0] <= 0.12                        # between two training patterns: median only (p90 reported)
+    assert e_s1[0] < e200[0] and e_s1[1] < e200[1]   # better than 200 fresh realizations, at no new realization
+    assert e_s1[0] < 0.5 * e_g[0]                 # the network adds to the Gaussian log variance
