@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void k3_delay(Delay3Args a) {
   Cx<T>* out = (Cx<T>*)a.out;
   const int ne = 2 * g.H + 1;
   for (int e = threadIdx.x; e < ne * nl; e += blockDim.x) {
-    int ec = e / nl, l = e - ec * nl;
+    int ec, l;
+    fdivmod(e, nl, rnl, ec, l);
     int eta = ec - g.H;
     int idx = eta < 0 ? eta + nc : eta;
     out[((size_t)ec * g.nub + ub) * g.nvb + v0 + l] = r[(size_t)l * ld + idx];
@@ -177,8 +178,10 @@ __global__ __launch_bounds__(256) void k3_vpass(Pass3Args a) {
   // T_j[x_v][eta][qu]: consecutive threads write consecutive qu rows of one x_v
   const int hp1 = a.hj[w.j] + 1;
   Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
+  const float rnl = 1.0f / (float)nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int i = e / nl, l = e - i * nl;
+    int i, l;
+    fdivmod(e, nl, rnl, i, l);
     out[((size_t)i * hp1 + w.eta) * g.nub + w.start + l] = r[(size_t)l * ld + i];
   }
 }
@@ -229,8 +232,10 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
       const int g0 = (e0 & 15) >> 2, gpl = min(a.NL >> 2, (hp1 - e0 + 3) >> 2);
       uint4* out = (uint4*)a.gs + a.off_gs[w.j];
       const float sc = (float)a.scale;
+      const float rgr = 1.0f / (float)(16 * gpl);
       for (int e = threadIdx.x; e < nxub * 16 * gpl; e += blockDim.x) {
-        const int xub = e / (16 * gpl), lr = e - xub * 16 * gpl;
+        int xub, lr;
+        fdivmod(e, 16 * gpl, rgr, xub, lr);
         const int lane = g0 * 16 + lr;
         const int xu = xub * 16 + (lane & 15), q0 = 4 * (lane >> 4) - (e0 & 15);
         uint32_t hw[4], lw[4];
@@ -254,8 +259,10 @@ __global__ __launch_bounds__(256) void k3_upass(Pass3Args a) {
     }
   }
   Cx<T>* out = (Cx<T>*)a.out + a.off_out[w.j];
+  const float rnl = 1.0f / (float)nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int i = e / nl, l = e - i * nl;
+    int i, l;
+    fdivmod(e, nl, rnl, i, l);
     out[((size_t)i * n + xv) * hp1 + e0 + l] = r[(size_t)l * ld + i];
   }
 }
