@@ -346,6 +346,90 @@ def bs_monopole(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edges:
     return mean.reshape(nk, 5, 5), counts.reshape(nk, 5, 5)
 
 
+def triangle_orientation(kperp: np.ndarray, kpar1: np.ndarray, kpar2: np.ndarray):
+    """Line-of-sight direction p = (p_x, p_y, p_z) in the frame of a cylindrical triangle (Eq. orient).
+
+    The sides are sorted as in triangle_shape (k1 >= k2 >= k3, vectors k_1, k_2 of the two largest
+    sides, kpar3 = -(kpar1 + kpar2)).  The frame puts k_1 along z and k_2 in the x-z plane with a
+    positive x component, k_2 / k2 = (sqrt(1 - mu^2), 0, -mu); the line of sight then has
+    p_z = mu_1 = kpar(k_1) / k1 and mu_2 = kpar(k_2) / k2 = -mu p_z + sqrt(1 - mu^2) p_x (Eq. orient),
+    so p_x = (mu_2 + mu p_z) / sqrt(1 - mu^2) and p_y = +sqrt(1 - p_x^2 - p_z^2) (the mirror image,
+    p_y -> -p_y, describes the same triangle; the sign is taken positive).  mu is the clamped shape
+    parameter of triangle_shape; p_x is clamped to |p_x| <= sqrt(1 - p_z^2) (ring-averaged kperp need
+    not close exactly).  Where mu = 1 (the sides are collinear) the azimuth is undefined: p_x and
+    p_y are returned as NaN.  Returns (p_x, p_y, p_z)."""
+    kpar3 = -(kpar1 + kpar2)
+    kp = np.stack(np.broadcast_arrays(kpar1, kpar2, kpar3), axis=-1).astype(np.float64)
+    s = np.stack([kperp[..., 0] * kperp[..., 0] + kp[..., 0] * kp[..., 0],
+                  kperp[..., 1] * kperp[..., 1] + kp[..., 1] * kp[..., 1],
+                  kperp[..., 2] * kperp[..., 2] + kp[..., 2] * kp[..., 2]], axis=-1)
+    order = np.argsort(-s, axis=-1, kind="stable")
+    s_sorted = np.take_along_axis(s, order, axis=-1)
+    kp_sorted = np.take_along_axis(kp, order, axis=-1)
+    k1, k2 = np.sqrt(s_sorted[..., 0]), np.sqrt(s_sorted[..., 1])
+    mu = np.clip(((s_sorted[..., 0] + s_sorted[..., 1]) - s_sorted[..., 2]) / (2.0 * (k1 * k2)), 0.5, 1.0)
+    pz = kp_sorted[..., 0] / k1
+    mu2 = kp_sorted[..., 1] / k2
+    sq = np.sqrt(np.maximum(1.0 - mu * mu, 0.0))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        px = np.where(sq > 0, (mu2 + mu * pz) / np.where(sq > 0, sq, 1.0), np.nan)
+    st = np.sqrt(np.maximum(1.0 - pz * pz, 0.0))
+    px = np.clip(px, -st, st)
+    py = np.sqrt(np.maximum(1.0 - pz * pz - px * px, 0.0))
+    py = np.where(np.isnan(px), np.nan, py)
+    return px, py, pz
+
+
+def lm_pairs(lmax: int):
+    """(l, m) in the order of the moments: l = 0 .. lmax, m = 0 .. l."""
+    return [(l, m) for l in range(lmax + 1) for m in range(l + 1)]
+
+
+def bs_multipoles(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edges: np.ndarray, lmax: int):
+    """Multipole moments B_l^m(k1, mu, t) of cylindrical 3D BS estimates (Eqs. orient, bs_lm).
+
+    Eq. bs_lm integrates [Y_l^m(p)]* B over the orientations p of the line of sight; a (k1, mu, t)
+    bin samples orientations through its cells, so the integral over the sphere is taken as 4 pi
+    times the mean over the bin's cells:
+        B_l^m = sqrt(4 pi (2l + 1)) mean over cells of Re[Y_l^m(p)]* Re B,
+    where the real part of Y* is the mean over the two mirror orientations (p_y and -p_y) that a
+    cylindrical cell stands for (Y_l^m from scipy.special, Condon-Shortley phase).  m < 0 follows
+    from B_l^-m = (-1)^m B_l^m.  Cells whose sides are collinear (mu = 1, azimuth undefined) add the
+    azimuthal mean, 0, to m > 0.  l = 0 is the monopole (bs_monopole).  Bins and cells as in
+    bs_monopole.  Returns (moments [n_lm][nk][5][5] in lm_pairs order, NaN where the bin is empty,
+    and the cell count [nk][5][5])."""
+    from scipy.special import sph_harm_y
+    Bcyl = np.asarray(Bcyl)
+    nt, nc = Bcyl.shape[0], Bcyl.shape[1]
+    k1_edges = np.asarray(k1_edges, dtype=np.float64)
+    nk = len(k1_edges) - 1
+    pairs = lm_pairs(lmax)
+    a = np.arange(nc)
+    kp = kpar_unit * np.where(2 * a < nc, a, a - nc).astype(np.float64)
+    sums = np.zeros((len(pairs), nk * 25))
+    counts = np.zeros(nk * 25, dtype=np.int64)
+    for t in range(nt):
+        kpt = np.broadcast_to(np.asarray(kperp[t], dtype=np.float64), (nc, nc, 3))
+        k1, mu, tt = triangle_shape(kpt, kp[:, None], kp[None, :])
+        px, py, pz = triangle_orientation(kpt, kp[:, None], kp[None, :])
+        j = np.searchsorted(k1_edges, k1, side="right") - 1
+        ok = (j >= 0) & (j < nk)
+        idx = (j * 25 + shape_bin(mu) * 5 + shape_bin(tt))[ok]
+        counts += np.bincount(idx, minlength=nk * 25)
+        theta = np.arccos(np.clip(pz[ok], -1.0, 1.0))
+        collinear = np.isnan(px[ok])
+        phi = np.where(collinear, 0.0, np.arctan2(np.nan_to_num(py[ok]), np.nan_to_num(px[ok])))
+        re_b = np.real(Bcyl[t])[ok]
+        for i, (l, m) in enumerate(pairs):
+            y = np.real(np.conj(sph_harm_y(l, m, theta, phi)))
+            if m > 0:
+                y = np.where(collinear, 0.0, y)
+            sums[i] += np.bincount(idx, weights=np.sqrt(4 * np.pi * (2 * l + 1)) * y * re_b, minlength=nk * 25)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mom = np.where(counts[None, :] > 0, sums / np.maximum(counts, 1)[None, :], np.nan)
+    return mom.reshape(len(pairs), nk, 5, 5), counts.reshape(nk, 5, 5)
+
+
 # ---------------------------------------------------------------------------
 # 3D bispectrum
 # ---------------------------------------------------------------------------
