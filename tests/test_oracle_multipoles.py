@@ -123,7 +123,10 @@ def test_moments_match_explicit_vectors(case):
         _, mu, _ = oe.triangle_shape(np.broadcast_to(kperp[0], (nc, nc, 3)), kp[:, None], kp[None, :])
         assert np.sum(mu == 1.0) >= 2          # the exactly collinear cells are there
     ref = sums[:, ok] / counts[ok]
-    assert np.allclose(mom[:, ok], ref, rtol=1e-9, atol=1e-11 * np.abs(B.real).max())
+    # near-collinear cells (mu within ~1e-10 of 1) take p_x from sqrt(1 - mu^2) with mu known to
+    # ~1e-16 absolute, i.e. ~1e-7 relative error in that one cell; elsewhere agreement is ~1e-12
+    rtol = 1e-9 if case == "closing" else 1e-6
+    assert np.allclose(mom[:, ok], ref, rtol=rtol, atol=1e-11 * np.abs(B.real).max())
     assert ok.sum() >= 10
 
 
