@@ -346,6 +346,9 @@ def bs_monopole(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edges:
     return mean.reshape(nk, 5, 5), counts.reshape(nk, 5, 5)
 
 
+COLLINEAR_TOL = 1e-9   # mu above 1 - COLLINEAR_TOL: collinear sides, azimuth undefined
+
+
 def triangle_orientation(kperp: np.ndarray, kpar1: np.ndarray, kpar2: np.ndarray):
     """Line-of-sight direction p = (p_x, p_y, p_z) in the frame of a cylindrical triangle (Eq. orient).
 
@@ -356,8 +359,10 @@ def triangle_orientation(kperp: np.ndarray, kpar1: np.ndarray, kpar2: np.ndarray
     so p_x = (mu_2 + mu p_z) / sqrt(1 - mu^2) and p_y = +sqrt(1 - p_x^2 - p_z^2) (the mirror image,
     p_y -> -p_y, describes the same triangle; the sign is taken positive).  mu is the clamped shape
     parameter of triangle_shape; p_x is clamped to |p_x| <= sqrt(1 - p_z^2) (ring-averaged kperp need
-    not close exactly).  Where mu = 1 (the sides are collinear) the azimuth is undefined: p_x and
-    p_y are returned as NaN.  Returns (p_x, p_y, p_z)."""
+    not close exactly).  Where the sides are collinear the azimuth is undefined; numerically that is
+    taken as mu > 1 - COLLINEAR_TOL (mu from the closure formula, the same numbers as the shape
+    bins): there sqrt(1 - mu^2) < 4.5e-5 and the rounding of mu (~1e-16) would make p_x arbitrary,
+    so p_x and p_y are returned as NaN.  Returns (p_x, p_y, p_z)."""
     kpar3 = -(kpar1 + kpar2)
     kp = np.stack(np.broadcast_arrays(kpar1, kpar2, kpar3), axis=-1).astype(np.float64)
     s = np.stack([kperp[..., 0] * kperp[..., 0] + kp[..., 0] * kp[..., 0],
@@ -371,8 +376,9 @@ def triangle_orientation(kperp: np.ndarray, kpar1: np.ndarray, kpar2: np.ndarray
     pz = kp_sorted[..., 0] / k1
     mu2 = kp_sorted[..., 1] / k2
     sq = np.sqrt(np.maximum(1.0 - mu * mu, 0.0))
+    defined = mu <= 1.0 - COLLINEAR_TOL
     with np.errstate(invalid="ignore", divide="ignore"):
-        px = np.where(sq > 0, (mu2 + mu * pz) / np.where(sq > 0, sq, 1.0), np.nan)
+        px = np.where(defined, (mu2 + mu * pz) / np.where(defined, sq, 1.0), np.nan)
     st = np.sqrt(np.maximum(1.0 - pz * pz, 0.0))
     px = np.clip(px, -st, st)
     py = np.sqrt(np.maximum(1.0 - pz * pz - px * px, 0.0))
@@ -394,8 +400,8 @@ def bs_multipoles(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edge
         B_l^m = sqrt(4 pi (2l + 1)) mean over cells of Re[Y_l^m(p)]* Re B,
     where the real part of Y* is the mean over the two mirror orientations (p_y and -p_y) that a
     cylindrical cell stands for (Y_l^m from scipy.special, Condon-Shortley phase).  m < 0 follows
-    from B_l^-m = (-1)^m B_l^m.  Cells whose sides are collinear (mu = 1, azimuth undefined) add the
-    azimuthal mean, 0, to m > 0.  l = 0 is the monopole (bs_monopole).  Bins and cells as in
+    from B_l^-m = (-1)^m B_l^m.  Cells whose sides are collinear (mu > 1 - COLLINEAR_TOL, azimuth
+    undefined) add the azimuthal mean, 0, to m > 0.  l = 0 is the monopole (bs_monopole).  Bins and cells as in
     bs_monopole.  Returns (moments [n_lm][nk][5][5] in lm_pairs order, NaN where the bin is empty,
     and the cell count [nk][5][5])."""
     from scipy.special import sph_harm_y
