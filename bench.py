@@ -40,7 +40,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # were taken on; None once that kernel changes until the counters are taken again.
 TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_gemms.md
                  "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
-                 "mono": (1255.3 + 14.8) * 1e6,   # profiles/mono_bin_133x768x768_k1x12.md
+                 "mono": None,
                  "grid": (0.0 + 126.8 + 1673.9 + 1304.4 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
 
 
@@ -246,8 +246,10 @@ def mabs_dft_block(bs, ctx, w, torch, nt=133):
 def monopole_block(bs, ctx, w, torch, Bcyl):
     """Monopole B(k1, mu, t) of the cylindrical BS just computed: the 133 ring triples of the
     cube's rings (k_perp at the geometric centres of the ring edges), k_par unit 2 pi / (r' B_bw),
-    12 log k1 bins over 0.003-1.258 Mpc^-1 x 5 mu x 5 t.  HBM-bound: 16 B (one complex128 entry)
-    read per cell; the oracle on two triangles beside it."""
+    12 log k1 bins over 0.003-1.258 Mpc^-1 x 5 mu x 5 t.  Only the cells inside the k1 edges are
+    read: the algorithmic bytes are 16 B (one complex128 entry) per binned cell, and the rate over
+    the whole cube (what a kernel that reads every cell must move) is reported beside it.  The
+    oracle on two triangles beside it."""
     from oracle import estimator as oe
     redges = w.shell_edges(20)
     h, ncand = bs.bs_make_bins(None, bs.BS_RING_U, w.n, w.nc, redges / (2 * np.pi * w.du / w.r_mpc))
@@ -270,19 +272,46 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
         kr.append(tm[2])
     t_wall = time_steps(f, 5, 0, torch)
     ms_b = float(np.median(kb))
-    byt = nt * nc * nc * 16
+    gc = cnt.cpu().numpy()
+    cube = nt * nc * nc * 16
+    byt = int(gc.sum()) * 16
     ach = byt / (ms_b * 1e-3) / 1e9
     t0 = time.perf_counter()
     Bh = Bcyl[:2].cpu().numpy()
     ref_m, ref_c = oe.bs_monopole(Bh, kperp[:2], unit, edges)
     t_cpu = (time.perf_counter() - t0) / 2
-    gc = cnt.cpu().numpy()
+    # multipole moments l <= 4 (15 moments) of the same cells and bins
+    mom = torch.empty((15, 12, 5, 5), dtype=torch.float64, device="cuda")
+    cnt2 = torch.empty((12, 5, 5), dtype=torch.int64, device="cuda")
+    g = lambda: bs.bs_multipoles(ctx, Bcyl, kperp, unit, edges, 4, mom, cnt2)
+    g()
+    mb = []
+    for _ in range(5):
+        g()
+        mb.append(bs.bs_last_timing(ctx)[1])
+    tm_wall = time_steps(g, 5, 0, torch)
+    ms_m = float(np.median(mb))
+    ach_m = byt / (ms_m * 1e-3) / 1e9
+    t0 = time.perf_counter()
+    oe.bs_multipoles(Bh[:1], kperp[:1], unit, edges, 4)
+    t_cpu_m = time.perf_counter() - t0
+    multipoles = {
+        "value": nt / tm_wall, "unit": "triangles/s", "ms_per_call": tm_wall * 1e3, "bin_kernel_ms": ms_m,
+        "moments": "l = 0..4, m = 0..l (15)", "counts_equal_monopole": bool(np.array_equal(cnt2.cpu().numpy(), gc)),
+        "roofline": {"bound": "hbm", "kernel": "k_multi_bin", "achieved": ach_m, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_m / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": byt, "traffic": None},
+        "whole_cube_rate_GBps": cube / (ms_m * 1e-3) / 1e9,
+        "cpu_oracle": {"value": 1.0 / t_cpu_m, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                       "sample": "1 of 133 triangles, float64 NumPy with scipy Y_l^m"},
+    }
     return {
+        "multipoles": multipoles,
         "value": nt / t_wall, "unit": "triangles/s", "ms_per_call": t_wall * 1e3, "bin_kernel_ms": ms_b,
         "reduce_kernel_ms": float(np.median(kr)), "cells_binned": int(gc.sum()), "bins_filled": int((gc > 0).sum()),
         "roofline": {"bound": "hbm", "kernel": "k_mono_bin", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": byt,
                      "traffic": TRAFFIC_BYTES.get("mono")},
+        "whole_cube_bytes": cube, "whole_cube_rate_GBps": cube / (ms_b * 1e-3) / 1e9,
         "cpu_oracle": {"value": 1.0 / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "2 of 133 triangles, float64 NumPy"},
         "workload": f"{nt} triangles x [{nc}][{nc}] cells -> 12 k1 x 5 mu x 5 t bins",
@@ -634,6 +663,9 @@ def main():
         mo = mdft["monopole"]
         log(f"[bench] monopole: {mo['ms_per_call']:.3f} ms/call (binning {mo['bin_kernel_ms']:.3f} ms, "
             f"{mo['roofline']['achieved']:.0f} GB/s), {mo['cells_binned']} cells in {mo['bins_filled']} bins")
+        mp = mo["multipoles"]
+        log(f"[bench] multipoles l<=4: {mp['ms_per_call']:.3f} ms/call (binning {mp['bin_kernel_ms']:.3f} ms, "
+            f"{mp['roofline']['achieved']:.0f} GB/s)")
     grid = None
     if not args.no_grid:
         log("[bench] Eq. (vg): gridding 262,144 baselines x 768 channels")

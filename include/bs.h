@@ -241,6 +241,25 @@ int bs_mabs_dft(bs_ctx* ctx, int32_t nc, int32_t n_tri, int32_t circular, const 
 int bs_monopole(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
                 const void* Bcyl, int32_t n_k1, const double* k1_edges_host, double* mean, int64_t* count);
 
+/* ---- multipole moments B_l^m(k1, mu, t) of the cylindrical 3D bispectrum (Sec. 2.2 Eqs. orient, bs_lm) ----
+ * The cells and bins of bs_monopole; each cell's triangle, its sides sorted k1 >= k2 >= k3 (ties in the
+ * order kperp_1, kperp_2, kperp_3), also fixes the line of sight p in the triangle's frame (k_1 along z,
+ * k_2 in the x-z plane, Eq. orient): p_z = kpar(k_1) / k1, p_x = (mu_2 + mu p_z) / sqrt(1 - mu^2) with
+ * mu_2 = kpar(k_2) / k2 and mu the clamped shape parameter, |p_x| <= sqrt(1 - p_z^2), p_y = +sqrt(1 -
+ * p_z^2 - p_x^2) (the mirror image p_y -> -p_y is the same triangle).  Eq. bs_lm's integral over the
+ * orientations is taken as 4 pi times the mean over the bin's cells:
+ *   moment (l, m) = (2l + 1) sqrt((l - m)! / (l + m)!) mean over cells of P_l^m(p_z) cos(m phi) Re B,
+ * P_l^m with the Condon-Shortley phase, phi the azimuth of (p_x, p_y); m < 0 follows from
+ * B_l^-m = (-1)^m B_l^m, and (0, 0) is the monopole.  Cells whose sides are collinear (mu > 1 - 1e-9,
+ * azimuth undefined) add 0 to m > 0.  lmax in [0, 4]; moments are ordered l = 0 .. lmax, m = 0 .. l.
+ * Outputs (device): moments float64 [(lmax+1)(lmax+2)/2][n_k1][5][5] (NaN where the bin is empty),
+ * count int64 [n_k1][5][5].  Needs 25 n_k1 (lmax+1)(lmax+2)/2 <= 6400.  Synchronises the context's
+ * stream; bs_last_timing reports [0] the call, [1] the binning kernel, [2] the reduction.
+ * Errors: those of bs_monopole, and BS_EINVAL for lmax outside [0, 4] or too many bin values. */
+int bs_multipoles(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
+                  const void* Bcyl, int32_t n_k1, const double* k1_edges_host, int32_t lmax, double* moments,
+                  int64_t* count);
+
 /* ---- allocation-free monopole ----
  * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): bs_monopole with the same inputs, outputs, binning and

@@ -26,6 +26,7 @@ EXPORTED = [
     "bs_mlp_set_data", "bs_mlp_loss_grad", "bs_mlp_train", "bs_mlp_predict", "bs_mlp_destroy", "bs_var_features",
     "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
     "bs_batch_tile", "bs_tune_set", "bs_tune_get", "bs_var_flag_proxy", "bs_var_features_flag",
+    "bs_multipoles",
 ]
 BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
     L.bs_mabs_dft.argtypes = [vp, i32, i32, i32, vp, dbl, vp]
     L.bs_grid_visibilities.argtypes = [vp, i32, i32, dbl, ctypes.c_int64, vp, vp, vp, i32, i32, vp, vp]
     L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
+    L.bs_multipoles.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), i32, vp, vp]
     L.bs_monopole_noalloc.argtypes = [vp, i32, i32, vp, dbl, vp, i32, vp, vp, vp]
     L.bs_decorrelation.argtypes = [vp, vp, ctypes.c_int64, vp, dbl, dbl, i32, vp]
     L.bs_set_timing.argtypes = [vp, i32]
@@ -273,6 +275,25 @@ def bs_monopole(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) 
     kpa = (ctypes.c_double * max(len(kp), 1))(*kp)
     kea = (ctypes.c_double * len(ke))(*ke)
     _check(ctx, lib().bs_monopole(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, _ptr(mean), _ptr(count)))
+
+
+def bs_multipoles(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, lmax: int, moments, count) -> None:
+    """Multipole moments B_l^m(k1, mu, t): as bs_monopole, moments float64 [(lmax+1)(lmax+2)/2][n_k1][5][5]
+    on the device (l = 0 .. lmax, m = 0 .. l), count int64 [n_k1][5][5]."""
+    nt, nc = int(Bcyl.shape[0]), int(Bcyl.shape[1])
+    kp = [float(x) for row in kperp for x in row]
+    ke = [float(x) for x in k1_edges]
+    nk = len(ke) - 1
+    nlm = (lmax + 1) * (lmax + 2) // 2
+    if (tuple(Bcyl.shape) != (nt, nc, nc) or len(kp) != 3 * nt or tuple(moments.shape) != (nlm, nk, 5, 5)
+            or tuple(count.shape) != (nk, 5, 5) or not Bcyl.is_contiguous() or not moments.is_contiguous()
+            or not count.is_contiguous()):
+        raise ValueError("bs_multipoles: Bcyl [n_tri][nc][nc], kperp [n_tri][3], moments [n_lm][n_k1][5][5], "
+                         "count [n_k1][5][5]")
+    kpa = (ctypes.c_double * max(len(kp), 1))(*kp)
+    kea = (ctypes.c_double * len(ke))(*ke)
+    _check(ctx, lib().bs_multipoles(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, int(lmax), _ptr(moments),
+                                    _ptr(count)))
 
 
 def bs_monopole_noalloc(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) -> None:

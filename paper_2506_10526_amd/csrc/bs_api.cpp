@@ -462,9 +462,10 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
     if (!(kperp_host[i] > 0.0) || !std::isfinite(kperp_host[i]))
       return ctx_fail(c, BS_EINVAL, "bs_monopole: kperp must be positive and finite");
   const int nb = n_k1 * 25;
-  // a block per 2048 cells or so, at most 4096: partial bins then a fixed-order reduction
+  // a wave per row, blocks of four rows, at most 2048 blocks (eight waves per SIMD on 256 CUs, to hide
+  // the latency of each row's loads): partial bins then a fixed-order reduction
   const long long rows = (long long)n_tri * nc;
-  const int nblocks = (int)std::max(1LL, std::min(4096LL, (rows * nc + 2047) / 2048));
+  const int nblocks = (int)std::max(1LL, std::min(2048LL, (rows + 3) / 4));
   MonoArgs a{};
   double* dk = static_cast<double*>(ctx_ws(c, "mono_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
   a.psum = static_cast<double*>(ctx_ws(c, "mono_psum", (size_t)nblocks * nb * sizeof(double)));
@@ -492,6 +493,71 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));   // the host staging of the tables is released on return
   if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_monopole launch");
+  return BS_OK;
+}
+
+// ------------------------------------------------------------------ multipoles (Eqs. orient, bs_lm)
+extern "C" int bs_multipoles(bs_ctx* c, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
+                             const void* Bcyl, int32_t n_k1, const double* k1_edges_host, int32_t lmax,
+                             double* moments, int64_t* count) {
+  if (!c) return BS_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  if (lmax < 0 || lmax > MULTI_MAX_LMAX) return ctx_fail(c, BS_EINVAL, "bs_multipoles: lmax must be in [0, 4]");
+  const int nlm = (lmax + 1) * (lmax + 2) / 2;
+  if (nc < 1 || nc > 65536) return ctx_fail(c, BS_EINVAL, "bs_multipoles: nc must be in [1, 65536]");
+  if (n_tri < 0 || (long long)n_tri * nc > (1LL << 31) - 1)
+    return ctx_fail(c, BS_EINVAL, "bs_multipoles: n_tri * nc must be in [0, 2^31)");
+  if (n_k1 < 1 || n_k1 > MONO_MAX_K1 || n_k1 * 25 * nlm > MULTI_MAX_BINVALS)
+    return ctx_fail(c, BS_EINVAL, "bs_multipoles: n_k1 must be in [1, 64] with 25 n_k1 (lmax+1)(lmax+2)/2 <= 6400");
+  if (!k1_edges_host || !moments || !count) return ctx_fail(c, BS_EINVAL, "bs_multipoles: NULL edges or outputs");
+  for (int i = 0; i < n_k1; ++i)
+    if (!(k1_edges_host[i + 1] > k1_edges_host[i]) || !(k1_edges_host[i] >= 0.0))
+      return ctx_fail(c, BS_EINVAL, "bs_multipoles: k1 edges must be non-negative and increasing");
+  if (!(kpar_unit > 0.0) || !std::isfinite(kpar_unit)) return ctx_fail(c, BS_EINVAL, "bs_multipoles: kpar_unit must be > 0");
+  if (n_tri > 0 && (!kperp_host || !Bcyl)) return ctx_fail(c, BS_EINVAL, "bs_multipoles: NULL kperp or Bcyl");
+  for (long long i = 0; i < 3LL * n_tri; ++i)
+    if (!(kperp_host[i] > 0.0) || !std::isfinite(kperp_host[i]))
+      return ctx_fail(c, BS_EINVAL, "bs_multipoles: kperp must be positive and finite");
+  const int nb = n_k1 * 25;
+  const long long rows = (long long)n_tri * nc;
+  // a wave per row: blocks of eight rows, at most 512 blocks
+  const int nblocks = (int)std::max(1LL, std::min(512LL, (rows + 7) / 8));
+  MultiArgs a{};
+  double* dk = static_cast<double*>(ctx_ws(c, "multi_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
+  a.m.psum = static_cast<double*>(ctx_ws(c, "multi_psum", (size_t)nblocks * nb * nlm * sizeof(double)));
+  a.m.pcnt = static_cast<int*>(ctx_ws(c, "multi_pcnt", (size_t)nblocks * nb * sizeof(int)));
+  if (!dk || !a.m.psum || !a.m.pcnt) return ctx_fail(c, BS_ENOMEM, "bs_multipoles workspace");
+  std::vector<double> hk((size_t)3 * n_tri + n_k1 + 1);
+  for (long long i = 0; i < 3LL * n_tri; ++i) hk[i] = kperp_host[i];
+  for (int i = 0; i <= n_k1; ++i) hk[(size_t)3 * n_tri + i] = k1_edges_host[i];
+  HIPCHK(c, hipMemcpyAsync(dk, hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  a.m.B = static_cast<const double*>(Bcyl);
+  a.m.kperp = dk;
+  a.m.k1e = dk + 3 * (size_t)n_tri;
+  a.m.kpar_unit = kpar_unit;
+  a.m.nc = nc;
+  a.m.nt = n_tri;
+  a.m.nk = n_k1;
+  a.lmax = lmax;
+  a.nlm = nlm;
+  // (2l + 1) sqrt((l - m)! / (l + m)!): sqrt(4 pi (2l + 1)) times the normalisation of Y_l^m
+  for (int l = 0; l <= lmax; ++l)
+    for (int m = 0; m <= l; ++m) {
+      double r = 1.0;
+      for (int k = l - m + 1; k <= l + m; ++k) r /= (double)k;
+      a.lm_norm[l * (l + 1) / 2 + m] = (2.0 * l + 1.0) * std::sqrt(r);
+    }
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  launch_multi_bin(a, nblocks, c->stream);
+  if (c->timing) { (void)hipEventRecord(c->ev[3], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  launch_multi_fin(a, nblocks, moments, count, c->stream);
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[5], c->stream);
+    (void)hipEventRecord(c->ev[1], c->stream);
+    c->have_timing = true;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the host staging of the tables is released on return
+  if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_multipoles launch");
   return BS_OK;
 }
 

@@ -280,6 +280,19 @@ void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s);
 // mean[b] = sum over blocks of psum / count (NaN where empty), count[b] as int64, fixed block order
 void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s);
 
+// Multipole moments (Eqs. orient, bs_lm): the monopole's cells and bins, n_lm = (lmax+1)(lmax+2)/2
+// moments per bin in the order l = 0.., m = 0..l; per-block partials [nblocks][n_lm][nk * 25] and
+// counts [nblocks][nk * 25]; lm_norm[i] = (2l+1) sqrt((l-m)! / (l+m)!).
+constexpr int MULTI_MAX_LMAX = 4, MULTI_MAX_NLM = 15, MULTI_MAX_BINVALS = 6400;
+struct MultiArgs {
+  MonoArgs m;            // B, kperp, k1e, kpar_unit, nc, nt, nk (psum / pcnt: the partials below)
+  int lmax, nlm;
+  double lm_norm[MULTI_MAX_NLM];
+};
+void launch_multi_bin(const MultiArgs& a, int nblocks, hipStream_t s);
+// moments[i][b] = sum over blocks (fixed order) / count (NaN where empty); count[b] int64
+void launch_multi_fin(const MultiArgs& a, int nblocks, double* moments, int64_t* count, hipStream_t s);
+
 // ---- Eq. (vg): nearest-grid-point gridding of visibilities ----
 struct GridArgs {
   const double* uv;            // [nvis][2] baselines in wavelengths

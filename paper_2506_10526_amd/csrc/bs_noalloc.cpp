@@ -65,11 +65,12 @@ extern "C" int bs_monopole_noalloc(bs_ctx* c, int32_t nc, int32_t n_tri, const d
   unsigned char* base = static_cast<unsigned char*>(scratch_of(c->device));
   if (!base) return ctx_fail(c, BS_EHIP, "bs_monopole_noalloc: scratch address of this device unknown");
   const int nb = n_k1 * 25;
-  // a block per 2048 cells or so (as bs_monopole), at most as many as the scratch holds
-  const long long cells = (long long)n_tri * nc * nc;
+  // a wave per row, blocks of four rows, at most 2048 blocks (as bs_monopole) and at most as many as the
+  // scratch holds
+  const long long rows = (long long)n_tri * nc;
   const long long per_block = (long long)nb * (sizeof(double) + sizeof(int));
   const long long cap = (long long)(kScratchBytes - 256) / per_block;
-  const int nblocks = (int)std::max(1LL, std::min(std::min(4096LL, cap), (cells + 2047) / 2048));
+  const int nblocks = (int)std::max(1LL, std::min(std::min(2048LL, cap), (rows + 3) / 4));
   const size_t sum_bytes = ((size_t)nblocks * nb * sizeof(double) + 255) / 256 * 256;
   if (sum_bytes + (size_t)nblocks * nb * sizeof(int) > kScratchBytes)
     return ctx_fail(c, BS_EINVAL, "bs_monopole_noalloc: partial bins exceed the scratch array");
