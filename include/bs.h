@@ -268,10 +268,11 @@ int bs_multipoles(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_ho
  *    kperp must be positive and the edges non-negative and increasing, as for bs_monopole);
  *  - the call only enqueues work on the context's stream: no host staging, no synchronisation,
  *    no bs_last_timing figures;
- *  - the per-block partial bins live in a fixed 8 MiB device array of the library, one per GPU,
- *    held until the process ends (at most 8 MiB / (25 n_k1 * 12 bytes) blocks, 436 at n_k1 = 64).
+ *  - the per-block partial bins and their group sums live in a fixed 8 MiB device array of the
+ *    library, one per GPU, held until the process ends (at most (8 MiB - 1 KiB) / (25 n_k1 * 13
+ *    bytes) blocks, 403 at n_k1 = 64).
  * Calls on one GPU share that array: calls that overlap on one GPU (two streams, two contexts)
- * race.  Every block writes all of its partial bins before they are read, so nothing has to be
+ * race.  Every block and group writes all of its slots before they are read, so nothing has to be
  * cleared between calls.  It allocates nothing: no hipMalloc, hipFree or allocating library call.
  * Errors: BS_EINVAL (n_k1 outside [1, 64], nc outside [1, 65536], n_tri * nc >= 2^31, kpar_unit not
  * positive, NULL pointers), BS_EHIP (launch failure, or the scratch address of the device unknown). */

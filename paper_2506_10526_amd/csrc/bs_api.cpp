@@ -470,7 +470,9 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
   double* dk = static_cast<double*>(ctx_ws(c, "mono_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
   a.psum = static_cast<double*>(ctx_ws(c, "mono_psum", (size_t)nblocks * nb * sizeof(double)));
   a.pcnt = static_cast<int*>(ctx_ws(c, "mono_pcnt", (size_t)nblocks * nb * sizeof(int)));
-  if (!dk || !a.psum || !a.pcnt) return ctx_fail(c, BS_ENOMEM, "bs_monopole workspace");
+  a.stage_s = static_cast<double*>(ctx_ws(c, "mono_stage_s", (size_t)part_groups(nblocks) * nb * sizeof(double)));
+  a.stage_c = static_cast<long long*>(ctx_ws(c, "mono_stage_c", (size_t)part_groups(nblocks) * nb * sizeof(long long)));
+  if (!dk || !a.psum || !a.pcnt || !a.stage_s || !a.stage_c) return ctx_fail(c, BS_ENOMEM, "bs_monopole workspace");
   std::vector<double> hk((size_t)3 * n_tri + n_k1 + 1);
   for (long long i = 0; i < 3LL * n_tri; ++i) hk[i] = kperp_host[i];
   for (int i = 0; i <= n_k1; ++i) hk[(size_t)3 * n_tri + i] = k1_edges_host[i];
@@ -526,7 +528,10 @@ extern "C" int bs_multipoles(bs_ctx* c, int32_t nc, int32_t n_tri, const double*
   double* dk = static_cast<double*>(ctx_ws(c, "multi_k", (size_t)(3 * std::max(n_tri, 1) + n_k1 + 1) * sizeof(double)));
   a.m.psum = static_cast<double*>(ctx_ws(c, "multi_psum", (size_t)nblocks * nb * nlm * sizeof(double)));
   a.m.pcnt = static_cast<int*>(ctx_ws(c, "multi_pcnt", (size_t)nblocks * nb * sizeof(int)));
-  if (!dk || !a.m.psum || !a.m.pcnt) return ctx_fail(c, BS_ENOMEM, "bs_multipoles workspace");
+  a.m.stage_s = static_cast<double*>(ctx_ws(c, "multi_stage_s", (size_t)part_groups(nblocks) * nb * nlm * sizeof(double)));
+  a.m.stage_c = static_cast<long long*>(ctx_ws(c, "multi_stage_c", (size_t)part_groups(nblocks) * nb * sizeof(long long)));
+  if (!dk || !a.m.psum || !a.m.pcnt || !a.m.stage_s || !a.m.stage_c)
+    return ctx_fail(c, BS_ENOMEM, "bs_multipoles workspace");
   std::vector<double> hk((size_t)3 * n_tri + n_k1 + 1);
   for (long long i = 0; i < 3LL * n_tri; ++i) hk[i] = kperp_host[i];
   for (int i = 0; i <= n_k1; ++i) hk[(size_t)3 * n_tri + i] = k1_edges_host[i];

@@ -273,9 +273,15 @@ struct MonoArgs {
   const double* k1e;     // [nk + 1] increasing k1 edges
   double* psum;          // per-block partial sums [nblocks][nk * 25]
   int* pcnt;             // per-block partial counts [nblocks][nk * 25]
+  double* stage_s;       // group sums [part_groups(nblocks)][nk * 25] (multipoles: [..][n_lm][nk * 25])
+  long long* stage_c;    // group counts [part_groups(nblocks)][nk * 25]
   double kpar_unit;
   int nc, nt, nk;
 };
+// The block partials are added in two fixed-order stages: groups of PART_KC consecutive blocks, then
+// the groups; the result does not depend on scheduling.
+constexpr int PART_KC = 32;
+inline int part_groups(int nblocks) { return (nblocks + PART_KC - 1) / PART_KC; }
 void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s);
 // mean[b] = sum over blocks of psum / count (NaN where empty), count[b] as int64, fixed block order
 void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s);

@@ -68,18 +68,25 @@ extern "C" int bs_monopole_noalloc(bs_ctx* c, int32_t nc, int32_t n_tri, const d
   // a wave per row, blocks of four rows, at most 2048 blocks (as bs_monopole) and at most as many as the
   // scratch holds
   const long long rows = (long long)n_tri * nc;
-  const long long per_block = (long long)nb * (sizeof(double) + sizeof(int));
-  const long long cap = (long long)(kScratchBytes - 256) / per_block;
+  // per block: its partial sums and counts (12 B a bin) and 1 / PART_KC of a group's sums and counts (16 B)
+  const long long per_block = (long long)nb * 13;
+  const long long cap = (long long)(kScratchBytes - 1024) / per_block;
   const int nblocks = (int)std::max(1LL, std::min(std::min(2048LL, cap), (rows + 3) / 4));
-  const size_t sum_bytes = ((size_t)nblocks * nb * sizeof(double) + 255) / 256 * 256;
-  if (sum_bytes + (size_t)nblocks * nb * sizeof(int) > kScratchBytes)
+  const int groups = part_groups(nblocks);
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t sum_bytes = up((size_t)nblocks * nb * sizeof(double));
+  const size_t cnt_bytes = up((size_t)nblocks * nb * sizeof(int));
+  const size_t gs_bytes = up((size_t)groups * nb * sizeof(double));
+  if (sum_bytes + cnt_bytes + gs_bytes + (size_t)groups * nb * sizeof(long long) > kScratchBytes)
     return ctx_fail(c, BS_EINVAL, "bs_monopole_noalloc: partial bins exceed the scratch array");
   MonoArgs a{};
   a.B = static_cast<const double*>(Bcyl);
   a.kperp = kperp;
   a.k1e = k1_edges;
-  a.psum = reinterpret_cast<double*>(base);            // every block stores all of its slots:
-  a.pcnt = reinterpret_cast<int*>(base + sum_bytes);   // nothing needs to start at zero
+  a.psum = reinterpret_cast<double*>(base);            // every block and group stores all of its
+  a.pcnt = reinterpret_cast<int*>(base + sum_bytes);   // slots: nothing needs to start at zero
+  a.stage_s = reinterpret_cast<double*>(base + sum_bytes + cnt_bytes);
+  a.stage_c = reinterpret_cast<long long*>(base + sum_bytes + cnt_bytes + gs_bytes);
   a.kpar_unit = kpar_unit;
   a.nc = nc;
   a.nt = n_tri;

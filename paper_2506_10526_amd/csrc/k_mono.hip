@@ -7,6 +7,7 @@
 // multiply-add), so that it is the same decision as a plain IEEE evaluation of the same formula.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "bs_kernels.h"
@@ -159,33 +160,50 @@ __global__ __launch_bounds__(MONO_THREADS) void k_mono_bin(MonoArgs a) {
   }
 }
 
-// One block per bin: thread k adds the partials of blocks k, k + 256, ... in order, then a fixed
-// tree in LDS; the result does not depend on scheduling.
-__global__ __launch_bounds__(256) void k_mono_fin(MonoArgs a, int nblocks, double* __restrict__ mean,
+// Stage 1 of the reduction of the block partials: group y adds blocks y PART_KC .. y PART_KC + PART_KC - 1
+// in order, entries over the lanes (each block's row of partials is read coalesced): sums of the E
+// entries, counts of the C bins.
+__global__ __launch_bounds__(64) void k_part_stage(const double* __restrict__ psum, const int* __restrict__ pcnt,
+                                                   int nblocks, int E, int C, double* __restrict__ ss,
+                                                   long long* __restrict__ sc) {
+  const int e = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y;
+  const int k0 = y * PART_KC, k1 = min(nblocks, k0 + PART_KC);
+  if (e < E) {
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) s += psum[(long long)k * E + e];
+    ss[(long long)y * E + e] = s;
+  }
+  if (e < C) {
+    long long c = 0;
+    for (int k = k0; k < k1; ++k) c += pcnt[(long long)k * C + e];
+    sc[(long long)y * C + e] = c;
+  }
+}
+
+// Stage 2: entry e adds the G groups in order and divides by its bin's count (bin e mod C; NaN where
+// the bin is empty); the first C entries also store the counts.
+__global__ __launch_bounds__(256) void k_part_fin(const double* __restrict__ ss, const long long* __restrict__ sc,
+                                                  int G, int E, int C, double* __restrict__ out,
                                                   int64_t* __restrict__ count) {
-  __shared__ double ss[256];
-  __shared__ long long sc[256];
-  const int nb = a.nk * 25, i = blockIdx.x;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  const int bin = e % C;
   double s = 0.0;
   long long c = 0;
-  for (int k = threadIdx.x; k < nblocks; k += 256) {
-    s += a.psum[(long long)k * nb + i];
-    c += a.pcnt[(long long)k * nb + i];
+  for (int y = 0; y < G; ++y) {
+    s += ss[(long long)y * E + e];
+    c += sc[(long long)y * C + bin];
   }
-  ss[threadIdx.x] = s;
-  sc[threadIdx.x] = c;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      ss[threadIdx.x] += ss[threadIdx.x + o];
-      sc[threadIdx.x] += sc[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    mean[i] = sc[0] > 0 ? ss[0] / (double)sc[0] : __builtin_nan("");
-    count[i] = sc[0];
-  }
+  out[e] = c > 0 ? s / (double)c : __builtin_nan("");
+  if (e < C) count[e] = c;
+}
+
+void launch_part_fin(const double* psum, const int* pcnt, int nblocks, int E, int C, double* ss, long long* sc,
+                     double* out, int64_t* count, hipStream_t s) {
+  const int G = part_groups(nblocks);
+  hipLaunchKernelGGL(k_part_stage, dim3((std::max(E, C) + 63) / 64, G), dim3(64), 0, s, psum, pcnt, nblocks, E, C,
+                     ss, sc);
+  hipLaunchKernelGGL(k_part_fin, dim3((E + 255) / 256), dim3(256), 0, s, ss, sc, G, E, C, out, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,34 +418,6 @@ __global__ __launch_bounds__(MULTI_THREADS) void k_multi_bin(MultiArgs a) {
   for (int i = threadIdx.x; i < nb; i += MULTI_THREADS) a.m.pcnt[(long long)blockIdx.x * nb + i] = scnt[i];
 }
 
-// One block per (moment, bin): fixed-order sums of the block partials, as k_mono_fin.
-__global__ __launch_bounds__(256) void k_multi_fin(MultiArgs a, int nblocks, double* __restrict__ mom,
-                                                   int64_t* __restrict__ count) {
-  __shared__ double ss[256];
-  __shared__ long long sc[256];
-  const int nb = a.m.nk * 25, e = blockIdx.x, i = e / nb, bin = e - i * nb;
-  double s = 0.0;
-  long long c = 0;
-  for (int k = threadIdx.x; k < nblocks; k += 256) {
-    s += a.m.psum[((long long)k * a.nlm + i) * nb + bin];
-    c += a.m.pcnt[(long long)k * nb + bin];
-  }
-  ss[threadIdx.x] = s;
-  sc[threadIdx.x] = c;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      ss[threadIdx.x] += ss[threadIdx.x + o];
-      sc[threadIdx.x] += sc[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    mom[e] = sc[0] > 0 ? ss[0] / (double)sc[0] : __builtin_nan("");
-    if (i == 0) count[bin] = sc[0];
-  }
-}
-
 }  // namespace
 
 void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s) {
@@ -435,7 +425,7 @@ void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s) {
 }
 
 void launch_mono_fin(const MonoArgs& a, int nblocks, double* mean, int64_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_mono_fin, dim3(a.nk * 25), dim3(256), 0, s, a, nblocks, mean, count);
+  launch_part_fin(a.psum, a.pcnt, nblocks, a.nk * 25, a.nk * 25, a.stage_s, a.stage_c, mean, count, s);
 }
 
 void launch_multi_bin(const MultiArgs& a, int nblocks, hipStream_t s) {
@@ -445,5 +435,6 @@ void launch_multi_bin(const MultiArgs& a, int nblocks, hipStream_t s) {
 }
 
 void launch_multi_fin(const MultiArgs& a, int nblocks, double* moments, int64_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_fin, dim3(a.m.nk * 25 * a.nlm), dim3(256), 0, s, a, nblocks, moments, count);
+  launch_part_fin(a.m.psum, a.m.pcnt, nblocks, a.m.nk * 25 * a.nlm, a.m.nk * 25, a.m.stage_s, a.m.stage_c, moments,
+                  count, s);
 }
