@@ -40,7 +40,8 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # were taken on; None once that kernel changes until the counters are taken again.
 TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768_and_mabs_gemms.md
                  "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
-                 "mono": None,
+                 "mono": (73.0 + 7.4) * 1e6,   # profiles/mono_multi_bin_133x768x768_k1x12.md
+                 "multi": (73.1 + 19.1) * 1e6,   # the same
                  "grid": (0.0 + 126.8 + 1673.9 + 1304.4 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
 
 
@@ -299,7 +300,8 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
         "value": nt / tm_wall, "unit": "triangles/s", "ms_per_call": tm_wall * 1e3, "bin_kernel_ms": ms_m,
         "moments": "l = 0..4, m = 0..l (15)", "counts_equal_monopole": bool(np.array_equal(cnt2.cpu().numpy(), gc)),
         "roofline": {"bound": "hbm", "kernel": "k_multi_bin", "achieved": ach_m, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach_m / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": byt, "traffic": None},
+                     "frac": ach_m / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": byt,
+                     "traffic": TRAFFIC_BYTES.get("multi")},
         "whole_cube_rate_GBps": cube / (ms_m * 1e-3) / 1e9,
         "cpu_oracle": {"value": 1.0 / t_cpu_m, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "1 of 133 triangles, float64 NumPy with scipy Y_l^m"},

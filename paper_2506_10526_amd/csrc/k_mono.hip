@@ -167,15 +167,24 @@ __global__ __launch_bounds__(64) void k_part_stage(const double* __restrict__ ps
                                                    int nblocks, int E, int C, double* __restrict__ ss,
                                                    long long* __restrict__ sc) {
   const int e = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y;
-  const int k0 = y * PART_KC, k1 = min(nblocks, k0 + PART_KC);
+  const int k0 = y * PART_KC, n = min(nblocks - k0, PART_KC);
+  // all of the group's loads in flight first, then the sums in block order (a missing block adds 0)
   if (e < E) {
+    double v[PART_KC];
+#pragma unroll
+    for (int i = 0; i < PART_KC; ++i) v[i] = i < n ? psum[(long long)(k0 + i) * E + e] : 0.0;
     double s = 0.0;
-    for (int k = k0; k < k1; ++k) s += psum[(long long)k * E + e];
+#pragma unroll
+    for (int i = 0; i < PART_KC; ++i) s += v[i];
     ss[(long long)y * E + e] = s;
   }
   if (e < C) {
+    int v[PART_KC];
+#pragma unroll
+    for (int i = 0; i < PART_KC; ++i) v[i] = i < n ? pcnt[(long long)(k0 + i) * C + e] : 0;
     long long c = 0;
-    for (int k = k0; k < k1; ++k) c += pcnt[(long long)k * C + e];
+#pragma unroll
+    for (int i = 0; i < PART_KC; ++i) c += v[i];
     sc[(long long)y * C + e] = c;
   }
 }
@@ -190,9 +199,19 @@ __global__ __launch_bounds__(256) void k_part_fin(const double* __restrict__ ss,
   const int bin = e % C;
   double s = 0.0;
   long long c = 0;
-  for (int y = 0; y < G; ++y) {
-    s += ss[(long long)y * E + e];
-    c += sc[(long long)y * C + bin];
+  for (int y0 = 0; y0 < G; y0 += 16) {   // sixteen groups' loads in flight, then their sums in order
+    double v[16];
+    long long w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      v[i] = y0 + i < G ? ss[(long long)(y0 + i) * E + e] : 0.0;
+      w[i] = y0 + i < G ? sc[(long long)(y0 + i) * C + bin] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      s += v[i];
+      c += w[i];
+    }
   }
   out[e] = c > 0 ? s / (double)c : __builtin_nan("");
   if (e < C) count[e] = c;
