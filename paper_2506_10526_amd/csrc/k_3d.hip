@@ -34,11 +34,24 @@ typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t dft_pk(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x, y}, bf16x2_t));
 }
+// A constant in a VGPR.  The asm is not volatile, so the compiler may share and hoist it.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t c) {
+  uint32_t r;
+  asm("" : "=v"(r) : "0"(c));
+  return r;
+}
 // Split of two floats into packed bf16 hi = rne(x) and lo = rne(x - hi) (x in the low halves);
-// x - hi is exact (hi lies within a factor two of x and shares its grid).
+// x - hi is exact (hi lies within a factor two of x and shares its grid), and v_dot2_f32_bf16 of
+// the packed hi with (-1, 0) or (0, -1), plus x or y, forms it in one instruction (a bf16 product
+// by -1 and one addition whose exact result is representable).  The (-1, 0) operand must sit in a
+// register: as the inline constant -1.0 this instruction does not read it as bf16 -1 in the low
+// half and 0 in the high half.
 __device__ __forceinline__ void dft_split2(float x, float y, uint32_t& hp, uint32_t& lp) {
   hp = dft_pk(x, y);
-  lp = dft_pk(x - __builtin_bit_cast(float, hp << 16), y - __builtin_bit_cast(float, hp & 0xffff0000u));
+  const bf16x2_t h = __builtin_bit_cast(bf16x2_t, hp);
+  const bf16x2_t mlo = __builtin_bit_cast(bf16x2_t, in_vgpr(0x0000BF80u));
+  const bf16x2_t mhi = __builtin_bit_cast(bf16x2_t, in_vgpr(0xBF800000u));
+  lp = dft_pk(__builtin_amdgcn_fdot2_f32_bf16(h, mlo, x, false), __builtin_amdgcn_fdot2_f32_bf16(h, mhi, y, false));
 }
 
 // --------------------------------------------------------------- delay transform
