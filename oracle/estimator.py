@@ -346,6 +346,40 @@ def bs_monopole(Bcyl: np.ndarray, kperp: np.ndarray, kpar_unit: float, k1_edges:
     return mean.reshape(nk, 5, 5), counts.reshape(nk, 5, 5)
 
 
+def kpar_bins(kpar: np.ndarray, edges: np.ndarray) -> np.ndarray:
+    """Bin of each k_par on increasing edges: half-open [e_i, e_i+1), the last bin closed at its
+    top edge; -1 outside."""
+    edges = np.asarray(edges, dtype=np.float64)
+    ne = len(edges) - 1
+    i = np.searchsorted(edges, kpar, side="right") - 1
+    i = np.where(kpar == edges[-1], ne - 1, i)
+    return np.where((i >= 0) & (i < ne), i, -1)
+
+
+def bs_kpar_grid(Bcyl: np.ndarray, kpar_unit: float, edges: np.ndarray):
+    """Cylindrical 3D BS of each ring triple binned on a (k_par1, k_par2) grid (Sec. 5, Fig. 4).
+
+    Cell (a, b) of Eq. (dft)'s output has k_par1 = kpar_unit a', k_par2 = kpar_unit b' (a' = a for
+    2a < nc, else a - nc); the same edges bin both axes (kpar_bins) and a bin's value is the mean of
+    Re B over its cells.  Returns (mean [nt][ne][ne], NaN where empty, and the cell count [ne][ne],
+    which does not depend on the triangle)."""
+    Bcyl = np.asarray(Bcyl)
+    nt, nc = Bcyl.shape[0], Bcyl.shape[1]
+    ne = len(edges) - 1
+    a = np.arange(nc)
+    kp = kpar_unit * np.where(2 * a < nc, a, a - nc).astype(np.float64)
+    ib = kpar_bins(kp, edges)
+    ok = (ib[:, None] >= 0) & (ib[None, :] >= 0)
+    idx = (ib[:, None] * ne + ib[None, :])[ok]
+    counts = np.bincount(idx, minlength=ne * ne)
+    mean = np.full((nt, ne * ne), np.nan)
+    for t in range(nt):
+        sums = np.bincount(idx, weights=np.real(Bcyl[t])[ok], minlength=ne * ne)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mean[t] = np.where(counts > 0, sums / np.maximum(counts, 1), np.nan)
+    return mean.reshape(nt, ne, ne), counts.reshape(ne, ne).astype(np.int64)
+
+
 COLLINEAR_TOL = 1e-9   # mu above 1 - COLLINEAR_TOL: collinear sides, azimuth undefined
 
 
