@@ -306,8 +306,37 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
         "cpu_oracle": {"value": 1.0 / t_cpu_m, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "1 of 133 triangles, float64 NumPy with scipy Y_l^m"},
     }
+    # the (k_par1, k_par2) grid of Fig. 4: 20 x 20 linear bins over +-1.149 Mpc^-1 per ring triple
+    kedges = np.linspace(-1.149, 1.149, 21)
+    kmean = torch.empty((nt, 20, 20), dtype=torch.float64, device="cuda")
+    kcnt = torch.empty((20, 20), dtype=torch.int64, device="cuda")
+    q = lambda: bs.bs_kpar_grid(ctx, Bcyl, unit, kedges, kmean, kcnt)
+    q()
+    kb2 = []
+    for _ in range(5):
+        q()
+        kb2.append(bs.bs_last_timing(ctx)[1])
+    tk_wall = time_steps(q, 5, 0, torch)
+    ms_k = float(np.median(kb2))
+    kc = kcnt.cpu().numpy()
+    byt_k = nt * int(kc.sum()) * 16
+    t0 = time.perf_counter()
+    rk_m, rk_c = oe.bs_kpar_grid(Bh, unit, kedges)
+    t_cpu_k = (time.perf_counter() - t0) / 2
+    kpar_grid = {
+        "value": nt / tk_wall, "unit": "triangles/s", "ms_per_call": tk_wall * 1e3, "bin_kernel_ms": ms_k,
+        "grid": "20 x 20 linear k_par bins over +-1.149 Mpc^-1", "counts_equal_oracle": bool(np.array_equal(kc, rk_c)),
+        "max_rel_err_vs_oracle_2_triangles": float(np.nanmax(np.abs(kmean[:2].cpu().numpy() - rk_m) /
+                                                             np.maximum(np.abs(rk_m), 1e-300))),
+        "roofline": {"bound": "hbm", "kernel": "k_kpar_bin", "achieved": byt_k / (ms_k * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": byt_k / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": byt_k, "traffic": None},
+        "cpu_oracle": {"value": 1.0 / t_cpu_k, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                       "sample": "2 of 133 triangles, float64 NumPy"},
+    }
     return {
         "multipoles": multipoles,
+        "kpar_grid": kpar_grid,
         "value": nt / t_wall, "unit": "triangles/s", "ms_per_call": t_wall * 1e3, "bin_kernel_ms": ms_b,
         "reduce_kernel_ms": float(np.median(kr)), "cells_binned": int(gc.sum()), "bins_filled": int((gc > 0).sum()),
         "roofline": {"bound": "hbm", "kernel": "k_mono_bin", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -668,6 +697,9 @@ def main():
         mp = mo["multipoles"]
         log(f"[bench] multipoles l<=4: {mp['ms_per_call']:.3f} ms/call (binning {mp['bin_kernel_ms']:.3f} ms, "
             f"{mp['roofline']['achieved']:.0f} GB/s)")
+        kg = mo["kpar_grid"]
+        log(f"[bench] k_par grid 20x20: {kg['ms_per_call']:.3f} ms/call (binning {kg['bin_kernel_ms']:.3f} ms, "
+            f"{kg['roofline']['achieved']:.0f} GB/s)")
     grid = None
     if not args.no_grid:
         log("[bench] Eq. (vg): gridding 262,144 baselines x 768 channels")

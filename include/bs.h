@@ -260,6 +260,21 @@ int bs_multipoles(bs_ctx* ctx, int32_t nc, int32_t n_tri, const double* kperp_ho
                   const void* Bcyl, int32_t n_k1, const double* k1_edges_host, int32_t lmax, double* moments,
                   int64_t* count);
 
+/* ---- the cylindrical 3D BS on a (k_par1, k_par2) grid (Sec. 5; the binning of Fig. 4) ----
+ * mean[t][i][j] = mean of Re Bcyl[t][a][b] over the cells whose k_par1 = kpar_unit a' lies in bin i
+ * and k_par2 = kpar_unit b' in bin j (a' = a for 2a < nc, else a - nc; b' likewise); the same
+ * n_e + 1 increasing edges bin both axes, half-open [e_i, e_i+1) with the last bin closed at its
+ * top edge, and cells outside them are dropped; NaN where a bin is empty.
+ * Bcyl: device complex128 [n_tri][nc][nc] (the output of bs_mabs_dft); edges_host: host float64
+ * [n_e + 1]; mean: device float64 [n_tri][n_e][n_e]; count: device int64 [n_e][n_e], the cells of
+ * each bin (the same for every triangle).  The bin of every index is decided on the host in
+ * float64.  Synchronises the context's stream; bs_last_timing reports [0] the call, [1] the
+ * binning kernel, [2] the reduction.
+ * Errors: BS_EINVAL (nc outside [1, 65536], n_tri * nc >= 2^31, n_e outside [1, 64], edges not
+ * finite and increasing, kpar_unit not positive, NULL pointers), BS_ENOMEM, BS_EHIP. */
+int bs_kpar_grid(bs_ctx* ctx, int32_t nc, int32_t n_tri, double kpar_unit, const void* Bcyl, int32_t n_e,
+                 const double* edges_host, double* mean, int64_t* count);
+
 /* ---- allocation-free monopole ----
  * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): bs_monopole with the same inputs, outputs, binning and

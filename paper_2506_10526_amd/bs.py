@@ -27,6 +27,7 @@ EXPORTED = [
     "bs_batch_create", "bs_batch_run", "bs_batch_info", "bs_batch_result", "bs_batch_destroy",
     "bs_batch_tile", "bs_tune_set", "bs_tune_get", "bs_var_flag_proxy", "bs_var_features_flag",
     "bs_multipoles",
+    "bs_kpar_grid",
 ]
 BS_MLP_NPARAM, BS_MLP_NSTATE = 133121, 133131
 BS_K_CUBIC, BS_K_PHYSICAL = 0, 1
@@ -99,6 +100,7 @@ def lib() -> ctypes.CDLL:
     L.bs_grid_visibilities.argtypes = [vp, i32, i32, dbl, ctypes.c_int64, vp, vp, vp, i32, i32, vp, vp]
     L.bs_monopole.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
     L.bs_multipoles.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), dbl, vp, i32, ctypes.POINTER(dbl), i32, vp, vp]
+    L.bs_kpar_grid.argtypes = [vp, i32, i32, dbl, vp, i32, ctypes.POINTER(dbl), vp, vp]
     L.bs_monopole_noalloc.argtypes = [vp, i32, i32, vp, dbl, vp, i32, vp, vp, vp]
     L.bs_decorrelation.argtypes = [vp, vp, ctypes.c_int64, vp, dbl, dbl, i32, vp]
     L.bs_set_timing.argtypes = [vp, i32]
@@ -294,6 +296,20 @@ def bs_multipoles(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, lmax: int, 
     kea = (ctypes.c_double * len(ke))(*ke)
     _check(ctx, lib().bs_multipoles(ctx, nc, nt, kpa, float(kpar_unit), _ptr(Bcyl), nk, kea, int(lmax), _ptr(moments),
                                     _ptr(count)))
+
+
+def bs_kpar_grid(ctx: int, Bcyl, kpar_unit: float, edges, mean, count) -> None:
+    """The cylindrical 3D BS binned on a (k_par1, k_par2) grid: Bcyl complex128 [n_tri][nc][nc],
+    edges [n_e + 1] (host values), mean float64 [n_tri][n_e][n_e] and count int64 [n_e][n_e] on the
+    device."""
+    nt, nc = int(Bcyl.shape[0]), int(Bcyl.shape[1])
+    ed = [float(x) for x in edges]
+    ne = len(ed) - 1
+    if (tuple(Bcyl.shape) != (nt, nc, nc) or tuple(mean.shape) != (nt, ne, ne) or tuple(count.shape) != (ne, ne)
+            or not Bcyl.is_contiguous() or not mean.is_contiguous() or not count.is_contiguous()):
+        raise ValueError("bs_kpar_grid: Bcyl [n_tri][nc][nc], mean [n_tri][n_e][n_e], count [n_e][n_e]")
+    eda = (ctypes.c_double * len(ed))(*ed)
+    _check(ctx, lib().bs_kpar_grid(ctx, nc, nt, float(kpar_unit), _ptr(Bcyl), ne, eda, _ptr(mean), _ptr(count)))
 
 
 def bs_monopole_noalloc(ctx: int, Bcyl, kperp, kpar_unit: float, k1_edges, mean, count) -> None:

@@ -498,6 +498,72 @@ extern "C" int bs_monopole(bs_ctx* c, int32_t nc, int32_t n_tri, const double* k
   return BS_OK;
 }
 
+// ------------------------------------------------------------------ (k_par1, k_par2) grid (Sec. 5, Fig. 4)
+extern "C" int bs_kpar_grid(bs_ctx* c, int32_t nc, int32_t n_tri, double kpar_unit, const void* Bcyl, int32_t n_e,
+                            const double* edges_host, double* mean, int64_t* count) {
+  if (!c) return BS_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, BS_EHIP, "hipSetDevice");
+  if (nc < 1 || nc > 65536) return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: nc must be in [1, 65536]");
+  if (n_tri < 0 || (long long)n_tri * nc > (1LL << 31) - 1)
+    return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: n_tri * nc must be in [0, 2^31)");
+  if (n_e < 1 || n_e > KPAR_MAX_BINS) return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: n_e must be in [1, 64]");
+  if (!edges_host || !mean || !count || (n_tri > 0 && !Bcyl)) return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: NULL pointer");
+  for (int i = 0; i <= n_e; ++i)
+    if (!std::isfinite(edges_host[i]) || (i > 0 && !(edges_host[i] > edges_host[i - 1])))
+      return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: edges must be finite and increasing");
+  if (!(kpar_unit > 0.0) || !std::isfinite(kpar_unit)) return ctx_fail(c, BS_EINVAL, "bs_kpar_grid: kpar_unit must be > 0");
+  // bin of every index on either axis, decided here once: k = kpar_unit a' in float64, the number of
+  // edges at or below it minus one, the top edge closing the last bin
+  std::vector<int> bin1(nc);
+  std::vector<long long> h(n_e, 0);
+  for (int x = 0; x < nc; ++x) {
+    const double k = kpar_unit * (double)(2 * x < nc ? x : x - nc);
+    int i = -1;
+    for (int e = 0; e <= n_e; ++e) i += edges_host[e] <= k;
+    if (k == edges_host[n_e]) i = n_e - 1;
+    bin1[x] = (i >= 0 && i < n_e) ? i : -1;
+    if (bin1[x] >= 0) ++h[bin1[x]];
+  }
+  std::vector<int64_t> cnt((size_t)n_e * n_e);
+  for (int i = 0; i < n_e; ++i)
+    for (int j = 0; j < n_e; ++j) cnt[(size_t)i * n_e + j] = h[i] * h[j];
+  KparArgs a{};
+  a.nc = nc;
+  a.nt = n_tri;
+  a.ne = n_e;
+  // the signed indices inside the edges form one interval (k_par grows with a', the bins with k_par)
+  a.jlo = 1;
+  a.jhi = 0;
+  for (int j = -(nc / 2); j <= (nc - 1) / 2; ++j) {
+    if (bin1[j < 0 ? j + nc : j] < 0) continue;
+    if (a.jlo > a.jhi) a.jlo = j;
+    a.jhi = j;
+  }
+  const int L = std::max(0, a.jhi - a.jlo + 1);
+  // row slabs of that interval so that about a thousand blocks run
+  a.slabs = std::max(1, std::min(std::max(L, 1), (1024 + std::max(n_tri, 1) - 1) / std::max(n_tri, 1)));
+  int* dbin = static_cast<int*>(ctx_ws(c, "kpar_bin", (size_t)nc * sizeof(int)));
+  a.psum = static_cast<double*>(ctx_ws(c, "kpar_psum", (size_t)std::max(n_tri, 1) * a.slabs * n_e * n_e * sizeof(double)));
+  if (!dbin || !a.psum) return ctx_fail(c, BS_ENOMEM, "bs_kpar_grid workspace");
+  HIPCHK(c, hipMemcpyAsync(dbin, bin1.data(), bin1.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(count, cnt.data(), cnt.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  a.B = static_cast<const double*>(Bcyl);
+  a.bin1 = dbin;
+  a.count = count;
+  if (c->timing) { (void)hipEventRecord(c->ev[0], c->stream); (void)hipEventRecord(c->ev[2], c->stream); }
+  if (n_tri > 0 && L > 0) launch_kpar_bin(a, c->stream);
+  if (c->timing) { (void)hipEventRecord(c->ev[3], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
+  if (n_tri > 0) launch_kpar_fin(a, mean, c->stream);
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[5], c->stream);
+    (void)hipEventRecord(c->ev[1], c->stream);
+    c->have_timing = true;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the host staging of the tables is released on return
+  if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_kpar_grid launch");
+  return BS_OK;
+}
+
 // ------------------------------------------------------------------ multipoles (Eqs. orient, bs_lm)
 extern "C" int bs_multipoles(bs_ctx* c, int32_t nc, int32_t n_tri, const double* kperp_host, double kpar_unit,
                              const void* Bcyl, int32_t n_k1, const double* k1_edges_host, int32_t lmax,

@@ -299,6 +299,22 @@ void launch_multi_bin(const MultiArgs& a, int nblocks, hipStream_t s);
 // moments[i][b] = sum over blocks (fixed order) / count (NaN where empty); count[b] int64
 void launch_multi_fin(const MultiArgs& a, int nblocks, double* moments, int64_t* count, hipStream_t s);
 
+// The cylindrical BS on a (k_par1, k_par2) grid (Sec. 5, Fig. 4): bin1[a] is the bin of index a on
+// either axis (-1 outside the edges); a block adds the cells of one triangle's row slab into LDS
+// bins and stores them as partials [nt][slabs][ne * ne]; the final kernel adds the slabs in order
+// and divides by the counts.
+constexpr int KPAR_MAX_BINS = 64;
+struct KparArgs {
+  const double* B;        // complex double [nt][nc][nc] (real parts read)
+  const int* bin1;        // [nc]
+  double* psum;           // [nt][slabs][ne * ne]
+  const int64_t* count;   // [ne * ne]
+  int nc, nt, ne, slabs;
+  int jlo, jhi;           // the signed indices a' inside the edges: one interval (bins are monotone)
+};
+void launch_kpar_bin(const KparArgs& a, hipStream_t s);
+void launch_kpar_fin(const KparArgs& a, double* mean, hipStream_t s);
+
 // ---- Eq. (vg): nearest-grid-point gridding of visibilities ----
 struct GridArgs {
   const double* uv;            // [nvis][2] baselines in wavelengths

@@ -437,6 +437,70 @@ __global__ __launch_bounds__(MULTI_THREADS) void k_multi_bin(MultiArgs a) {
   for (int i = threadIdx.x; i < nb; i += MULTI_THREADS) a.m.pcnt[(long long)blockIdx.x * nb + i] = scnt[i];
 }
 
+// ---------------------------------------------------------------------------
+// (k_par1, k_par2) grid.  Only the signed indices jlo..jhi lie inside the edges, on both axes: a
+// wave per row j1 of the block's slab of that interval (its bin i1 is the row's), lanes over j2 in
+// it with their bins from the table; lanes of a wave in one bin are summed before one LDS atomic
+// (a bin spans many consecutive j2).
+__global__ __launch_bounds__(256) void k_kpar_bin(KparArgs a) {
+  extern __shared__ double ks[];   // [ne * ne]
+  const int nb = a.ne * a.ne, nc = a.nc;
+  const int t = blockIdx.x / a.slabs, sl = blockIdx.x - t * a.slabs;
+  for (int i = threadIdx.x; i < nb; i += 256) ks[i] = 0.0;
+  __syncthreads();
+  const int L = a.jhi - a.jlo + 1;
+  const int r0 = (int)((long long)sl * L / a.slabs), r1 = (int)((long long)(sl + 1) * L / a.slabs);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = r0 + wave; r < r1; r += 4) {
+    const int j1 = a.jlo + r, row = j1 < 0 ? j1 + nc : j1;
+    const int i1 = a.bin1[row];   // wave-uniform, inside the edges
+    const double* __restrict__ rowp = a.B + 2 * ((long long)t * nc + row) * nc;
+    for (int q0 = 0; q0 < L; q0 += 4 * 64) {
+      int bin[4], col[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * 64 + lane, j2 = a.jlo + q;
+        col[u] = j2 < 0 ? j2 + nc : j2;
+        bin[u] = q < L ? a.bin1[col[u]] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = bin[u] >= 0 ? rowp[2 * col[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        unsigned long long m = __ballot(bin[u] >= 0);
+        while (m) {
+          const int leader = __ffsll((long long)m) - 1;
+          const int lb = __shfl(bin[u], leader);
+          const bool mine = bin[u] == lb;
+          const unsigned long long mm = __ballot(mine);
+          const double x = wave_sum(mine ? v[u] : 0.0);
+          if (lane == leader) atomicAdd(&ks[i1 * a.ne + lb], x);
+          m &= ~mm;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 256) a.psum[(long long)blockIdx.x * nb + i] = ks[i];
+}
+
+// (triangle, bin) per thread: the slabs in order, divided by the bin's count (NaN where empty)
+__global__ __launch_bounds__(256) void k_kpar_fin(KparArgs a, double* __restrict__ mean) {
+  const int nb = a.ne * a.ne;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)a.nt * nb) return;
+  const int t = (int)(e / nb), k = (int)(e - (long long)t * nb);
+  const long long c = a.count[k];
+  if (c <= 0) {   // no cell in the bin (no partial was written for it when no index is inside)
+    mean[e] = __builtin_nan("");
+    return;
+  }
+  double s = 0.0;
+  for (int sl = 0; sl < a.slabs; ++sl) s += a.psum[((long long)t * a.slabs + sl) * nb + k];
+  mean[e] = s / (double)c;
+}
+
 }  // namespace
 
 void launch_mono_bin(const MonoArgs& a, int nblocks, hipStream_t s) {
@@ -456,4 +520,14 @@ void launch_multi_bin(const MultiArgs& a, int nblocks, hipStream_t s) {
 void launch_multi_fin(const MultiArgs& a, int nblocks, double* moments, int64_t* count, hipStream_t s) {
   launch_part_fin(a.m.psum, a.m.pcnt, nblocks, a.m.nk * 25 * a.nlm, a.m.nk * 25, a.m.stage_s, a.m.stage_c, moments,
                   count, s);
+}
+
+void launch_kpar_bin(const KparArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)a.ne * a.ne * sizeof(double);
+  hipLaunchKernelGGL(k_kpar_bin, dim3(a.nt * a.slabs), dim3(256), lds, s, a);
+}
+
+void launch_kpar_fin(const KparArgs& a, double* mean, hipStream_t s) {
+  const long long n = (long long)a.nt * a.ne * a.ne;
+  hipLaunchKernelGGL(k_kpar_fin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mean);
 }
