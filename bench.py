@@ -42,6 +42,7 @@ TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_25
                  "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
                  "mono": (73.0 + 7.4) * 1e6,   # profiles/mono_multi_bin_133x768x768_k1x12.md
                  "multi": (73.1 + 19.1) * 1e6,   # the same
+                 "kpar": (78.1 + 3.4) * 1e6,   # the same
                  "grid": (0.0 + 126.8 + 1673.9 + 1304.4 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
 
 
@@ -330,7 +331,7 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
                                                              np.maximum(np.abs(rk_m), 1e-300))),
         "roofline": {"bound": "hbm", "kernel": "k_kpar_bin", "achieved": byt_k / (ms_k * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": byt_k / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": byt_k, "traffic": None},
+                     "algorithmic_bytes_per_launch": byt_k, "traffic": TRAFFIC_BYTES.get("kpar")},
         "cpu_oracle": {"value": 1.0 / t_cpu_k, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                        "sample": "2 of 133 triangles, float64 NumPy"},
     }
