@@ -88,15 +88,11 @@ __device__ __forceinline__ void row_span(double hi2, double kq1, double kq2, dou
   jhi = (int)fmin(floor(hi), (double)((nc - 1) / 2));
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
 // Rows (t, a) one per wave, in a strided order over the grid; lanes over the row's span of j (only
-// there can a cell be binned, and only binned cells are read).  Lanes of a wave that fall in the same
-// bin are summed first (one LDS atomic per bin and wave); each block writes its partial bins.
+// there can a cell be binned, and only binned cells are read).  Every binned lane adds its value
+// into the block's LDS bins with its own atomic (neighbouring cells share bins, but the LDS
+// serialises those adds faster than a wave reduction per bin could combine them); each block
+// writes its partial bins.
 __global__ __launch_bounds__(MONO_THREADS) void k_mono_bin(MonoArgs a) {
   __shared__ double ssum[MONO_MAX_K1 * 25];
   __shared__ int scnt[MONO_MAX_K1 * 25];
@@ -137,18 +133,9 @@ __global__ __launch_bounds__(MONO_THREADS) void k_mono_bin(MonoArgs a) {
       }
 #pragma unroll
       for (int u = 0; u < MONO_NB; ++u) {
-        unsigned long long m = __ballot(bin[u] >= 0);
-        while (m) {
-          const int leader = __ffsll((long long)m) - 1;
-          const int lb = __shfl(bin[u], leader);
-          const bool mine = bin[u] == lb;
-          const unsigned long long mm = __ballot(mine);
-          const double x = wave_sum(mine ? v[u] : 0.0);
-          if (lane == leader) {
-            atomicAdd(&ssum[lb], x);
-            atomicAdd(&scnt[lb], (int)__popcll(mm));
-          }
-          m &= ~mm;
+        if (bin[u] >= 0) {
+          atomicAdd(&ssum[bin[u]], v[u]);
+          atomicAdd(&scnt[bin[u]], 1);
         }
       }
     }
@@ -440,8 +427,7 @@ __global__ __launch_bounds__(MULTI_THREADS) void k_multi_bin(MultiArgs a) {
 // ---------------------------------------------------------------------------
 // (k_par1, k_par2) grid.  Only the signed indices jlo..jhi lie inside the edges, on both axes: a
 // wave per row j1 of the block's slab of that interval (its bin i1 is the row's), lanes over j2 in
-// it with their bins from the table; lanes of a wave in one bin are summed before one LDS atomic
-// (a bin spans many consecutive j2).
+// it with their bins from the table, each adding its value into the block's LDS bins.
 __global__ __launch_bounds__(256) void k_kpar_bin(KparArgs a) {
   extern __shared__ double ks[];   // [ne * ne]
   const int nb = a.ne * a.ne, nc = a.nc;
@@ -467,18 +453,8 @@ __global__ __launch_bounds__(256) void k_kpar_bin(KparArgs a) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[u] = bin[u] >= 0 ? rowp[2 * col[u]] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        unsigned long long m = __ballot(bin[u] >= 0);
-        while (m) {
-          const int leader = __ffsll((long long)m) - 1;
-          const int lb = __shfl(bin[u], leader);
-          const bool mine = bin[u] == lb;
-          const unsigned long long mm = __ballot(mine);
-          const double x = wave_sum(mine ? v[u] : 0.0);
-          if (lane == leader) atomicAdd(&ks[i1 * a.ne + lb], x);
-          m &= ~mm;
-        }
-      }
+      for (int u = 0; u < 4; ++u)
+        if (bin[u] >= 0) atomicAdd(&ks[i1 * a.ne + bin[u]], v[u]);
     }
   }
   __syncthreads();
