@@ -110,3 +110,24 @@ def test_multipoles_full_size_sample(ctx):
     print(f"[multi] full nc sample nt={kperp.shape[0]}", flush=True)
     got = run(ctx, Bd, kperp, unit, edges, 4)
     check(got, Bd.cpu().numpy(), kperp, unit, edges, 4, "full")
+
+
+def test_multipoles_of_the_dft_chain(ctx):
+    """The paper's chain on a small periodic cube: the oracle's MABS collapse, then Eq. (dft) and the
+    moments on the GPU, against Eq. (dft) and the moments in the oracle (ring k_perp at the
+    geometric centres of the ring edges, in grid units)."""
+    from oracle import bins as ob
+    n, nc = 16, 12
+    redges = np.array([1.0, 2.5, 4.0, 5.5])
+    rb = ob.make_bins(ob.RING_U, n, nc, redges)
+    V = synth.make_cube(synth.small_workload(n, nc), 53)
+    B, N, _, _ = oe.estimate_mabs(rb, V)
+    Bbar, _, _ = oe.collapse_mabs(B, N)
+    cen = np.sqrt(redges[:-1] * redges[1:]) * 2 * np.pi / n
+    kperp = np.array([[cen[i] for i in tri] for tri in rb.triangles])
+    out = torch.empty((len(rb.triangles), nc, nc), dtype=torch.complex128, device="cuda")
+    bs.bs_mabs_dft(ctx, nc, cuda(Bbar), out)
+    unit = 2 * np.pi / nc
+    edges = np.geomspace(0.2, 8.0, 9)
+    got = run(ctx, out, kperp, unit, edges, 4)
+    check(got, oe.mabs_dft(Bbar), kperp, unit, edges, 4, "chain")
