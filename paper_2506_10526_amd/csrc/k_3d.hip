@@ -700,6 +700,9 @@ __device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const 
         bf16x8 ah, al;
         split8(v, ah, al);
         __builtin_amdgcn_sched_barrier(0);
+        // a raised wave priority while the MFMAs issue: the SIMD's other wave fills the gaps with
+        // its vector work instead of holding the matrix core back
+        __builtin_amdgcn_s_setprio(1);
         acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[0], acc[rt][0], 0, 0, 0);
         acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[0], acc[rt][0], 0, 0, 0);
         acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], acc[rt][0], 0, 0, 0);
@@ -709,6 +712,7 @@ __device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const 
           acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[1], acc[rt][1], 0, 0, 0);
           acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], acc[rt][1], 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
       }
     }
   }
@@ -859,12 +863,14 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
                 gh[u] = __builtin_bit_cast(bf16x8, stage[(size_t)f[u] * 64 + lane]);
                 gl[u] = __builtin_bit_cast(bf16x8, stage[(size_t)(f[u] + 1) * 64 + lane]);
               }
+              __builtin_amdgcn_s_setprio(1);
 #pragma unroll
               for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[u], wh, dk[4 * c + u], 0, 0, 0);
 #pragma unroll
               for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wl, dk[4 * c + u], 0, 0, 0);
 #pragma unroll
               for (int u = 0; u < 4; ++u) dk[4 * c + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[u], wh, dk[4 * c + u], 0, 0, 0);
+              __builtin_amdgcn_s_setprio(0);
             }
           }
         }
