@@ -16,9 +16,6 @@
 namespace {
 
 __device__ __forceinline__ int sidx(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
-// bf16 bits (round to nearest even) of x, and the float value of bf16 bits
-__device__ __forceinline__ uint32_t dft_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
-__device__ __forceinline__ float dft_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
 __device__ __forceinline__ int wrap(int q, int n) { return q < 0 ? q + n : q; }
 // Workgroups are dispatched to the eight XCDs in turn (id mod 8).  This maps the dispatch id to a
 // logical block so that every XCD runs one contiguous range of logical blocks: neighbours that
