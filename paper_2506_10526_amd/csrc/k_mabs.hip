@@ -1349,7 +1349,7 @@ __global__ __launch_bounds__(256) void k_tperp(const double* __restrict__ I, con
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) Tsum[t] = npix2 * red[0];
@@ -1479,11 +1479,11 @@ __global__ __launch_bounds__(256) void k_mabs_collapse(MabsCollapseArgs a) {
 
 // ----------------------------------------------------------------- launchers
 void launch_mabs_fields_f32(const MabsFieldArgs& a, int nbins, int nchan, size_t lds, hipStream_t s) {
-  hipFuncSetAttribute((const void*)k_mabs_fields<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_mabs_fields<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_mabs_fields<float>, dim3(a.G, nchan, nbins), dim3(256), lds, s, a);
 }
 void launch_mabs_fields_f64(const MabsFieldArgs& a, int nbins, int nchan, size_t lds, hipStream_t s) {
-  hipFuncSetAttribute((const void*)k_mabs_fields<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_mabs_fields<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_mabs_fields<double>, dim3(a.G, nchan, nbins), dim3(256), lds, s, a);
 }
 void launch_split_bf16(const float* F, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s) {
