@@ -659,11 +659,17 @@ extern "C" int bs_grid_visibilities(bs_ctx* c, int32_t n, int32_t nc, double du_
   const size_t cells = (size_t)a.nco * n * (n / 2 + 1);
   a.acc = static_cast<double*>(ctx_ws(c, "grid_acc", cells * 2 * sizeof(double)));
   a.cnt = static_cast<int*>(ctx_ws(c, "grid_cnt", cells * sizeof(int)));
-  if (!a.acc || !a.cnt) return ctx_fail(c, BS_ENOMEM, "bs_grid_visibilities workspace");
+  const size_t hot = (size_t)a.nco * (size_t)std::max(1LL, grid_blocks(n_vis)) * GRID_NHOT;
+  a.hot_v = static_cast<double*>(ctx_ws(c, "grid_hot_v", hot * 2 * sizeof(double)));
+  a.hot_c = static_cast<int*>(ctx_ws(c, "grid_hot_c", hot * sizeof(int)));
+  if (!a.acc || !a.cnt || !a.hot_v || !a.hot_c) return ctx_fail(c, BS_ENOMEM, "bs_grid_visibilities workspace");
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
   launch_grid_zero(a, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[2], c->stream);
-  if (n_vis > 0) launch_grid_scatter(a, c->stream);
+  if (n_vis > 0) {
+    launch_grid_scatter(a, c->stream);
+    launch_grid_hot(a, c->stream);
+  }
   if (c->timing) { (void)hipEventRecord(c->ev[3], c->stream); (void)hipEventRecord(c->ev[4], c->stream); }
   launch_grid_fin(a, out_precision == BS_FP64, Vg, Ng, c->stream);
   if (c->timing) {
@@ -767,16 +773,23 @@ extern "C" int bs_decorrelation(bs_ctx* c, const bs_bins* rings, int64_t n_vis, 
   double* dk = static_cast<double*>(ctx_ws(c, "dec_k", (size_t)nk * 2 * sizeof(double)));
   g.acc = static_cast<double*>(ctx_ws(c, "grid_acc", (size_t)nk * plane * 2 * sizeof(double)));
   g.cnt = static_cast<int*>(ctx_ws(c, "grid_cnt", (size_t)nk * plane * sizeof(int)));
+  const size_t ghot = (size_t)nk * (size_t)std::max(1LL, grid_blocks(n_vis)) * GRID_NHOT;
+  g.hot_v = static_cast<double*>(ctx_ws(c, "grid_hot_v", ghot * 2 * sizeof(double)));
+  g.hot_c = static_cast<int*>(ctx_ws(c, "grid_hot_c", ghot * sizeof(int)));
   void* phi = ctx_ws(c, "dec_phi", (size_t)nk * plane * 2 * sizeof(double));
   int32_t* ng32 = static_cast<int32_t*>(ctx_ws(c, "dec_ng32", (size_t)nk * plane * sizeof(int32_t)));
   uint16_t* ng16 = static_cast<uint16_t*>(ctx_ws(c, "dec_ng16", plane * sizeof(uint16_t)));
   double* dB = static_cast<double*>(ctx_ws(c, "dec_B", (size_t)std::max(ncand, 1) * sizeof(double)));
   int64_t* dN = static_cast<int64_t*>(ctx_ws(c, "dec_N", (size_t)std::max(ncand, 1) * sizeof(int64_t)));
-  if (!dk || !g.acc || !g.cnt || !phi || !ng32 || !ng16 || !dB || !dN) return ctx_fail(c, BS_ENOMEM, "bs_decorrelation workspace");
+  if (!dk || !g.acc || !g.cnt || !g.hot_v || !g.hot_c || !phi || !ng32 || !ng16 || !dB || !dN)
+    return ctx_fail(c, BS_ENOMEM, "bs_decorrelation workspace");
   g.knode = dk;
   HIPCHK(c, hipMemcpyAsync(dk, kn.data(), kn.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   launch_grid_zero(g, c->stream);
-  if (n_vis > 0) launch_grid_scatter(g, c->stream);
+  if (n_vis > 0) {
+    launch_grid_scatter(g, c->stream);
+    launch_grid_hot(g, c->stream);
+  }
   launch_grid_fin(g, true, phi, ng32, c->stream);
   if (hipGetLastError() != hipSuccess) return ctx_fail(c, BS_EHIP, "bs_decorrelation gridding");
   // the counts do not depend on the node: N_g of node 0 as the per-cell weights (uint16)

@@ -329,7 +329,16 @@ struct GridArgs {
   // exp(i k_o . delta_i), k_o = knode[2o], knode[2o+1] (radians per wavelength), delta_i = U_i - du q_i
   // its offset from its grid point
   const double* knode;
+  // the LDS cells' block partials [nco][blocks][GRID_NHOT] (sums re, im and counts), stored whole
+  // by every block and added over blocks in block order by launch_grid_hot
+  double* hot_v;
+  int* hot_c;
 };
+constexpr int GRID_HOT = 32;                                   // LDS cells: |q_u| < 32, q_v < 32
+constexpr int GRID_NHOT = (2 * GRID_HOT - 1) * GRID_HOT;
+constexpr int GRID_VPB = 16384;                                // visibilities a block
+inline long long grid_blocks(long long nvis) { return (nvis + GRID_VPB - 1) / GRID_VPB; }
+void launch_grid_hot(const GridArgs& a, hipStream_t s);
 void launch_grid_zero(const GridArgs& a, hipStream_t s);
 void launch_grid_scatter(const GridArgs& a, hipStream_t s);
 // out: complex64 (fp64 == 0) or complex128 [nco][n][n/2+1]; ng: int32 of the same shape

@@ -25,12 +25,10 @@ __global__ void k_grid_zero(GridArgs a) {
 }
 
 // Short baselines crowd into the cells around the origin, so the cells |q_u| < GRID_HOT,
-// q_v < GRID_HOT of a block's visibilities are summed in LDS and added to the grid once per block
-// and channel group; the other cells take global atomics directly.  Large blocks of visibilities
-// (GRID_VPB) give the LDS cells many samples to combine.
-constexpr int GRID_HOT = 32;
-constexpr int GRID_NHOT = (2 * GRID_HOT - 1) * GRID_HOT;
-constexpr int GRID_VPB = 16384;   // visibilities a block
+// q_v < GRID_HOT of a block's visibilities are summed in LDS, stored whole as the block's partials
+// per channel group and added over blocks in block order (k_grid_hot); the other cells take global
+// atomics directly.  Large blocks of visibilities (GRID_VPB) give the LDS cells many samples to
+// combine.
 
 __device__ __forceinline__ void cell_add(const GridArgs& a, long long o, long long cell, double re, double im, int c) {
   const long long plane = (long long)a.n * (a.n / 2 + 1);
@@ -102,14 +100,36 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_scatter(GridArgs a) {
       }
     }
     __syncthreads();
+    // the block's partials of every LDS cell, stored whole (no atomics; added over blocks later)
+    const long long base = ((long long)o * gridDim.x + blockIdx.x) * GRID_NHOT;
     for (int h = threadIdx.x; h < GRID_NHOT; h += GRID_THREADS) {
-      if (hc[h]) {
-        const int iu = h / GRID_HOT - (GRID_HOT - 1), iv = h - (h / GRID_HOT) * GRID_HOT;
-        cell_add(a, o, (long long)(iu < 0 ? iu + n : iu) * nh + iv, hre[h], him[h], hc[h]);
-      }
+      a.hot_v[2 * (base + h)] = hre[h];
+      a.hot_v[2 * (base + h) + 1] = him[h];
+      a.hot_c[base + h] = hc[h];
     }
     __syncthreads();
   }
+}
+
+// The LDS cells: their block partials added in block order, one plain store per cell and output
+// channel (no other path writes these cells: a far baseline's mirror on the line q_v = 0 is far too).
+__global__ __launch_bounds__(256) void k_grid_hot(GridArgs a, int nbx) {
+  const int h = blockIdx.x * 256 + threadIdx.x, o = blockIdx.y;
+  if (h >= GRID_NHOT) return;
+  const int iu = h / GRID_HOT - (GRID_HOT - 1), iv = h - (h / GRID_HOT) * GRID_HOT;
+  if (iu <= -a.n / 2 || iu >= a.n / 2 || iv >= a.n / 2) return;   // beyond a small grid
+  double re = 0.0, im = 0.0;
+  int c = 0;
+  for (int b = 0; b < nbx; ++b) {
+    const long long k = ((long long)o * nbx + b) * GRID_NHOT + h;
+    re += a.hot_v[2 * k];
+    im += a.hot_v[2 * k + 1];
+    c += a.hot_c[k];
+  }
+  const long long cell = (long long)o * a.n * (a.n / 2 + 1) + (long long)(iu < 0 ? iu + a.n : iu) * (a.n / 2 + 1) + iv;
+  a.acc[2 * cell] = re;
+  a.acc[2 * cell + 1] = im;
+  a.cnt[cell] = c;
 }
 
 template <typename T>
@@ -132,6 +152,11 @@ void launch_grid_scatter(const GridArgs& a, hipStream_t s) {
   const unsigned bx = (unsigned)((a.nvis + GRID_VPB - 1) / GRID_VPB);
   const unsigned by = (unsigned)(a.nco < 64 ? a.nco : 64);
   hipLaunchKernelGGL(k_grid_scatter, dim3(bx, by), dim3(GRID_THREADS), 0, s, a);
+}
+
+void launch_grid_hot(const GridArgs& a, hipStream_t s) {
+  const int nbx = (int)grid_blocks(a.nvis);
+  hipLaunchKernelGGL(k_grid_hot, dim3((GRID_NHOT + 255) / 256, a.nco), dim3(256), 0, s, a, nbx);
 }
 
 void launch_grid_fin(const GridArgs& a, bool fp64, void* out, int32_t* ng, hipStream_t s) {
