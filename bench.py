@@ -43,7 +43,7 @@ TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_25
                  "mono": (73.0 + 7.4) * 1e6,   # profiles/mono_multi_bin_133x768x768_k1x12.md
                  "multi": (73.1 + 19.1) * 1e6,   # the same
                  "kpar": (78.1 + 3.4) * 1e6,   # the same
-                 "grid": (0.0 + 126.8 + 1673.9 + 1304.4 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
+                 "grid": (0.0 + 126.8 + 1675.0 + 1213.4 + 123.9 + 8.3 + 126.8 + 76.1) * 1e6}   # profiles/grid_262144x768_to_192x256x129.md
 
 
 def log(*a):
@@ -393,7 +393,7 @@ def grid_block(bs, ctx, w, torch, nvis=262144):
     return {
         "value": nc * nvis / t_wall, "unit": "visibility samples/s", "ms_per_call": t_wall * 1e3,
         "kernels_ms": ms, "scatter_ms": ms_s, "output_ms": ms_f,
-        "roofline": {"bound": "hbm", "kernel": "k_grid_scatter + k_grid_fin (zero, scatter, output)", "achieved": ach,
+        "roofline": {"bound": "hbm", "kernel": "k_grid_zero + k_grid_scatter + k_grid_hot + k_grid_fin", "achieved": ach,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": alg, "traffic": TRAFFIC_BYTES.get("grid")},
         "counts_match_oracle_on_24_channels": counts_ok,
