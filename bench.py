@@ -350,6 +350,48 @@ def monopole_block(bs, ctx, w, torch, Bcyl):
     }
 
 
+def decorrelation_block(bs, ctx, w, torch, nvis=262144, nodes=12):
+    """Eq. (S3): the primary-beam decorrelation factor D of every candidate ring triangle of the
+    cube's 20 log rings, for 262,144 seeded baselines (log-uniform radius over 0.5-120 cells, as the
+    grid block) gridded with the cube's spacing, theta_0 = 0.6 x 24.68 deg, a 12-point Gauss rule
+    per axis (72 nodes after the z -> -z symmetry): per node one phase-mode gridding and one FP64
+    MABS of the per-cell phase averages.  The oracle's enumeration over closed grid triangles and
+    baseline triplets on a 16^2 grid with 400 baselines and 3 rings (a bounded sample) beside it."""
+    import math as _m
+    from oracle import beam as obm
+    from oracle import bins as ob
+    from paper_2506_10526_amd import synth
+    theta0 = 0.6 * _m.radians(24.68)
+    redges = w.shell_edges(20) / (2 * np.pi * w.du / w.r_mpc)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, w.n, 1, redges)
+    try:
+        uv = synth.uv_tracks(nvis, 31, 0.5 * w.du, 120 * w.du)
+        uvd = torch.from_numpy(np.ascontiguousarray(uv, dtype=np.float64)).cuda()
+        f = lambda: bs.bs_decorrelation(ctx, h, ncand, uvd, w.du, theta0, nodes)
+        D = f()
+        t_wall = time_steps(f, 3, 0, torch)
+    finally:
+        bs.bs_free_bins(h)
+    fin = D[np.isfinite(D)]
+    # the oracle's enumeration on a small case, as in the parity tests
+    small_edges = np.array([1.0, 2.0, 3.2, 5.0])
+    sb = ob.make_bins(ob.RING_U, 16, 1, small_edges)
+    suv = synth.uv_tracks(400, 5, 0.6 * w.du, 6.5 * w.du)
+    t0 = time.perf_counter()
+    Dref = obm.decorrelation_factor(sb, suv, w.du, theta0)
+    t_cpu = time.perf_counter() - t0
+    return {
+        "value": ncand / t_wall, "unit": "ring triangles/s", "ms_per_call": t_wall * 1e3, "triangles": int(ncand),
+        "baselines": int(nvis), "gauss_nodes": f"{nodes} per axis, {nodes * nodes // 2} after the z -> -z symmetry",
+        "D_finite": int(fin.size), "D_min": float(fin.min()) if fin.size else None,
+        "D_median": float(np.median(fin)) if fin.size else None,
+        "cpu_oracle": {"value": int(np.isfinite(Dref).sum()) / t_cpu, "unit": "ring triangles/s", "cores": 1,
+                       "kind": "oracle", "sample": "16^2 grid, 400 baselines, 3 rings: enumeration over closed grid "
+                                                   "triangles and baseline triplets"},
+        "workload": f"{ncand} ring triangles of the {w.n}^2 grid, {nvis} baselines",
+    }
+
+
 def grid_block(bs, ctx, w, torch, nvis=262144):
     """Eq. (vg) gridding of the cube's shape: 262,144 seeded baselines (log-uniform radius over
     0.5-120 cells, uniform angle) x 768 channels of complex64 visibilities in HBM, the periodic
@@ -707,6 +749,12 @@ def main():
         grid = grid_block(bs, ctx, w, torch)
         log(f"[bench] grid: {grid['ms_per_call']:.3f} ms/call (scatter {grid['scatter_ms']:.3f}, output "
             f"{grid['output_ms']:.3f}), {grid['roofline']['achieved']:.0f} GB/s algorithmic")
+    dec = None
+    if not args.no_grid:
+        log("[bench] Eq. (S3): decorrelation factor of the ring triangles, 262,144 baselines")
+        dec = decorrelation_block(bs, ctx, w, torch)
+        log(f"[bench] decorrelation: {dec['ms_per_call']:.1f} ms/call for {dec['triangles']} ring triangles "
+            f"(median D {dec['D_median']:.4f})")
     mc = None
     if not args.no_mc:
         log("[bench] Monte Carlo: 64 flagged realizations from one graph")
@@ -759,6 +807,7 @@ def main():
         "mabs": mabs,
         "mabs_dft": mdft,
         "grid": grid,
+        "decorrelation": dec,
         "mc": mc,
         "batch": batch,
         "surrogate": sur,
