@@ -1334,6 +1334,32 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_f64(MabsGemmArgs a) {
     }
 }
 
+// Few entries (n_nu1 nc x nc <= 64, e.g. one channel): a 64 x 64 tile would be almost all padding,
+// so a block per (entry, triangle, pixel chunk) sums F1 F2 F3 over its chunk, threads over pixels
+// (the same fused product F1 F2 * F3 per pixel), then a fixed tree; it writes the chunk's partial
+// where the tiled kernel would.
+__global__ __launch_bounds__(256) void k_mabs_dot_f64(MabsGemmArgs a) {
+  __shared__ double red[256];
+  const int nrows = a.n_nu1 * a.nc;
+  const int ent = blockIdx.x, row = ent / a.nc, col = ent - row * a.nc;
+  const int t = blockIdx.z / a.kchunks, kc = blockIdx.z - t * a.kchunks;
+  const int b1 = a.tri[3 * t], b2 = a.tri[3 * t + 1], b3 = a.tri[3 * t + 2];
+  const int i = row / a.nc, nu2 = row - i * a.nc;
+  const double* __restrict__ f1 = a.F64 + (size_t)b1 * a.bin_stride + (size_t)a.nu1[i] * a.P;
+  const double* __restrict__ f2 = a.F64 + (size_t)b2 * a.bin_stride + (size_t)nu2 * a.P;
+  const double* __restrict__ f3 = a.F64 + (size_t)b3 * a.bin_stride + (size_t)col * a.P;
+  const int kbeg = kc * a.kchunk, kend = min(a.P, kbeg + a.kchunk);
+  double s = 0.0;
+  for (int k = kbeg + (int)threadIdx.x; k < kend; k += 256) s = fma(f1[k] * f2[k], f3[k], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.S[((size_t)kc * a.ntri + t) * (size_t)nrows * a.nc + ent] = red[0];
+}
+
 // ---------------------------------------------------------------------------
 // Channel-independent triangle counts: Tsum[t] = npix^2 sum_p I_b1(p) I_b2(p) I_b3(p).
 // ---------------------------------------------------------------------------
@@ -1555,7 +1581,11 @@ void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_mabs_gemm<1>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
 }
 void launch_mabs_gemm_f64(const MabsGemmArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mabs_gemm_f64, gemm_grid(a, 64, 64), dim3(256), 0, s, a);
+  const long long ents = (long long)a.n_nu1 * a.nc * a.nc;
+  if (ents <= 64)
+    hipLaunchKernelGGL(k_mabs_dot_f64, dim3((unsigned)ents, 1, a.ntri * a.kchunks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_mabs_gemm_f64, gemm_grid(a, 64, 64), dim3(256), 0, s, a);
 }
 void launch_tperp(const double* I, const int* tri, int ntri, int P, double npix2, double* Tsum, hipStream_t s) {
   if (ntri > 0) hipLaunchKernelGGL(k_tperp, dim3(ntri), dim3(256), 0, s, I, tri, P, npix2, Tsum);

@@ -117,6 +117,32 @@ def test_cell_count_weights(ctx, prec):
     compare_B(Bg, Bref, Nref, scale, TOL[prec], f"ng prec={prec}")
 
 
+@pytest.mark.parametrize("nc,weighted", [(1, False), (1, True), (2, True), (3, False), (4, True)])
+def test_fp64_few_channels(ctx, nc, weighted):
+    """FP64 MABS with few channels (n_nu1 nc^2 <= 64 entries a triangle, the per-entry pixel sums
+    instead of the tiled GEMM), unweighted and with per-cell N_g weights (whose counts also take
+    that path); counts bit-exact."""
+    n = 32
+    rng = np.random.default_rng(11 + nc)
+    edges = np.geomspace(1.0, 11.0, 5)
+    V = synth.make_cube(synth.small_workload(n, nc), seed=13 + nc)
+    b = ob.make_bins(ob.RING_U, n, nc, edges)
+    wk, ow = {}, None
+    if weighted:
+        ng = rng.integers(0, 4, size=(nc, n, n // 2 + 1)).astype(np.uint16)
+        neg = (-np.arange(n)) % n
+        ng[:, :, 0] = np.maximum(ng[:, :, 0], ng[:, neg, 0])
+        wk, ow = {"ng": cuda(ng)}, oe.Weights(ng=ng)
+    Bref, Nref, scale = oracle_full(b, V, ow)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, n, nc, edges)
+    try:
+        Bg, Ng = run_gpu(ctx, h, V, bs.BS_FP64, ncand, nc, nc, **wk)
+    finally:
+        bs.bs_free_bins(h)
+    assert np.array_equal(Ng, Nref)
+    compare_B(Bg, Bref, Nref, scale, TOL[bs.BS_FP64], f"few channels nc={nc}")
+
+
 @pytest.mark.parametrize("collapse", [1, 2])
 def test_collapse(ctx, collapse):
     n, nc = 32, 8
