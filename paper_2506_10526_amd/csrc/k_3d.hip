@@ -634,15 +634,15 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // reads of the current one: a wave's LDS operations complete in order, so the writes cannot pass
 // those reads, and the pipeline runs through all four quarters without draining.
 template <int RTN>
-__device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const f32x4 (&dk)[DFT_MAX_FIELDS], int nbu,
+__device__ __forceinline__ void dft_contract_tile(float* __restrict__ sF, const f32x4 (&dk)[DFT_MAX_FIELDS],
                                                   const int (&oa)[RTN], const int (&ob)[RTN], const int (&oc)[2],
                                                   int ct1_tiles, f32x4 (&acc)[RTN][2]) {
   const int lane = threadIdx.x & 63, kq = lane >> 4;
   float4 ra[2][2], rb[2][2], rc[2][2][2];
   auto write_q = [&](int q) {
 #pragma unroll
-    for (int j = 0; j < DFT_MAX_FIELDS; ++j)
-      if (j < nbu) sF[(size_t)j * DFT_LDQ + lane] = dk[j][q];
+    for (int j = 0; j < DFT_MAX_FIELDS; ++j)   // rows past nbu hold zeros and are never read
+      sF[(size_t)j * DFT_LDQ + lane] = dk[j][q];
   };
   auto load_ab = [&](int ks, int rt, int buf) {
     const int vb = ks * 32 + kq * 8;
@@ -809,8 +809,13 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int since = 0;
-  for (int g = g_beg; g < g_end; ++g) {
-    for (int tt = wave; tt < ntt; tt += DFT_WAVES) {
+  // One t-tile: synthesis, then (on the wave's last tile of the group, LAST) the barrier and the
+  // copy of the next group's fragments, then the contraction.  The last tile is a separate copy
+  // of the code: while a copy into LDS may be in flight the compiler can only wait for all LDS
+  // reads at once, so the other tiles, with no copy in flight, keep their partial LDS waits.
+  auto tile = [&](const int tt, const int g, auto last_c) {
+    constexpr bool LAST = decltype(last_c)::value;
+    {
       // twiddle B-fragment of step s for this lane: modes q_c = 16 s + 4 (lane / 16) + c (c = 0..3) at
       // t = 16 tt + lane % 16, i.e. e^{2 pi i q_c t / M}; step 0 comes from the table and every later
       // step is the previous one times e^{2 pi i 16 t / M} (FP32 rotations, at most seven)
@@ -872,15 +877,22 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
           }
         }
       }
-      if (tt + DFT_WAVES >= ntt) {
+      if constexpr (LAST) {
         // the group's last synthesis on every wave: the fragments of the next group may land
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
       }
-      dft_contract_tile<RTN>(sF, dk, nbu, oa, ob, oc, a.ct1_tiles, acc);
+      dft_contract_tile<RTN>(sF, dk, oa, ob, oc, a.ct1_tiles, acc);
       since += 256;
       if (since >= a.flush_vox) { since = 0; flush(); }
     }
+  };
+  for (int g = g_beg; g < g_end; ++g) {
+    // ntt is a multiple of DFT_WAVES: every wave has ntt / DFT_WAVES tiles, the last one at
+    // ntt - DFT_WAVES + wave
+    int tt = wave;
+    for (; tt + DFT_WAVES < ntt; tt += DFT_WAVES) tile(tt, g, std::false_type{});
+    tile(tt, g, std::true_type{});
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
