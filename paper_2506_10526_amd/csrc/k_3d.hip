@@ -624,6 +624,8 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // current group and lands while that tile is contracted.  Each wave adds its FP32 sums into its
 // own FP64 slot of `partial` every a.flush_vox voxels.
 typedef __attribute__((address_space(3))) void lds_void_t;
+// word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format, no swizzle)
+constexpr int BUF_DWORD3 = 0x00020000;
 
 // Contraction of one 16 x 16 synthesis tile (256 voxels, dk[j] for field j) into acc, in four
 // quarters of 64 voxels staged in rows sF[j * DFT_LDQ + v] (v < 64): RTN pair row tiles (row
@@ -794,14 +796,19 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
   // fragment s2 of field j (hi / lo of step s2 / 2): each lane copies its 16 bytes, lanes whose
   // group holds no mode of the field (16 step + 4 (lane / 16) > H_j) copy nothing
+  // The copies are buffer loads into LDS over each field's fragment array (a buffer resource per
+  // field, byte offsets below 2^32): unlike the global form, the compiler does not count them as
+  // LDS operations, so the LDS reads issued while they are in flight keep partial waits.
   auto copy_group = [&](int g) {
     for (int j = 0; j < nbu; ++j) {
       const int S = a.Sj[j], f0 = 2 * a.kb[j], lim = a.Hj[j] - 4 * (lane >> 4);
-      const v4u_t* src = Gs + a.offGs[j] + (size_t)g * S * 128 + lane;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(Gs + a.offGs[j]), (short)0, (int)((unsigned)a.ngroups * (unsigned)S * 2048u), BUF_DWORD3);
+      const unsigned vo = ((unsigned)g * (unsigned)S * 128u + (unsigned)lane) * 16u;
       for (int s2 = (wave - f0) & (DFT_WAVES - 1); s2 < 2 * S; s2 += DFT_WAVES)
         if (16 * (s2 >> 1) <= lim)
-          __builtin_amdgcn_global_load_lds((const void*)(src + s2 * 64), (lds_void_t*)(stage + (size_t)(f0 + s2) * 64),
-                                           16, 0, 0);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(stage + (size_t)(f0 + s2) * 64), 16, vo, s2 * 1024,
+                                                   0, 0);
     }
   };
   __syncthreads();   // the zeroed stage is complete before any copy lands in it
@@ -810,11 +817,8 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   __syncthreads();
   int since = 0;
   // One t-tile: synthesis, then (on the wave's last tile of the group, LAST) the barrier and the
-  // copy of the next group's fragments, then the contraction.  The last tile is a separate copy
-  // of the code: while a copy into LDS may be in flight the compiler can only wait for all LDS
-  // reads at once, so the other tiles, with no copy in flight, keep their partial LDS waits.
-  auto tile = [&](const int tt, const int g, auto last_c) {
-    constexpr bool LAST = decltype(last_c)::value;
+  // copy of the next group's fragments, then the contraction.
+  auto tile = [&](const int tt, const int g, const bool LAST) {
     {
       // twiddle B-fragment of step s for this lane: modes q_c = 16 s + 4 (lane / 16) + c (c = 0..3) at
       // t = 16 tt + lane % 16, i.e. e^{2 pi i q_c t / M}; step 0 comes from the table and every later
@@ -877,7 +881,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
           }
         }
       }
-      if constexpr (LAST) {
+      if (LAST) {
         // the group's last synthesis on every wave: the fragments of the next group may land
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
@@ -888,11 +892,8 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
     }
   };
   for (int g = g_beg; g < g_end; ++g) {
-    // ntt is a multiple of DFT_WAVES: every wave has ntt / DFT_WAVES tiles, the last one at
-    // ntt - DFT_WAVES + wave
-    int tt = wave;
-    for (; tt + DFT_WAVES < ntt; tt += DFT_WAVES) tile(tt, g, std::false_type{});
-    tile(tt, g, std::true_type{});
+    // ntt is a multiple of DFT_WAVES: every wave has ntt / DFT_WAVES tiles
+    for (int tt = wave; tt < ntt; tt += DFT_WAVES) tile(tt, g, tt + DFT_WAVES >= ntt);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
