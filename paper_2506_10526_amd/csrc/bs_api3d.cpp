@@ -480,7 +480,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
                         (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
             dlds <= 160 * 1024 && (e.pd.NLu == 16 || e.pd.NLu == 8) && (M / 16) % DFT_WAVES == 0 &&
-            (double)(nlines / 16) * Smax * 2048.0 <= 4294967295.0 &&   // byte offsets of a field's fragments
+            buffer_fits(nlines / 16 * Smax * 2048) &&   // byte offsets of a field's fragments
             !getenv("BS_3D_FFT");
     if (e.dft) {
       const long long ngroups = nlines / 16;

@@ -147,11 +147,12 @@ void tile_decode(int code, int& kind, int& m1, int& kchunks) {
   kind = code & 15; m1 = (code >> 4) & 255; kchunks = code >> 12;
 }
 // whether (kind, m1, kchunks) can run a GEMM of this class
-bool tile_ok(int kind, int m1, int kchunks, int n, int n_nu1) {
+bool tile_ok(int kind, int m1, int kchunks, int n, int nc, int n_nu1) {
   const int P = n * n;
   if (kchunks < 1 || kchunks > 8 || (kchunks & (kchunks - 1)) || P % (32 * kchunks) || P / kchunks < 1024) return false;
   if (kind == 0) return m1 == 0;
-  return kind == 1 && n_nu1 >= 4 && (m1 == 4 || m1 == 8 || m1 == 16 || m1 == 32) && (m1 == 4 || m1 <= n_nu1);
+  return kind == 1 && n_nu1 >= 4 && (m1 == 4 || m1 == 8 || m1 == 16 || m1 == 32) && (m1 == 4 || m1 <= n_nu1) &&
+         buffer_fits((long long)nc * P * 4);
 }
 
 // Generator, ring fields and split of one cube into the arena slots (launches only).
@@ -217,16 +218,16 @@ int pick_tile(bs_ctx* c, bs_batch* bt, BCube& q, int nrings, hipStream_t s) {
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) {
     tile_decode(it->second, q.kind, q.m1, q.kchunks);
-    if (!tile_ok(q.kind, q.m1, q.kchunks, q.n, q.n_nu1))
+    if (!tile_ok(q.kind, q.m1, q.kchunks, q.n, q.nc, q.n_nu1))
       return ctx_fail(c, BS_EINVAL, "the tile set for this cube shape cannot run it");
     return BS_OK;
   }
   std::vector<std::pair<int, int>> tiles{{0, 0}};
   for (int m1 : {4, 8, 16, 32})
-    if (tile_ok(1, m1, 1, q.n, q.n_nu1)) tiles.push_back({1, m1});
+    if (tile_ok(1, m1, 1, q.n, q.nc, q.n_nu1)) tiles.push_back({1, m1});
   std::vector<int> ks;
   for (int k = 1; k <= 8; k *= 2)
-    if (tile_ok(0, 0, k, q.n, q.n_nu1)) ks.push_back(k);
+    if (tile_ok(0, 0, k, q.n, q.nc, q.n_nu1)) ks.push_back(k);
   if (ks.empty()) return ctx_fail(c, BS_EINVAL, "batch cube too small for the split-BF16 contraction");
   // temporary slots for one cube at the largest pixel-chunk count
   BCube t = q;
@@ -536,7 +537,7 @@ extern "C" int bs_tune_set(bs_ctx* c, int32_t n, int32_t nc, int32_t n_nu1, int3
   if (!c) return BS_EINVAL;
   const int kind = tile_m == 256 ? 1 : (tile_m == 128 ? 0 : -1);
   if (kind < 0 || n < 16 || n % 8 || nc < 1 || n_nu1 < 1 || n_nu1 > nc || nrings < 1 || nrings > 64 ||
-      !tile_ok(kind, kind ? m1 : 0, kchunks, n, n_nu1))
+      !tile_ok(kind, kind ? m1 : 0, kchunks, n, nc, n_nu1))
     return ctx_fail(c, BS_EINVAL, "bs_tune_set: this tile cannot run the cube shape");
   c->tuned[tile_key(n, nc, n_nu1, nrings)] = tile_code(kind, kind ? m1 : 0, kchunks);
   return BS_OK;

@@ -33,6 +33,12 @@ struct MabsFieldArgs {
 };
 
 // ------------------------------------------------------------- contractions
+// Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format, no swizzle); the
+// kernels copy into LDS with buffer loads over one array or field plane, whose byte offsets must
+// stay below 2^32.
+constexpr int BUF_DWORD3 = 0x00020000;
+inline bool buffer_fits(long long bytes) { return bytes >= 0 && bytes <= 0xFFFFFFFFll; }
+
 struct MabsGemmArgs {
   const float* F;           // FP32 fields [nb][nc][P]
   const uint16_t* Fh;       // bf16 hi parts (bit patterns), same layout

@@ -689,9 +689,11 @@ constexpr int T3_M = 256, T3_N = 64 * T3_NJ, T3_K = 32, T3_FLUSH = 8192;
 constexpr int T3_AL = T3_M * T3_K, T3_ABUF = 2 * T3_M * T3_K;   // A stage buffer: hi rows, then lo rows (32 KB)
 constexpr int T3_BL = T3_N * T3_K, T3_BBUF = 2 * T3_N * T3_K;   // B stage buffer: hi columns, then lo (24 KB)
 constexpr int T3_RAWLD = 36;                   // floats per raw row: 8 data chunks + 1 pad (bank spread)
-constexpr int T3_RAWMAX = 4 + 64;              // raw rows m1 + m2 at most
 constexpr int T3_RAW = 12 * 64 * 4;             // floats per raw buffer: 12 copy instructions of 64 chunks
-static_assert(T3_RAW >= T3_RAWMAX * T3_RAWLD, "raw buffer holds every raw row");
+// the F_b1 rows rounded up to whole copy instructions, then the F_b2 rows (m1 = 4, 8, 16, 32)
+constexpr int t3_raw_chunks(int m1) { return 64 * ((9 * m1 + 63) / 64) + 9 * (256 / m1); }
+static_assert(t3_raw_chunks(4) <= 12 * 64 && t3_raw_chunks(8) <= 12 * 64 && t3_raw_chunks(16) <= 12 * 64 &&
+              t3_raw_chunks(32) <= 12 * 64, "twelve copy instructions hold every raw row");
 static_assert(2 * (size_t)(T3_ABUF + T3_BBUF) * 2 + 2 * (size_t)T3_RAW * 4 <= 160 * 1024, "stage and raw buffers fit in LDS");
 
 
@@ -727,32 +729,50 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b, uint16
   const int nst = (kend - kbeg) / T3_K;   // >= 1; pixel ranges are multiples of T3_K
   const int klast = kend - T3_K;          // copies past the range re-read the last stage
 
-  // raw copies: chunk g of (m1 + m2) x 9 (row q = g / 9, chunk c = g % 9, the ninth a pad that
-  // re-reads chunk 0); rows q < m1 are F_b1 at nu1[i0 + q], the rest F_b2 at nu2 = n20 + q - m1,
-  // clamped to the last valid row (their products are never stored).  Every wave issues three
-  // copy instructions per stage (12 x 64 chunks, at least the 612 of the largest row set): chunks
-  // past the row set re-read the last row into the unused tail of the raw buffer, so the copies
-  // carry no branch
-  const float* rsrc[3];
+  // Copies into LDS are buffer loads (the global form counts as an LDS access for the compiler,
+  // which then drains every LDS read at each wait); a buffer resource covers one field plane
+  // (byte offsets below 2^32, checked by the launchers).  Raw copies: 12 instructions of 64
+  // 16-byte chunks a stage (three a wave), each within one plane.  Chunks from 0 hold the m1 rows
+  // of F_b1 (row q = nu1[i0 + q], chunk c at 9 q + c, the ninth a pad that re-reads chunk 0), chunks
+  // from R2 = 64 ceil(9 m1 / 64) the m2 rows of F_b2 (nu2 = n20 + q) the same way; rows past the
+  // valid ones are clamped (their products are never stored) and chunks past a row set re-read
+  // its last row into unused LDS, so the copies carry no branch.
+  const int nI1 = (9 * m1 + 63) / 64, R2 = 64 * nI1;
+  unsigned roff[3];
+  bool rsec[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int g = (wave + 4 * k) * 64 + lane;
-    const int q = min(g / 9, m1 + m2 - 1), c = g % 9 == 8 ? 0 : g % 9;
-    const float* row = q < m1 ? a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[min(i0 + q, a.n_nu1 - 1)] * a.P
-                              : a.F + (size_t)b2 * a.bin_stride + (size_t)min(n20 + q - m1, a.nc - 1) * a.P;
-    rsrc[k] = row + 4 * c;
+    const int I = wave + 4 * k;
+    rsec[k] = I >= nI1;
+    const int h = rsec[k] ? (I - nI1) * 64 + lane : I * 64 + lane;
+    const int q = min(h / 9, (rsec[k] ? m2 : m1) - 1), c = h % 9 == 8 ? 0 : h % 9;
+    const int row = rsec[k] ? min(n20 + q, a.nc - 1) : a.nu1[min(i0 + q, a.n_nu1 - 1)];
+    roff[k] = (unsigned)(((size_t)row * a.P + 4 * c) * 4);
   }
+  // the resources are built from values read from the first lane: every lane holds the same ones,
+  // and the compiler must see them as uniform (else it loops over the lanes' distinct resources)
+  const int plane4 = __builtin_amdgcn_readfirstlane((int)(unsigned)(a.bin_stride * 4));
+  const int plane2 = __builtin_amdgcn_readfirstlane((int)(unsigned)(a.bin_stride * 2));
+  auto rsrc = [](const void* p, int bytes) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v), hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0, bytes, BUF_DWORD3);
+  };
+  const __amdgpu_buffer_rsrc_t rF1 = rsrc(a.F + (size_t)b1 * a.bin_stride, plane4);
+  const __amdgpu_buffer_rsrc_t rF2 = rsrc(a.F + (size_t)b2 * a.bin_stride, plane4);
+  const __amdgpu_buffer_rsrc_t rH = rsrc(a.Fh + (size_t)b3 * a.bin_stride, plane2);
+  const __amdgpu_buffer_rsrc_t rL = rsrc(a.Fl + (size_t)b3 * a.bin_stride, plane2);
   // B copies: this wave's columns w*16NJ .. w*16NJ+16NJ-1, 16 per instruction, hi then lo
-  size_t boff[T3_NJ];
+  unsigned boff[T3_NJ];
 #pragma unroll
   for (int q = 0; q < T3_NJ; ++q) {
     const int br = wave * 16 * T3_NJ + q * 16 + (lane >> 2);
     const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
-    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 8 * swz_rows(br, lane & 3);
+    boff[q] = (unsigned)(((size_t)col * a.P + 8 * swz_rows(br, lane & 3)) * 2);
   }
   // A formation: thread r = tid owns tile row r = (i1, i2), i2 = r mod m2
   const int fr = tid, fi1 = fr >> lm2, fi2 = fr & (m2 - 1);
-  const int rawf1 = fi1 * T3_RAWLD, rawf2 = (m1 + fi2) * T3_RAWLD;
+  const int rawf1 = fi1 * T3_RAWLD, rawf2 = 4 * R2 + fi2 * T3_RAWLD;
   // fragment offsets (uint16, inside a stage buffer) per half-stage kk
   int oa[2][4], ob[2][T3_NJ];
 #pragma unroll
@@ -772,12 +792,13 @@ __device__ __forceinline__ void split3_tile(const MabsGemmArgs& a, int b, uint16
 
   auto copy_b1 = [&](int m, int k0, uint16_t* buf) {   // copy m of 2 NJ: columns q = m/2, hi or lo
     const int q = m >> 1;
-    __builtin_amdgcn_global_load_lds((const void*)((m & 1 ? a.Fl : a.Fh) + boff[q] + k0),
-                                     (lds_void*)(buf + (m & 1 ? T3_BL : 0) + (wave * 16 * T3_NJ + q * 16) * T3_K),
-                                     16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(m & 1 ? rL : rH,
+                                             (lds_void*)(buf + (m & 1 ? T3_BL : 0) + (wave * 16 * T3_NJ + q * 16) * T3_K),
+                                             16, boff[q], 2 * k0, 0, 0);
   };
   auto copy_raw1 = [&](int k, int k0, float* rb) {    // raw copy instruction wave + 4 k
-    __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + (wave + 4 * k) * 256), 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsec[k] ? rF2 : rF1, (lds_void*)(rb + (wave + 4 * k) * 256), 16, roff[k],
+                                             4 * k0, 0, 0);
   };
   // A formation piece pc of 4 (pixels 8 pc .. 8 pc + 7 of row fr) in six steps spread over the
   // MFMA slots: the raw reads (into R[pc]), four pair products split into bf16 hi / lo words (one
@@ -1526,7 +1547,7 @@ void launch_mabs_gemm_split(const MabsGemmArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_mabs_gemm<2>, gemm_grid(a, TM, TN), dim3(256), 0, s, a);
     return;
   }
-  if (a.n_nu1 >= 4 && !getenv("BS_MABS_TILE128")) {
+  if (a.n_nu1 >= 4 && buffer_fits(a.bin_stride * 4) && !getenv("BS_MABS_TILE128")) {
     // 256 x 192 tiles over (nu1 block x nu2 block) rows
     MabsGemmArgs b = a;
     if (const char* e = getenv("BS_MABS_M1")) b.tile_m1 = atoi(e);   // tuning switch: 4, 8, 16 or 32

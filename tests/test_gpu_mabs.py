@@ -279,3 +279,25 @@ def test_multi_flush(ctx, prec, monkeypatch):
         bs.bs_free_bins(h)
     assert np.array_equal(Ng, Nref)
     compare_B(Bg, Bref, Nref, scale, TOL[prec], f"multi flush prec={prec}")
+
+
+@pytest.mark.parametrize("m1", [4, 8, 16, 32])
+def test_row_blockings(ctx, m1, monkeypatch):
+    """Every row blocking of the 256 x 192 split-BF16 tiles (m1 nu1 rows x 256 / m1 nu2 rows, set by
+    BS_MABS_M1): 33 nu1 rows and nc = 40 leave partial nu1, nu2 and column blocks, and the raw-row
+    copies of the F_b1 and F_b2 rows start at different copy instructions for each m1."""
+    monkeypatch.setenv("BS_MABS_M1", str(m1))
+    n, nc = 32, 40
+    w = synth.small_workload(n, nc)
+    edges = np.geomspace(1.0, synth.default_umax(n) + 1.0, 5)
+    V = synth.make_cube(w, seed=53 + m1)
+    b = ob.make_bins(ob.RING_U, n, nc, edges)
+    nu1 = list(range(0, 40, 3)) + list(range(1, 40, 2))[:20]
+    Bref, Nref, scale = oracle_full(b, V, None, nu1=nu1)
+    h, ncand = bs.bs_make_bins(ctx, bs.BS_RING_U, n, nc, edges)
+    try:
+        Bg, Ng = run_gpu(ctx, h, V, bs.BS_SPLIT_BF16, ncand, len(nu1), nc, nu1=nu1)
+    finally:
+        bs.bs_free_bins(h)
+    assert np.array_equal(Ng, Nref)
+    compare_B(Bg, Bref, Nref, scale, TOL[bs.BS_SPLIT_BF16], f"row blocking m1={m1}")
