@@ -38,7 +38,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated by a 1 GiB copy: FETCH_SIZE x 2, WRITE_SIZE x 1), kept with the kernel version they
 # were taken on; None once that kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {"k3_dft": (269.1 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768.md
+TRAFFIC_BYTES = {"k3_dft": (269.0 + 71.3) * 1e6,   # profiles/k3_dft_split_3d_256x256x768.md
                  "mdft": (1805.9 + 629.2 + 630.1 + 1255.2) * 1e6,   # profiles/mdft_fp64_133x1535x1535_nc768.md
                  "mono": (73.0 + 7.4) * 1e6,   # profiles/mono_multi_bin_133x768x768_k1x12.md
                  "multi": (73.1 + 19.1) * 1e6,   # the same

@@ -624,8 +624,6 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // current group and lands while that tile is contracted.  Each wave adds its FP32 sums into its
 // own FP64 slot of `partial` every a.flush_vox voxels.
 typedef __attribute__((address_space(3))) void lds_void_t;
-// word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format, no swizzle)
-constexpr int BUF_DWORD3 = 0x00020000;
 
 // Contraction of one 16 x 16 synthesis tile (256 voxels, dk[j] for field j) into acc, in four
 // quarters of 64 voxels staged in rows sF[j * DFT_LDQ + v] (v < 64): RTN pair row tiles (row
