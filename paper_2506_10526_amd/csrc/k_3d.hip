@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k3_fused(Fused3Args a) {
 // Split-BF16 fused kernel: the C2R along eta as MFMA GEMMs against a twiddle-fragment table, then
 // the pair x field contraction.  A block of DFT_WAVES waves owns a range of line groups
 // (16 consecutive x_u of one x_v).  For each group it copies the group's spectrum fragments (all
-// fields, all K-steps) into LDS with 16-byte global_load_lds; each wave then takes t-tiles of 16
+// fields, all K-steps) into LDS with 16-byte buffer loads; each wave then takes t-tiles of 16
 // delay samples and computes, for every field j, F_j[16 lines][16 t] = sum over K-steps of three
 // MFMAs (lo.hi, hi.lo, hi.hi), four fields at a time so that consecutive MFMAs are independent
 // (missing K-steps read a zero fragment).  Lane l then holds F_j at lines 4 (l / 16) + i,

@@ -673,7 +673,7 @@ __global__ __launch_bounds__(256) void k_mabs_gemm_split2(MabsGemmArgs a) {
 // 32x32x16 tiles, 192 FP32 accumulators per lane), pixel stages of 32 in two A buffers (hi/lo,
 // 32 KB each), two B buffers (hi/lo, 24 KB each) and two raw buffers of the m1 + m2 FP32 rows:
 //  * the B rows of stage s+1 (pre-split F_b3) and the raw rows of stage s+2 are copied from
-//    global memory straight into LDS (16-byte global_load_lds) at the start of stage s;
+//    global memory straight into LDS (16-byte buffer loads) at the start of stage s;
 //  * the A operand of stage s+1 is formed from the raw rows of stage s+1 (products F1 F2 split
 //    into bf16 hi / lo) and stored into the other A buffer during stage s;
 //  * one set of fragments: each kind (A lo / hi, B hi / lo) is reloaded for the next half stage as
