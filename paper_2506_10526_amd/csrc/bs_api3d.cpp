@@ -480,7 +480,7 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
                         (size_t)DFT_WAVES * (DFT_MAX_FIELDS + 1) * DFT_LDQ * 4;
     e.dft = e.precision == BS_SPLIT_BF16 && P.n % 16 == 0 && fa.nbu <= DFT_MAX_FIELDS && Smax <= DFT_MAX_STEPS &&
             dlds <= 160 * 1024 && (e.pd.NLu == 16 || e.pd.NLu == 8) && (M / 16) % DFT_WAVES == 0 &&
-            buffer_fits(nlines / 16 * Smax * 2048) &&   // byte offsets of a field's fragments
+            nlines / 16 * kb.back() * 2048 < 0x80000000ll &&   // byte offsets into the fragment array
             !getenv("BS_3D_FFT");
     if (e.dft) {
       const long long ngroups = nlines / 16;
@@ -490,10 +490,18 @@ int est3_prepare(bs_ctx* c, const bs_bins* b, const bs_weights* w, int32_t preci
       e.fd.Gs = ctx_ws(c, (tag + "_Gs").c_str(), (size_t)tot * 16);
       if (!e.fd.Gs) return ctx_fail(c, BS_ENOMEM, "workspace (spectrum fragments)");
       e.fd.d_offGs = upload(c, tag + "_offGs", offGs, rc); if (rc) return rc;
+      // copy table, per stage fragment f = 2 kb[j] + s2: offset of group 0 (16-byte units), per-group
+      // stride, and H_j - 16 (s2 / 2) (the lanes whose first mode 4 (lane / 16) lies above it copy nothing)
+      std::vector<int> ctab;
+      for (int j = 0; j < fa.nbu; ++j)
+        for (int s2 = 0; s2 < 2 * Sj[j]; ++s2)
+          ctab.insert(ctab.end(), {(int)(offGs[j] + 64 * s2), (int)(128 * Sj[j]), e.pd.hj[j] - 16 * (s2 >> 1), 0});
+      e.fd.d_ctab = upload(c, tag + "_ctab", ctab, rc); if (rc) return rc;
       e.fd.gscale = fa.scale;
       Dft3Args& da = e.da;
       da = Dft3Args{};
       da.Gs = e.fd.Gs;
+      da.ctab = e.fd.d_ctab;
       for (int j = 0; j < fa.nbu; ++j) { da.offGs[j] = offGs[j]; da.Sj[j] = Sj[j]; da.Hj[j] = e.pd.hj[j]; }
       for (int j = 0; j <= fa.nbu; ++j) da.kb[j] = kb[j];
       da.nbu = fa.nbu; da.n = P.n; da.M = M; da.Smax = Smax;

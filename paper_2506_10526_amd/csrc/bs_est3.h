@@ -41,6 +41,7 @@ struct Fields3Dev {
   Work3 *d_wv = nullptr, *d_wu = nullptr, *d_we = nullptr;
   void* Gs = nullptr;                // when set, the u pass writes bf16 A-fragments here
   long long* d_offGs = nullptr;
+  int* d_ctab = nullptr;             // fragment copy table of the split-BF16 3D kernel
   double gscale = 1.0;               // folded into the fragments: 1 / (M n^2)
 };
 

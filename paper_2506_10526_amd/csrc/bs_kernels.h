@@ -227,6 +227,8 @@ constexpr int DFT_MAX_FIELDS = 24, DFT_MAX_STEPS = 8, DFT_LDQ = 68;   // row str
 // scalars, so a table read never waits for the fragment copies in flight.
 struct Dft3Args {
   const void* Gs;                           // uint4 fragments
+  const int* ctab;                          // [2 kb[nbu]][4] per stage fragment: offset of group 0
+                                            // (16-byte units), per-group stride, H_j - 16 (s2 / 2), 0
   long long offGs[DFT_MAX_FIELDS];          // per field (16-byte units)
   int Sj[DFT_MAX_FIELDS];                   // per field: K-steps ceil((H_j + 1) / 16)
   int kb[DFT_MAX_FIELDS + 1];               // prefix of Sj

@@ -794,21 +794,41 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
   // fragment s2 of field j (hi / lo of step s2 / 2): each lane copies its 16 bytes, lanes whose
   // group holds no mode of the field (16 step + 4 (lane / 16) > H_j) copy nothing
-  // The copies are buffer loads into LDS over each field's fragment array (a buffer resource per
-  // field, byte offsets below 2^32): unlike the global form, the compiler does not count them as
-  // LDS operations, so the LDS reads issued while they are in flight keep partial waits.
+  // The copies are buffer loads into LDS over the whole fragment array (byte offsets below 2^32):
+  // unlike the global form, the compiler does not count them as LDS operations, so the LDS reads
+  // issued while they are in flight keep partial waits.  Wave w copies the stage fragments
+  // f = w (mod DFT_WAVES), reading their offsets from the copy table with scalar loads (a table in
+  // LDS would make every read wait for the copies before it; per-field arguments read field by
+  // field serialise their scalar loads).
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)Gs, (short)0, (int)((unsigned)a.ngroups * (unsigned)a.kb[nbu] * 2048u), BUF_DWORD3);
+  // the table is read through the constant address space, so its uniform reads are scalar loads
+  typedef const __attribute__((address_space(4))) int cint_t;
+  cint_t* ctab = (cint_t*)(unsigned long long)a.ctab;
   auto copy_group = [&](int g) {
-    for (int j = 0; j < nbu; ++j) {
-      const int S = a.Sj[j], f0 = 2 * a.kb[j], lim = a.Hj[j] - 4 * (lane >> 4);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(Gs + a.offGs[j]), (short)0, (int)((unsigned)a.ngroups * (unsigned)S * 2048u), BUF_DWORD3);
-      const unsigned vo = ((unsigned)g * (unsigned)S * 128u + (unsigned)lane) * 16u;
-      for (int s2 = (wave - f0) & (DFT_WAVES - 1); s2 < 2 * S; s2 += DFT_WAVES)
-        if (16 * (s2 >> 1) <= lim)
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(stage + (size_t)(f0 + s2) * 64), 16, vo, s2 * 1024,
-                                                   0, 0);
+    // three fragments a round: their table reads go out together (indices clamped to the table)
+    for (int f0 = wave; f0 < nfr; f0 += 3 * DFT_WAVES) {
+      int tx[3], ty[3], tz[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int f = min(f0 + u * DFT_WAVES, nfr - 1);
+        tx[u] = ctab[4 * f]; ty[u] = ctab[4 * f + 1]; tz[u] = ctab[4 * f + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int f = f0 + u * DFT_WAVES;
+        if (f < nfr) {
+          // lanes whose modes all lie above H_j get bit 31 set in their offset (the fragment array
+          // is below 2^31 bytes), which reads past the end of the resource and returns zeros: their
+          // part of the stage stays zero, and the copy needs no branch
+          const unsigned above = (unsigned)(tz[u] - 4 * (lane >> 4)) >> 31;
+          const unsigned off = ((unsigned)(tx[u] + g * ty[u] + lane) * 16u) | (above << 31);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(stage + (size_t)f * 64), 16, off, 0, 0, 0);
+        }
+      }
     }
   };
+
   __syncthreads();   // the zeroed stage is complete before any copy lands in it
   if (g_beg < g_end) copy_group(g_beg);
   __builtin_amdgcn_s_waitcnt(0);
