@@ -792,11 +792,12 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   const int ntt = M >> 4;   // a multiple of 8: every wave takes ntt / DFT_WAVES tiles per group
   const int g_beg = blockIdx.x * a.groups_per_block;
   const int g_end = min(a.ngroups, g_beg + a.groups_per_block);
-  // fragment s2 of field j (hi / lo of step s2 / 2): each lane copies its 16 bytes, lanes whose
-  // group holds no mode of the field (16 step + 4 (lane / 16) > H_j) copy nothing
-  // The copies are buffer loads into LDS over the whole fragment array (byte offsets below 2^32):
-  // unlike the global form, the compiler does not count them as LDS operations, so the LDS reads
-  // issued while they are in flight keep partial waits.  Wave w copies the stage fragments
+  // Stage fragment f = 2 kb[j] + s2 holds the hi (s2 even) or lo part of K-step s2 / 2 of field j;
+  // each lane copies its 16 bytes, and lanes whose group holds no mode of the field
+  // (16 (s2 / 2) + 4 (lane / 16) > H_j) copy zeros.  The copies are buffer loads into LDS over the
+  // whole fragment array (byte offsets below 2^31): unlike the global form, the compiler does not
+  // count them as LDS operations, so the LDS reads issued while they are in flight keep partial
+  // waits.  Wave w copies the stage fragments
   // f = w (mod DFT_WAVES), reading their offsets from the copy table with scalar loads (a table in
   // LDS would make every read wait for the copies before it; per-field arguments read field by
   // field serialise their scalar loads).
@@ -834,10 +835,9 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int since = 0;
-  // One t-tile: synthesis, then (on the wave's last tile of the group, LAST) the barrier and the
-  // copy of the next group's fragments, then the contraction.
-  auto tile = [&](const int tt, const int g, const bool LAST) {
-    {
+  for (int g = g_beg; g < g_end; ++g) {
+    // ntt is a multiple of DFT_WAVES: every wave has ntt / DFT_WAVES tiles
+    for (int tt = wave; tt < ntt; tt += DFT_WAVES) {
       // twiddle B-fragment of step s for this lane: modes q_c = 16 s + 4 (lane / 16) + c (c = 0..3) at
       // t = 16 tt + lane % 16, i.e. e^{2 pi i q_c t / M}; step 0 comes from the table and every later
       // step is the previous one times e^{2 pi i 16 t / M} (FP32 rotations, at most seven)
@@ -899,7 +899,7 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
           }
         }
       }
-      if (LAST) {
+      if (tt + DFT_WAVES >= ntt) {
         // the group's last synthesis on every wave: the fragments of the next group may land
         __syncthreads();
         if (g + 1 < g_end) copy_group(g + 1);
@@ -908,10 +908,6 @@ __global__ __launch_bounds__(DFT_WAVES * 64) void k3_dft(Dft3Args a) {
       since += 256;
       if (since >= a.flush_vox) { since = 0; flush(); }
     }
-  };
-  for (int g = g_beg; g < g_end; ++g) {
-    // ntt is a multiple of DFT_WAVES: every wave has ntt / DFT_WAVES tiles
-    for (int tt = wave; tt < ntt; tt += DFT_WAVES) tile(tt, g, tt + DFT_WAVES >= ntt);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
