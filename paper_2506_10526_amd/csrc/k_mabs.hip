@@ -1005,7 +1005,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 constexpr int F4_M = 128, F4_N = 128, F4_RUN = 256, F4_FLUSH = 8192;
 constexpr int F4_AB = F4_M * T3_K, F4_BB = F4_N * T3_K;   // floats per A / B stage buffer (16 KB each)
 constexpr int F4_RAW = 8 * 64 * 4;                        // floats per raw buffer: 8 copy instructions
-static_assert(F4_RAW >= 36 * T3_RAWLD, "raw buffer holds the m1 + m2 <= 36 raw rows");
+// the F_b1 rows rounded up to whole copy instructions, then the F_b2 rows (m1 = 4, 8, 16, 32)
+constexpr int f4_raw_chunks(int m1) { return 64 * ((9 * m1 + 63) / 64) + 9 * (128 / m1); }
+static_assert(f4_raw_chunks(4) <= 8 * 64 && f4_raw_chunks(8) <= 8 * 64 && f4_raw_chunks(16) <= 8 * 64 &&
+              f4_raw_chunks(32) <= 8 * 64, "eight copy instructions hold every raw row");
 __device__ __forceinline__ int f4_swz(int r, int c) { return c ^ ((r ^ (r >> 3)) & 7); }
 __device__ __forceinline__ int f4_m1(const MabsGemmArgs& a) {
   return a.tile_m1 ? a.tile_m1 : (a.n_nu1 >= 16 ? 16 : (a.n_nu1 >= 8 ? 8 : 4));
@@ -1036,31 +1039,44 @@ __device__ __forceinline__ void f32t_tile(const MabsGemmArgs& a, int b, float* a
   const int nst = (kend - kbeg) / T3_K;   // >= 1; pixel ranges are multiples of T3_K
   const int klast = kend - T3_K;          // copies past the range re-read the last stage
 
-  // raw copies: chunk g of (m1 + m2) x 9 (row q = g / 9, chunk c = g % 9, the ninth a pad that
-  // re-reads chunk 0), rows q < m1 F_b1 at nu1[i0 + q], the rest F_b2 at nu2 = n20 + q - m1 (both
-  // clamped to a valid row; such products are never stored); two copy instructions a wave, chunks
-  // past the row set re-read the last row into the unused tail of the buffer
-  const float* rsrc[2];
+  // Copies into LDS are buffer loads over one field plane each, laid out as in the split kernel:
+  // raw copies are 8 instructions of 64 16-byte chunks a stage (two a wave), chunks from 0 the m1
+  // rows of F_b1 (row q = nu1[i0 + q], chunk c at 9 q + c, the ninth a pad that re-reads chunk 0),
+  // chunks from 64 ceil(9 m1 / 64) the m2 rows of F_b2 (nu2 = n20 + q), rows clamped to a valid
+  // one (their products are never stored), chunks past a row set re-reading its last row.
+  const int nI1 = (9 * m1 + 63) / 64, rbase2 = 64 * nI1;
+  unsigned roff[2];
+  bool rsec[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int g = (wave + 4 * k) * 64 + lane;
-    const int q = min(g / 9, m1 + m2 - 1), c = g % 9 == 8 ? 0 : g % 9;
-    const float* row = q < m1 ? a.F + (size_t)b1 * a.bin_stride + (size_t)a.nu1[min(i0 + q, a.n_nu1 - 1)] * a.P
-                              : a.F + (size_t)b2 * a.bin_stride + (size_t)min(n20 + q - m1, a.nc - 1) * a.P;
-    rsrc[k] = row + 4 * c;
+    const int I = wave + 4 * k;
+    rsec[k] = I >= nI1;
+    const int h = rsec[k] ? (I - nI1) * 64 + lane : I * 64 + lane;
+    const int q = min(h / 9, (rsec[k] ? m2 : m1) - 1), c = h % 9 == 8 ? 0 : h % 9;
+    const int row = rsec[k] ? min(n20 + q, a.nc - 1) : a.nu1[min(i0 + q, a.n_nu1 - 1)];
+    roff[k] = (unsigned)(((size_t)row * a.P + 4 * c) * 4);
   }
+  const int plane4 = __builtin_amdgcn_readfirstlane((int)(unsigned)(a.bin_stride * 4));
+  auto rsrc = [](const void* p, int bytes) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v), hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0, bytes, BUF_DWORD3);
+  };
+  const __amdgpu_buffer_rsrc_t rF1 = rsrc(a.F + (size_t)b1 * a.bin_stride, plane4);
+  const __amdgpu_buffer_rsrc_t rF2 = rsrc(a.F + (size_t)b2 * a.bin_stride, plane4);
+  const __amdgpu_buffer_rsrc_t rF3 = rsrc(a.F + (size_t)b3 * a.bin_stride, plane4);
   // B copies: this wave's columns w*32 .. w*32+31, eight a copy instruction (lane l: column l / 8,
   // LDS slot l % 8, which holds global chunk (l % 8) ^ swizzle)
-  size_t boff[4];
+  unsigned boff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int br = wave * 32 + q * 8 + (lane >> 3);
     const int col = min(col0 + br, a.nc - 1);   // columns past nc load a valid row, never stored
-    boff[q] = (size_t)b3 * a.bin_stride + (size_t)col * a.P + 4 * f4_swz(br, lane & 7);
+    boff[q] = (unsigned)(((size_t)col * a.P + 4 * f4_swz(br, lane & 7)) * 4);
   }
   // A formation: threads 2r, 2r + 1 own tile row r = (i1, i2), i2 = r mod m2, chunks 4h .. 4h + 3
   const int fr = tid >> 1, fh = tid & 1, fi1 = fr >> lm2, fi2 = fr & (m2 - 1);
-  const int rawf1 = fi1 * T3_RAWLD, rawf2 = (m1 + fi2) * T3_RAWLD;
+  const int rawf1 = fi1 * T3_RAWLD, rawf2 = 4 * rbase2 + fi2 * T3_RAWLD;
   // fragment offsets (floats, inside a stage buffer) per 8-pixel group q
   int oa[4][2], ob[4][2];
 #pragma unroll
@@ -1078,11 +1094,11 @@ __device__ __forceinline__ void f32t_tile(const MabsGemmArgs& a, int b, float* a
     }
   }
   auto copy_b1 = [&](int q, int k0, float* buf) {
-    __builtin_amdgcn_global_load_lds((const void*)(a.F + boff[q] + k0), (lds_void*)(buf + (wave * 32 + q * 8) * T3_K),
-                                     16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rF3, (lds_void*)(buf + (wave * 32 + q * 8) * T3_K), 16, boff[q], 4 * k0, 0, 0);
   };
   auto copy_raw1 = [&](int k, int k0, float* rb) {
-    __builtin_amdgcn_global_load_lds((const void*)(rsrc[k] + k0), (lds_void*)(rb + (wave + 4 * k) * 256), 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsec[k] ? rF2 : rF1, (lds_void*)(rb + (wave + 4 * k) * 256), 16, roff[k],
+                                             4 * k0, 0, 0);
   };
   float4 R1, R2;
   auto form_read = [&](int c, const float* rb) {   // chunk 4 fh + c of this thread's row
@@ -1590,7 +1606,7 @@ void launch_mabs_gemm_persist(int kind, const MabsPersistArgs& p, int nblocks, h
   }
 }
 void launch_mabs_gemm_f32(const MabsGemmArgs& a, hipStream_t s) {
-  if (a.n_nu1 >= 4 && !getenv("BS_MABS_F32_TILE128")) {
+  if (a.n_nu1 >= 4 && buffer_fits(a.bin_stride * 4) && !getenv("BS_MABS_F32_TILE128")) {
     MabsGemmArgs b = a;
     if (const char* e = getenv("BS_MABS_M1")) b.tile_m1 = atoi(e);   // tuning switch: 4, 8, 16 or 32
     const int m1 = b.tile_m1 ? b.tile_m1 : (b.n_nu1 >= 16 ? 16 : (b.n_nu1 >= 8 ? 8 : 4)), m2 = 128 / m1;
